@@ -1,0 +1,259 @@
+"""Pins for the oracle: checks against facts fixed by the mathematics of
+AES and by an independent AES (the openssl executable), never against the
+oracle's own formulas.
+
+Each function takes an ``oracle.ref.Oracle`` and returns a list of failure
+strings (empty when the pin holds), so that the same pins run both on the
+oracle as committed and on copies with a planted mistake, where at least one
+of them must fail.
+"""
+import numpy as np
+
+import seedgen
+from tests import openssl_cli
+
+POLY = 0x11B  # x^8 + x^4 + x^3 + x + 1
+
+
+# --- an independent GF(2^8): carry-less product, then long division -------
+def clmul(a, b):
+    p = 0
+    for i in range(8):
+        if (b >> i) & 1:
+            p ^= a << i
+    return p
+
+
+def reduce_poly(p):
+    for bit in range(14, 7, -1):
+        if (p >> bit) & 1:
+            p ^= POLY << (bit - 8)
+    return p
+
+
+def gmul(a, b):
+    return reduce_poly(clmul(a, b))
+
+
+def gpow(a, e):
+    r = 1
+    for _ in range(e):
+        r = gmul(r, a)
+    return r
+
+
+def rotl8(b, n):
+    return ((b << n) | (b >> (8 - n))) & 0xFF
+
+
+def sbox_closed_form(x):
+    """S(x) = A(x^254) + 0x63 with A as the circulant sum of rotations."""
+    inv = gpow(x, 254)  # x^254 = x^-1 for x != 0, and 0 for x = 0
+    return inv ^ rotl8(inv, 1) ^ rotl8(inv, 2) ^ rotl8(inv, 3) ^ rotl8(inv, 4) ^ 0x63
+
+
+def poly_mulmod4(a, col):
+    """(a0 + a1 x + a2 x^2 + a3 x^3) * col(x) mod x^4 + 1, coefficients in GF(2^8)."""
+    out = [0, 0, 0, 0]
+    for i in range(4):
+        for j in range(4):
+            out[(i + j) % 4] ^= gmul(a[i], col[j])
+    return out
+
+
+MIX_POLY = (0x02, 0x01, 0x01, 0x03)      # a(x) = {03}x^3 + {01}x^2 + {01}x + {02}
+INV_MIX_POLY = (0x0E, 0x09, 0x0D, 0x0B)  # a^-1(x) = {0b}x^3 + {0d}x^2 + {09}x + {0e}
+
+
+# --- pins -----------------------------------------------------------------
+def pin_gf(o):
+    fails = []
+    for a in range(256):
+        if o.xtime(a) != gmul(a, 2):
+            fails.append("xtime(%#x)" % a)
+            break
+    for a in range(256):
+        for b in range(256):
+            if o.gf_mul(a, b) != gmul(a, b):
+                fails.append("gf_mul(%#x,%#x)" % (a, b))
+                return fails
+    for j in range(1, 15):
+        if o.rcon(j) != gpow(2, j - 1):
+            fails.append("rcon[%d]" % j)
+    return fails
+
+
+def pin_sbox(o):
+    fails = []
+    s, inv = o.sbox(), o.inv_sbox()
+    expect = np.array([sbox_closed_form(x) for x in range(256)], np.uint8)
+    if not np.array_equal(s, expect):
+        fails.append("sbox != closed form at %s" % np.nonzero(s != expect)[0][:4])
+    if len(set(s.tolist())) != 256:
+        fails.append("sbox not a bijection")
+    if not np.array_equal(inv[s], np.arange(256, dtype=np.uint8)):
+        fails.append("inv_sbox . sbox != id")
+    x = np.arange(256)
+    if np.any(s == x) or np.any(s == (x ^ 0xFF)):
+        fails.append("sbox has a fixed or opposite-fixed point")
+    blk = seedgen.bytes_np(seedgen.stream_seed(7, seedgen.TAG_DATA), 16)
+    if not np.array_equal(o.step("sub_bytes", blk), s[blk]):
+        fails.append("SubBytes step != sbox per byte")
+    return fails
+
+
+def _cols(block):
+    return [list(block[4 * c:4 * c + 4]) for c in range(4)]
+
+
+def pin_mix_columns(o):
+    """MixColumns is GF(2)-linear, so agreement with the polynomial product on
+    all 128 single-bit states, plus linearity, fixes it completely."""
+    fails = []
+    for name, poly in (("mix_columns", MIX_POLY), ("inv_mix_columns", INV_MIX_POLY)):
+        for bit in range(128):
+            b = np.zeros(16, np.uint8)
+            b[bit // 8] = 1 << (bit % 8)
+            got = o.step(name, b)
+            want = np.array(sum((poly_mulmod4(poly, c) for c in _cols(b)), []), np.uint8)
+            if not np.array_equal(got, want):
+                fails.append("%s on basis bit %d" % (name, bit))
+                break
+        rnd = seedgen.bytes_np(seedgen.stream_seed(11, seedgen.TAG_DATA), 32 * 16).reshape(-1, 16)
+        for i in range(0, len(rnd), 2):
+            x, y = rnd[i], rnd[i + 1]
+            if not np.array_equal(o.step(name, x ^ y), o.step(name, x) ^ o.step(name, y)):
+                fails.append("%s not linear" % name)
+                break
+    rnd = seedgen.bytes_np(seedgen.stream_seed(12, seedgen.TAG_DATA), 16 * 16).reshape(-1, 16)
+    for x in rnd:
+        if not np.array_equal(o.step("inv_mix_columns", o.step("mix_columns", x)), x):
+            fails.append("InvMixColumns . MixColumns != id")
+            break
+    return fails
+
+
+def pin_shift_rows(o):
+    """Row r of the 4x4 state (s[r][c] = in[r + 4c]) rotates left by r."""
+    fails = []
+    b = np.arange(16, dtype=np.uint8)
+    m = b.reshape(4, 4).T          # m[r][c] = b[r + 4c]
+    want = np.stack([np.roll(m[r], -r) for r in range(4)]).T.reshape(-1)
+    if not np.array_equal(o.step("shift_rows", b), want):
+        fails.append("ShiftRows permutation")
+    if not np.array_equal(o.step("inv_shift_rows", o.step("shift_rows", b)), b):
+        fails.append("InvShiftRows . ShiftRows != id")
+    return fails
+
+
+def pin_key_expansion(o):
+    fails = []
+    for bits in (128, 192, 256):
+        k = seedgen.key(21, bits, bits)
+        w, nr = o.expand_key(k)
+        if nr != bits // 32 + 6 or w.size != 16 * (nr + 1):
+            fails.append("AES-%d: Nr/length" % bits)
+        if not np.array_equal(w[:bits // 8], k):
+            fails.append("AES-%d: first Nk words != key" % bits)
+    return fails
+
+
+def pin_openssl(o, nkeys=8, blocks_per_key=128):
+    """Whole-cipher agreement with an independent AES (the openssl
+    executable): ECB both ways for every key size, CTR with tails."""
+    if not openssl_cli.available():
+        return ["openssl executable not available"]
+    fails = []
+    for bits in (128, 192, 256):
+        for i in range(nkeys):
+            k = seedgen.key(31, 1000 * bits + i, bits)
+            w, nr = o.expand_key(k)
+            pt = seedgen.data_np(31, 1000 * bits + i, 16 * blocks_per_key)
+            ct = o.ecb_encrypt(w, nr, pt)
+            if not np.array_equal(ct, openssl_cli.enc("ecb", k, pt)):
+                fails.append("ECB-%d encrypt, key %d" % (bits, i))
+                break
+            if not np.array_equal(o.ecb_decrypt(w, nr, pt), openssl_cli.enc("ecb", k, pt, decrypt=True)):
+                fails.append("ECB-%d decrypt, key %d" % (bits, i))
+                break
+            n = 16 * blocks_per_key - 16 + 1 + (i * 5) % 15   # partial final block
+            ctr0 = seedgen.nonce(31, 1000 * bits + i)
+            got = o.ctr(w, nr, ctr0, pt[:n])
+            if not np.array_equal(got, openssl_cli.enc("ctr", k, pt[:n], iv=ctr0)):
+                fails.append("CTR-%d, key %d, %d bytes" % (bits, i, n))
+                break
+    return fails
+
+
+def pin_ctr_structure(o):
+    """CTR keystream block j is Cipher(T_j) with T_j = nonce || BE32(c0+j),
+    the counter wraps modulo 2^32 without carrying into the nonce, a partial
+    tail is a prefix of the full-block result, and CTR is an involution."""
+    fails = []
+    k = seedgen.key(41, 0, 128)
+    w, nr = o.expand_key(k)
+    ctr0 = seedgen.nonce(41, 0)
+    ctr0[12:16] = [0xFF, 0xFF, 0xFF, 0xF0]        # counter wraps after 16 blocks
+    zeros = np.zeros(16 * 40, np.uint8)
+    ks = o.ctr(w, nr, ctr0, zeros)
+    for j in range(40):
+        c = (0xFFFFFFF0 + j) & 0xFFFFFFFF
+        t = np.concatenate([ctr0[:12], np.array([c >> 24, (c >> 16) & 255, (c >> 8) & 255, c & 255], np.uint8)])
+        if not np.array_equal(o.ctr_block(ctr0, j), t):
+            fails.append("counter block %d layout" % j)
+            break
+        if not np.array_equal(ks[16 * j:16 * j + 16], o.encrypt_block(w, nr, t)):
+            fails.append("keystream block %d != Cipher(T_j)" % j)
+            break
+    pt = seedgen.data_np(41, 1, 16 * 40)
+    full = o.ctr(w, nr, ctr0, pt)
+    for n in (0, 1, 15, 17, 33, 16 * 40 - 1):
+        if not np.array_equal(o.ctr(w, nr, ctr0, pt[:n]), full[:n]):
+            fails.append("CTR tail of %d bytes is not a prefix" % n)
+    if not np.array_equal(o.ctr(w, nr, ctr0, full), pt):
+        fails.append("CTR is not an involution")
+    return fails
+
+
+def pin_roundtrip(o):
+    fails = []
+    for bits in (128, 192, 256):
+        k = seedgen.key(51, bits, bits)
+        w, nr = o.expand_key(k)
+        pt = seedgen.data_np(51, bits, 16 * 64)
+        if not np.array_equal(o.ecb_decrypt(w, nr, o.ecb_encrypt(w, nr, pt)), pt):
+            fails.append("AES-%d: decrypt(encrypt(x)) != x" % bits)
+    return fails
+
+
+def pin_chunking(o):
+    """The paper's premise: chunks processed apart and concatenated equal the
+    whole (checked through the pthreads runner)."""
+    fails = []
+    k = seedgen.key(61, 0, 256)
+    w, nr = o.expand_key(k)
+    ctr0 = seedgen.nonce(61, 0)
+    pt = seedgen.data_np(61, 0, 16 * 1000 + 9)
+    whole_ecb = o.ecb_encrypt(w, nr, pt[:16 * 1000])
+    whole_ctr = o.ctr(w, nr, ctr0, pt)
+    for t in (1, 2, 3, 7, 32, 64):
+        got, _ = o.par_run(0, w, nr, pt[:16 * 1000], t)
+        if not np.array_equal(got, whole_ecb):
+            fails.append("ECB with %d chunks" % t)
+        got, _ = o.par_run(2, w, nr, pt, t, ctr0=ctr0)
+        if not np.array_equal(got, whole_ctr):
+            fails.append("CTR with %d chunks" % t)
+    return fails
+
+
+ALL_PINS = (pin_gf, pin_sbox, pin_mix_columns, pin_shift_rows, pin_key_expansion,
+            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking)
+
+
+def run_all(o, fast=False):
+    out = {}
+    for pin in ALL_PINS:
+        if fast and pin is pin_gf:
+            continue
+        out[pin.__name__] = pin(o)
+    return out
