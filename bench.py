@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: AES-128 ECB encryption of a 1 GiB device-resident
+buffer on one MI355X, through the C ABI (aes_expand_key + aes_encrypt).
+
+One step = Key Expansion on the host + one ECB encryption of the whole 1 GiB
+buffer (67,108,864 16-byte blocks) of seeded uniform random bytes.  The
+input is produced on the device before the timed region.  W untimed steps,
+then exactly K timed steps between two synchronisations; every launch is
+also bracketed by HIP events on the stream it runs on, which gives the
+kernel's own duration for the roofline figures.
+
+Prints one JSON line.  Besides the headline it carries:
+  roofline      the binding ceiling (LDS-lookup issue rate or HBM), with the
+                algorithmic work of one launch divided by its measured time;
+  roofline_hbm, roofline_issue   both ceilings;
+  cpu_baseline  the oracle (plain byte-oriented C AES) on the host's cores,
+                run with the paper's pthreads chunking on a bounded sample;
+  secondary     the other operations of the path on the same buffer (CTR,
+                ECB decryption, AES-256) and the copy kernel's bandwidth.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import seedgen  # noqa: E402
+
+GiB = 1 << 30
+HBM_PEAK_GBS = 8000.0             # MI355X HBM3E, published
+CUS, CLOCK_GHZ = 256, 2.4          # MI355X compute units, peak engine clock
+LDS_LANES_PER_CLK = 32             # LDS: 32 banks x 4 B per clock per CU
+LDS_PEAK_TLOOKUPS = CUS * CLOCK_GHZ * 1e9 * LDS_LANES_PER_CLK / 1e12   # 19.66
+KERNEL_SRC = os.path.join(ROOT, "paper_1403_7295_amd", "csrc", "aes_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cipher_kernel_aes128_ecb_enc_1GiB.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nbytes", type=int, default=GiB)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--cpu-sample-mib", type=int, default=32)
+    return ap.parse_args()
+
+
+def lookups_per_block(nr, ctr=False):
+    # 16 table lookups per round; CTR saves 12 of round 1's (shared nonce columns)
+    return 16 * nr - (12 if ctr else 0)
+
+
+def timed_launches(torch, stream, launch, steps, warmup):
+    """Runs `launch` warmup + steps times; returns (wall seconds of the timed
+    steps, mean kernel seconds from HIP events on `stream`)."""
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        launch()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = sum(a.elapsed_time(b) for a, b in evs) / steps / 1e3
+    return wall, kern
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for name in ("aes_kernels.hip", "abi.cpp", "internal.h"):
+        with open(os.path.join(os.path.dirname(KERNEL_SRC), name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed hardware-counter runs, if they were
+    taken on the kernel source as it is now; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sample_bytes):
+    """The oracle, untuned, on all host cores with the paper's pthreads split."""
+    import numpy as np  # noqa: F401
+    from oracle import ref
+    o = ref.default()
+    key = seedgen.key(2, 0, 128)
+    rk, nr = o.expand_key(key)
+    x = seedgen.data_np(2, 0, sample_bytes)
+    threads = len(os.sched_getaffinity(0))
+    secs = []
+    for _ in range(3):
+        _, s = o.par_run(0, rk, nr, x, threads)
+        secs.append(s)
+    secs.sort()
+    s = secs[len(secs) // 2]
+    return {"value": round(sample_bytes / s / 1e9, 5), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "AES-128 ECB encrypt of the first %d MiB of the same seeded input, "
+                      "%d pthreads (contiguous whole-block chunks), median of 3 runs, %.2f s each"
+                      % (sample_bytes >> 20, threads, s)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each GPU would encrypt its own shard with no exchange); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1403_7295_amd import aesgpu as A
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.nbytes
+    key128 = seedgen.key(2, 0, 128)
+    ctr0 = seedgen.nonce(2, 0)
+    x = seedgen.data_torch(2, 0, n, dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        rk, nr = A.aes_expand_key(key128)
+        A.aes_encrypt(x, y, n, rk, nr, A.AES_MODE_ECB, stream=stream)
+
+    wall, kern = timed_launches(torch, stream, step, args.steps, args.warmup)
+    launch = A.aes_get_launch(n, A.AES_MODE_ECB, False)
+    value = n * args.steps / wall / 1e9
+    nblocks = n // 16
+
+    hbm_achieved = 2 * n / kern / 1e9
+    lk = lookups_per_block(10) * nblocks
+    issue_achieved = lk / kern / 1e12
+    traffic = measured_traffic()
+    roof_hbm = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+    roof_issue = {"bound": "alu", "achieved": round(issue_achieved, 3),
+                  "peak": round(LDS_PEAK_TLOOKUPS, 3), "unit": "Tlookup/s",
+                  "frac": round(issue_achieved / LDS_PEAK_TLOOKUPS, 4), "traffic": traffic,
+                  "note": "LDS table lookups (16 per round per block); peak = 256 CUs x 2.4 GHz "
+                          "x 32 lanes per clock"}
+    binding = roof_issue if roof_issue["frac"] >= roof_hbm["frac"] else roof_hbm
+
+    out = {
+        "metric": "AES-128 ECB encrypt GB/s @1 GiB",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (SplitMix64-seeded uniform random bytes, generated on the device)",
+        "config": {"workload": "AES-128 ECB encrypt of a 1 GiB device-resident buffer, one seeded key",
+                   "nbytes": n, "blocks": nblocks, "key_bits": 128, "mode": "ECB",
+                   "launch": launch},
+        "gbps": round(8 * value, 1),
+        "kernel_ms": round(kern * 1e3, 4),
+        "roofline": binding,
+        "roofline_hbm": roof_hbm,
+        "roofline_issue": roof_issue,
+    }
+
+    if not args.no_secondary:
+        sec = {}
+        key256 = seedgen.key(2, 0, 256)
+        for name, key, mode, dec in (("aes128_ctr_enc", key128, A.AES_MODE_CTR, False),
+                                     ("aes128_ecb_dec", key128, A.AES_MODE_ECB, True),
+                                     ("aes128_ctr_dec", key128, A.AES_MODE_CTR, True),
+                                     ("aes256_ecb_enc", key256, A.AES_MODE_ECB, False),
+                                     ("aes256_ctr_enc", key256, A.AES_MODE_CTR, False)):
+            rk, nr = A.aes_expand_key(key)
+            fn = A.aes_decrypt if dec else A.aes_encrypt
+            w, k = timed_launches(torch, stream,
+                                  lambda: fn(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream), 10, 2)
+            sec[name] = {"GB/s": round(n / k / 1e9, 1),
+                         "Tlookup/s": round(lookups_per_block(nr, mode == A.AES_MODE_CTR) * nblocks / k / 1e12, 3)}
+        w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, 2)
+        sec["copy_kernel"] = {"GB/s (read+write)": round(2 * n / k / 1e9, 1)}
+        out["secondary"] = sec
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_mib << 20)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

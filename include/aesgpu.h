@@ -1,0 +1,147 @@
+/*
+ * aesgpu: AES (FIPS-197) encryption and decryption of large device-resident
+ * buffers on AMD Instinct MI355X (gfx950), in ECB and CTR mode.
+ *
+ * The operation is the one the paper (Barnes, Fernando, Mettananda, Ragel,
+ * "Improving the Throughput of the AES Algorithm with Multicore Processors")
+ * parallelises: a buffer is cut into independent 16-byte blocks and each
+ * block goes through Key Expansion's round keys, an initial AddRoundKey,
+ * Nr - 1 rounds of SubBytes, ShiftRows, MixColumns and AddRoundKey, and a
+ * final round without MixColumns (Section III-A).  The arithmetic of each
+ * step is that of FIPS-197 (sections 5.1 - 5.3); CTR is NIST SP 800-38A
+ * section 6.5 with a 32-bit big-endian counter in bytes 12..15 of the
+ * counter block.
+ *
+ * Conventions for every call:
+ *   - Every function returns an aes_status; none throws or aborts.  On a
+ *     non-zero status, aes_last_error() holds a message (per thread).
+ *   - Buffers are owned by the caller.  The library never allocates device
+ *     memory on these paths; it only launches kernels.
+ *   - Calls are asynchronous with respect to the host: they return once the
+ *     kernel is enqueued on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Host-side arguments (round keys, counter block) are read
+ *     before the call returns and may be freed at once.  Device buffers must
+ *     stay valid until the stream has run the kernel.
+ *   - Arguments are validated on the host before anything is enqueued; a
+ *     launch failure reports AES_E_DEVICE.
+ *   - Only gfx950 devices are supported; any other device gives
+ *     AES_E_DEVICE.
+ */
+#ifndef AESGPU_H
+#define AESGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AES_OK = 0,
+    AES_E_NULL = 1,     /* a required pointer is NULL                        */
+    AES_E_KEYBITS = 2,  /* key size not 128, 192 or 256                      */
+    AES_E_NR = 3,       /* Nr not 10, 12 or 14                               */
+    AES_E_LENGTH = 4,   /* ECB length not a multiple of 16, or size too big  */
+    AES_E_ALIGN = 5,    /* device pointer not 16-byte aligned                */
+    AES_E_OVERLAP = 6,  /* in and out overlap without being identical        */
+    AES_E_MODE = 7,     /* unknown mode, or a CTR call without a counter     */
+    AES_E_DEVICE = 8,   /* no usable gfx950 device, or a HIP call failed     */
+    AES_E_ARG = 9       /* any other invalid argument                        */
+} aes_status;
+
+typedef enum { AES_MODE_ECB = 0, AES_MODE_CTR = 1 } aes_mode;
+
+/*
+ * Key Expansion (FIPS-197 section 5.2; the paper's first step,
+ * Section III-A).
+ *   key        host pointer to keybits/8 bytes.
+ *   keybits    128, 192 or 256.
+ *   roundkeys  host pointer to at least 16*(Nr+1) bytes (176, 208 or 240),
+ *              receives the words w[0] .. w[4Nr+3] of the key schedule, each
+ *              word as its 4 bytes in the standard's order, so that bytes
+ *              16r .. 16r+15 are exactly the bytes XORed into state bytes
+ *              0..15 by AddRoundKey in round r.
+ *   Nr         host pointer; receives 10, 12 or 14.
+ * Runs on the host only.  Errors: AES_E_NULL, AES_E_KEYBITS.
+ */
+int aes_expand_key(const uint8_t *key, int keybits, uint8_t *roundkeys, int *Nr);
+
+/*
+ * Encrypt nbytes of `in` into `out` (the cipher of FIPS-197 section 5.1,
+ * applied to every 16-byte block; the paper's Section III-A step list).
+ *   in, out    device pointers, 16-byte aligned.  in == out (in place) is
+ *              allowed; any other overlap is AES_E_OVERLAP.
+ *   nbytes     ECB: a multiple of 16.  CTR: any length; a final partial
+ *              block uses the leading bytes of its keystream block.
+ *              nbytes == 0 returns AES_OK and enqueues nothing.
+ *   roundkeys  host pointer to the 16*(Nr+1)-byte ENCRYPTION schedule as
+ *              written by aes_expand_key.
+ *   Nr         10, 12 or 14.
+ *   mode       AES_MODE_ECB or AES_MODE_CTR.
+ *   ctr0       CTR: host pointer to the 16-byte initial counter block; block
+ *              j uses bytes 0..11 of ctr0 followed by (c0 + j) mod 2^32 in
+ *              big-endian order, c0 being the big-endian value of
+ *              ctr0[12..15] (no carry into bytes 0..11).  ECB: ignored, may
+ *              be NULL.
+ *   stream     hipStream_t to enqueue on, or NULL.
+ */
+int aes_encrypt(const void *in, void *out, size_t nbytes,
+                const uint8_t *roundkeys, int Nr, int mode,
+                const uint8_t *ctr0, void *stream);
+
+/*
+ * Decrypt: the inverse cipher (FIPS-197 section 5.3), computed in the
+ * equivalent-inverse-cipher form of section 5.3.5.  Same arguments as
+ * aes_encrypt; `roundkeys` is still the ENCRYPTION schedule (the decryption
+ * schedule is derived inside).  For CTR, decryption is the same operation
+ * as encryption.
+ */
+int aes_decrypt(const void *in, void *out, size_t nbytes,
+                const uint8_t *roundkeys, int Nr, int mode,
+                const uint8_t *ctr0, void *stream);
+
+/* Message for the last non-zero status returned on this thread. */
+const char *aes_last_error(void);
+
+/*
+ * Launch configuration of the buffer kernels (ECB and CTR).  Exposed so
+ * that a tuner can sweep it and tests can show the result does not depend
+ * on it.  All fields 0 mean "the library's choice".
+ *   layout            0 = four round tables, 32 copies each, in LDS;
+ *                     1 = two round tables, 64 copies each (the other two
+ *                         are rotations of them).
+ *   blocks_per_thread 1, 2 or 4 16-byte blocks in flight per thread.
+ *   wg_size           256, 512 or 1024 threads per workgroup.
+ *   grid              workgroups launched (each loops over the buffer); 0 =
+ *                     one per compute unit.
+ */
+typedef struct {
+    int layout;
+    int blocks_per_thread;
+    int wg_size;
+    int grid;
+} aes_launch;
+
+/* Set (cfg != NULL) or clear (cfg == NULL) the launch configuration used by
+ * later aes_encrypt / aes_decrypt calls from every thread.  Errors:
+ * AES_E_ARG for values outside the lists above. */
+int aes_set_launch(const aes_launch *cfg);
+
+/* The configuration the next call with these arguments would use. */
+int aes_get_launch(size_t nbytes, int mode, int decrypt, aes_launch *cfg);
+
+/*
+ * Measurement helper (not part of the cipher): copies nbytes (a multiple of
+ * 16) from `in` to `out` with the same 16-byte-per-lane loads and stores and
+ * the same persistent grid as the cipher kernels.  Its run time is the HBM
+ * ceiling the cipher is compared with, and its hardware counters calibrate
+ * byte counts.  Errors as for aes_encrypt.
+ */
+int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AESGPU_H */

@@ -1,0 +1,257 @@
+// The C ABI of libaesgpu (declared in include/aesgpu.h): argument checks,
+// per-device set-up, the launch-configuration choice, and the host halves of
+// the key schedule.  No call here allocates device memory.
+#include "aesgpu.h"
+
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+using namespace aesgpu;
+
+thread_local std::string g_error;
+
+int fail(int status, const std::string &msg) {
+    g_error = msg;
+    return status;
+}
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceState {
+    int status = AES_E_DEVICE;
+    std::string error;
+    int cus = 0;
+};
+
+std::once_flag g_once[kMaxDevices];
+DeviceState g_dev[kMaxDevices];
+
+void init_device(int dev) {
+    DeviceState &d = g_dev[dev];
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) {
+        d.error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+        return;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        d.error = std::string("aesgpu is built for gfx950 only; device is ") + prop.gcnArchName;
+        return;
+    }
+    if (prop.sharedMemPerBlock < 160 * 1024) {
+        d.error = "device offers less than 160 KiB of LDS per workgroup";
+        return;
+    }
+    e = upload_tables(host_tables());
+    if (e != hipSuccess) {
+        d.error = std::string("table upload: ") + hipGetErrorString(e);
+        return;
+    }
+    d.cus = prop.multiProcessorCount;
+    d.status = AES_OK;
+}
+
+// Checks the current device and initialises it once; returns its state.
+const DeviceState *current_device(int *status) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *status = fail(AES_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    std::call_once(g_once[dev], init_device, dev);
+    if (g_dev[dev].status != AES_OK) {
+        *status = fail(AES_E_DEVICE, g_dev[dev].error);
+        return nullptr;
+    }
+    *status = AES_OK;
+    return &g_dev[dev];
+}
+
+// Launch-configuration override (0 = library choice).
+std::mutex g_launch_mu;
+aes_launch g_launch = {0, 0, 0, 0};
+bool g_launch_set = false;
+
+bool valid_launch(const aes_launch &c) {
+    return (c.layout == 0 || c.layout == 1) &&
+           (c.blocks_per_thread == 0 || c.blocks_per_thread == 1 || c.blocks_per_thread == 2 ||
+            c.blocks_per_thread == 4) &&
+           (c.wg_size == 0 || c.wg_size == 256 || c.wg_size == 512 || c.wg_size == 1024) &&
+           c.grid >= 0;
+}
+
+LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes) {
+    aes_launch o;
+    bool set;
+    {
+        std::lock_guard<std::mutex> lk(g_launch_mu);
+        o = g_launch;
+        set = g_launch_set;
+    }
+    LaunchCfg c;
+    c.layout = set ? o.layout : LAYOUT_T4X32;
+    c.bpt = set && o.blocks_per_thread ? o.blocks_per_thread : 2;
+    c.wg = set && o.wg_size ? o.wg_size : 1024;
+    // The round tables fill most of the LDS, so one workgroup runs per
+    // compute unit; a persistent grid of one workgroup per CU sweeps the
+    // buffer.  Small buffers get only as many workgroups as they can keep busy.
+    uint64_t grid = set && o.grid ? uint64_t(o.grid) : uint64_t(d.cus);
+    const uint64_t nblk = (nbytes + 15) / 16;
+    const uint64_t per_wg = uint64_t(c.wg) * c.bpt;
+    const uint64_t useful = (nblk + per_wg - 1) / per_wg;
+    if (!(set && o.grid) && useful < grid)
+        grid = useful;
+    if (grid < 1)
+        grid = 1;
+    if (grid > 0x7fffffff)
+        grid = 0x7fffffff;
+    c.grid = int(grid);
+    return c;
+}
+
+int check_buffers(const void *in, void *out, size_t nbytes) {
+    if (!in || !out)
+        return fail(AES_E_NULL, "in and out must not be NULL");
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u)
+        return fail(AES_E_ALIGN, "in and out must be 16-byte aligned");
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+    if (a != b && a < b + nbytes && b < a + nbytes)
+        return fail(AES_E_OVERLAP, "in and out overlap without being the same buffer");
+    return AES_OK;
+}
+
+int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *roundkeys, int Nr,
+          int mode, const uint8_t *ctr0, void *stream) {
+    if (Nr != 10 && Nr != 12 && Nr != 14)
+        return fail(AES_E_NR, "Nr must be 10, 12 or 14");
+    if (mode != AES_MODE_ECB && mode != AES_MODE_CTR)
+        return fail(AES_E_MODE, "mode must be AES_MODE_ECB or AES_MODE_CTR");
+    if (!roundkeys)
+        return fail(AES_E_NULL, "roundkeys must not be NULL");
+    if (mode == AES_MODE_CTR && !ctr0)
+        return fail(AES_E_NULL, "CTR needs the initial counter block ctr0");
+    if (mode == AES_MODE_ECB && nbytes % 16 != 0)
+        return fail(AES_E_LENGTH, "ECB length must be a multiple of 16 bytes");
+    if (nbytes == 0)
+        return AES_OK;
+    int st = check_buffers(in, out, nbytes);
+    if (st != AES_OK)
+        return st;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+
+    CipherArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.in = static_cast<const uint8_t *>(in);
+    a.out = static_cast<uint8_t *>(out);
+    a.nbytes = nbytes;
+    uint32_t w[60];
+    const int nwords = 4 * (Nr + 1);
+    for (int i = 0; i < nwords; i++)
+        std::memcpy(&w[i], roundkeys + 4 * i, 4);  // bytes in order = little-endian column word
+    const bool dec_cipher = decrypt && mode == AES_MODE_ECB;
+    if (dec_cipher)
+        decryption_schedule(w, Nr, a.rk);
+    else
+        std::memcpy(a.rk, w, 4 * nwords);
+    if (mode == AES_MODE_CTR) {
+        std::memcpy(a.ctr, ctr0, 12);
+        a.ctr[3] = (uint32_t(ctr0[12]) << 24) | (uint32_t(ctr0[13]) << 16) |
+                   (uint32_t(ctr0[14]) << 8) | uint32_t(ctr0[15]);
+    }
+    const LaunchCfg cfg = choose_launch(*d, nbytes);
+    hipError_t e = launch_cipher(Nr, mode == AES_MODE_CTR ? MODE_CTR : MODE_ECB,
+                                 dec_cipher ? DIR_DEC : DIR_ENC, cfg, a,
+                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aes_expand_key(const uint8_t *key, int keybits, uint8_t *roundkeys, int *Nr) {
+    if (!key || !roundkeys || !Nr)
+        return fail(AES_E_NULL, "key, roundkeys and Nr must not be NULL");
+    uint32_t w[60];
+    const int nr = expand_key_host(key, keybits, w);
+    if (nr < 0)
+        return fail(AES_E_KEYBITS, "keybits must be 128, 192 or 256");
+    for (int i = 0; i < 4 * (nr + 1); i++)
+        std::memcpy(roundkeys + 4 * i, &w[i], 4);
+    *Nr = nr;
+    return AES_OK;
+}
+
+int aes_encrypt(const void *in, void *out, size_t nbytes, const uint8_t *roundkeys, int Nr, int mode,
+                const uint8_t *ctr0, void *stream) {
+    return crypt(0, in, out, nbytes, roundkeys, Nr, mode, ctr0, stream);
+}
+
+int aes_decrypt(const void *in, void *out, size_t nbytes, const uint8_t *roundkeys, int Nr, int mode,
+                const uint8_t *ctr0, void *stream) {
+    return crypt(1, in, out, nbytes, roundkeys, Nr, mode, ctr0, stream);
+}
+
+const char *aes_last_error(void) { return g_error.c_str(); }
+
+int aes_set_launch(const aes_launch *cfg) {
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    if (!cfg) {
+        g_launch_set = false;
+        g_launch = aes_launch{0, 0, 0, 0};
+        return AES_OK;
+    }
+    if (!valid_launch(*cfg))
+        return fail(AES_E_ARG, "launch configuration out of range");
+    g_launch = *cfg;
+    g_launch_set = true;
+    return AES_OK;
+}
+
+int aes_get_launch(size_t nbytes, int mode, int decrypt, aes_launch *cfg) {
+    (void)mode;
+    (void)decrypt;
+    if (!cfg)
+        return fail(AES_E_NULL, "cfg must not be NULL");
+    int st;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+    const LaunchCfg c = choose_launch(*d, nbytes);
+    cfg->layout = c.layout;
+    cfg->blocks_per_thread = c.bpt;
+    cfg->wg_size = c.wg;
+    cfg->grid = c.grid;
+    return AES_OK;
+}
+
+int aes_copy(const void *in, void *out, size_t nbytes, void *stream) {
+    if (nbytes % 16 != 0)
+        return fail(AES_E_LENGTH, "copy length must be a multiple of 16 bytes");
+    if (nbytes == 0)
+        return AES_OK;
+    int st = check_buffers(in, out, nbytes);
+    if (st != AES_OK)
+        return st;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+    hipError_t e = launch_copy(in, out, nbytes, d->cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
+}  // extern "C"

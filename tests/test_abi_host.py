@@ -1,0 +1,97 @@
+"""The C-ABI library on the CPU: it loads, exports every function its header
+declares, and its host-side logic (key schedule, argument checks) behaves as
+documented.  Nothing here launches a kernel: every call below returns before
+the library touches a device."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import seedgen
+from oracle import ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "aesgpu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aes_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1403_7295_amd import aesgpu
+    return aesgpu
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("aes_expand_key", "aes_encrypt", "aes_decrypt", "aes_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(A):
+    out = subprocess.run(["nm", "-D", "--defined-only", A.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (aes_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(declared_functions()) == set(A._SIGNATURES)
+
+
+@pytest.mark.parametrize("bits", [128, 192, 256])
+def test_key_schedule_matches_oracle(A, bits):
+    o = ref.default()
+    for i in range(16):
+        k = seedgen.key(77, 100 * bits + i, bits)
+        rk, nr = A.aes_expand_key(k)
+        rk_ref, nr_ref = o.expand_key(k)
+        assert nr == nr_ref == bits // 32 + 6
+        assert np.array_equal(rk, rk_ref)
+
+
+def test_bad_key_size(A):
+    with pytest.raises(A.AESError) as e:
+        A.aes_expand_key(np.zeros(20, np.uint8), 160)
+    assert e.value.code == A.AES_E_KEYBITS
+
+
+# Fake, never-dereferenced device addresses: every case below is rejected (or
+# is a no-op) before the library looks at a device.
+IN, OUT = 0x10000, 0x20000
+
+
+@pytest.mark.parametrize("fn", ["aes_encrypt", "aes_decrypt"])
+def test_argument_checks(A, fn):
+    rk, nr = A.aes_expand_key(np.zeros(16, np.uint8))
+    call = getattr(A, fn)
+
+    def code(*args, **kw):
+        with pytest.raises(A.AESError) as e:
+            call(*args, stream=0, **kw)
+        return e.value.code
+
+    assert code(IN, OUT, 32, rk, 11, "ecb") == A.AES_E_NR
+    assert code(IN, OUT, 32, rk, nr, 5) == A.AES_E_MODE
+    assert code(IN, OUT, 17, rk, nr, "ecb") == A.AES_E_LENGTH
+    assert code(IN, OUT, 32, rk, nr, "ctr") == A.AES_E_NULL          # no counter block
+    assert code(None, OUT, 32, rk, nr, "ecb") == A.AES_E_NULL
+    assert code(IN + 4, OUT, 32, rk, nr, "ecb") == A.AES_E_ALIGN
+    assert code(IN, IN + 16, 64, rk, nr, "ecb") == A.AES_E_OVERLAP
+    assert code(IN + 16, IN, 64, rk, nr, "ctr", ctr0=bytes(16)) == A.AES_E_OVERLAP
+    # empty buffers are a no-op, whatever the pointers
+    call(None, None, 0, rk, nr, "ecb", stream=0)
+    call(None, None, 0, rk, nr, "ctr", ctr0=bytes(16), stream=0)
+
+
+def test_launch_config_validation(A):
+    for bad in ({"layout": 2}, {"blocks_per_thread": 3}, {"wg_size": 100}, {"grid": -1}):
+        with pytest.raises(A.AESError) as e:
+            A.aes_set_launch(bad)
+        assert e.value.code == A.AES_E_ARG
+    A.aes_set_launch({"layout": 1, "blocks_per_thread": 4, "wg_size": 512, "grid": 3})
+    A.aes_set_launch(None)

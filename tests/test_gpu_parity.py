@@ -1,0 +1,253 @@
+"""Parity of the HIP path with the oracle, bit for bit, through the C ABI.
+
+AES output is fully determined by (key, mode, counter block, input), so the
+tolerance everywhere is zero: every compared byte must be equal.  Small and
+ragged sizes are compared in full; the 1 GiB and 4 GiB buffers, in the launch
+configuration the benchmark uses, are compared on sampled blocks that the
+oracle computes one by one, plus decrypt(encrypt(x)) == x over the whole
+buffer.
+"""
+import numpy as np
+import pytest
+
+import seedgen
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1403_7295_amd import aesgpu
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return aesgpu
+
+
+@pytest.fixture(scope="module")
+def O():
+    return ref.default()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def gpu_op(A, op, x_np, rk, nr, ctr0=None, inplace=False, stream=None):
+    """Run one operation ('enc' / 'dec' in ECB, or 'ctr') on the GPU; returns numpy."""
+    x = to_dev(x_np)
+    out = x if inplace else torch.empty_like(x)
+    n = x_np.size
+    if op == "enc":
+        A.aes_encrypt(x, out, n, rk, nr, "ecb", stream=stream)
+    elif op == "dec":
+        A.aes_decrypt(x, out, n, rk, nr, "ecb", stream=stream)
+    elif op == "ctr":
+        A.aes_encrypt(x, out, n, rk, nr, "ctr", ctr0=ctr0, stream=stream)
+    elif op == "ctr_dec":
+        A.aes_decrypt(x, out, n, rk, nr, "ctr", ctr0=ctr0, stream=stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_op(O, op, x_np, rk, nr, ctr0=None):
+    if op == "enc":
+        return O.ecb_encrypt(rk, nr, x_np)
+    if op == "dec":
+        return O.ecb_decrypt(rk, nr, x_np)
+    return O.ctr(rk, nr, ctr0, x_np)
+
+
+def assert_same(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.nonzero(got != want)[0]
+        raise AssertionError("%s: %d bytes differ, first at %d (block %d)"
+                             % (what, bad.size, bad[0], bad[0] // 16))
+
+
+# --- C1: AES-128 ECB encrypt then decrypt, 1 MiB, whole buffer -------------
+def test_c1_ecb_1mib(A, O):
+    k = seedgen.key(1, 0, 128)
+    rk, nr = A.aes_expand_key(k)
+    x = seedgen.data_np(1, 0, 1 << 20)
+    ct = gpu_op(A, "enc", x, rk, nr)
+    assert_same(ct, O.ecb_encrypt(rk, nr, x), "C1 encrypt")
+    pt = gpu_op(A, "dec", ct, rk, nr)
+    assert_same(pt, x, "C1 decrypt(encrypt(x))")
+
+
+SIZES = [16, 4096, 65535 * 16, (1 << 20) + 48]
+CTR_ONLY_SIZES = [1, 15, 17, 31, 1000003]
+
+
+@pytest.mark.parametrize("bits", [128, 192, 256])
+@pytest.mark.parametrize("op", ["enc", "dec", "ctr", "ctr_dec"])
+@pytest.mark.parametrize("nbytes", SIZES + CTR_ONLY_SIZES)
+def test_sizes(A, O, bits, op, nbytes):
+    if op in ("enc", "dec") and nbytes % 16:
+        pytest.skip("ECB takes whole blocks")
+    seed = 1000 * bits + nbytes
+    k = seedgen.key(3, seed, bits)
+    rk, nr = A.aes_expand_key(k)
+    x = seedgen.data_np(3, seed, nbytes)
+    ctr0 = seedgen.nonce(3, seed)
+    got = gpu_op(A, op, x, rk, nr, ctr0=ctr0)
+    assert_same(got, oracle_op(O, op, x, rk, nr, ctr0), "%s AES-%d %d bytes" % (op, bits, nbytes))
+
+
+def test_empty_buffer(A):
+    rk, nr = A.aes_expand_key(bytes(16))
+    x = torch.empty(0, dtype=torch.uint8, device="cuda")
+    A.aes_encrypt(x, x, 0, rk, nr, "ecb")
+    A.aes_decrypt(x, x, 0, rk, nr, "ctr", ctr0=bytes(16))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("op", ["enc", "dec", "ctr"])
+def test_in_place_equals_out_of_place(A, O, op):
+    k = seedgen.key(4, 0, 256)
+    rk, nr = A.aes_expand_key(k)
+    x = seedgen.data_np(4, 0, 300000 * 16 + (0 if op != "ctr" else 7))
+    ctr0 = seedgen.nonce(4, 0)
+    a = gpu_op(A, op, x, rk, nr, ctr0=ctr0)
+    b = gpu_op(A, op, x, rk, nr, ctr0=ctr0, inplace=True)
+    assert_same(b, a, "in place vs out of place")
+    assert_same(a, oracle_op(O, op, x, rk, nr, ctr0), "oracle")
+
+
+def test_ctr_counter_wraps_without_carry(A, O):
+    k = seedgen.key(5, 0, 128)
+    rk, nr = A.aes_expand_key(k)
+    ctr0 = seedgen.nonce(5, 0)
+    ctr0[12:16] = [0xFF, 0xFF, 0xFF, 0xF0]
+    x = seedgen.data_np(5, 0, 16 * 5000 + 3)
+    got = gpu_op(A, "ctr", x, rk, nr, ctr0=ctr0)
+    assert_same(got, O.ctr(rk, nr, ctr0, x), "CTR across the 2^32 wrap")
+
+
+LAUNCHES = [dict(layout=l, blocks_per_thread=b, wg_size=w, grid=g)
+            for l in (0, 1) for b in (1, 2, 4) for w in (256, 1024) for g in (0, 1, 7)]
+
+
+@pytest.fixture(scope="module")
+def ragged_case(A, O):
+    k = seedgen.key(6, 0, 128)
+    rk, nr = A.aes_expand_key(k)
+    x = seedgen.data_np(6, 0, 3 * 65536 * 16 + 48 + 5)
+    ctr0 = seedgen.nonce(6, 0)
+    n16 = x.size - 5
+    want = {"enc": O.ecb_encrypt(rk, nr, x[:n16]), "dec": O.ecb_decrypt(rk, nr, x[:n16]),
+            "ctr": O.ctr(rk, nr, ctr0, x)}
+    return rk, nr, x, n16, ctr0, want
+
+
+@pytest.mark.parametrize("cfg", LAUNCHES, ids=lambda c: "L%d-B%d-W%d-G%d" % tuple(c.values()))
+def test_launch_configurations_agree(A, ragged_case, cfg):
+    rk, nr, x, n16, ctr0, want = ragged_case
+    A.aes_set_launch(cfg)
+    try:
+        assert_same(gpu_op(A, "enc", x[:n16], rk, nr), want["enc"], "enc %s" % cfg)
+        assert_same(gpu_op(A, "dec", x[:n16], rk, nr), want["dec"], "dec %s" % cfg)
+        assert_same(gpu_op(A, "ctr", x, rk, nr, ctr0=ctr0), want["ctr"], "ctr %s" % cfg)
+    finally:
+        A.aes_set_launch(None)
+
+
+def test_side_stream(A, O):
+    k = seedgen.key(7, 0, 256)
+    rk, nr = A.aes_expand_key(k)
+    x = seedgen.data_np(7, 0, 1 << 18)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got = gpu_op(A, "enc", x, rk, nr, stream=s)
+    assert_same(got, O.ecb_encrypt(rk, nr, x), "side stream")
+
+
+def test_device_errors(A):
+    rk, nr = A.aes_expand_key(bytes(16))
+    x = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(A.AESError) as e:
+        A.aes_encrypt(x[1:], x[1:], 1024, rk, nr, "ecb")
+    assert e.value.code == A.AES_E_ALIGN
+    with pytest.raises(A.AESError) as e:
+        A.aes_encrypt(x[:1024], x[16:], 1024, rk, nr, "ecb")
+    assert e.value.code == A.AES_E_OVERLAP
+
+
+def test_copy_helper(A):
+    x = seedgen.data_torch(8, 0, (1 << 20) + 16 * 3, "cuda")
+    y = torch.empty_like(x)
+    A.aes_copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+
+
+def test_device_generator_matches_host(A):
+    for n in (1, 1000, (1 << 22) + 5):
+        d = seedgen.data_torch(9, 1, n, "cuda").cpu().numpy()
+        assert np.array_equal(d, seedgen.data_np(9, 1, n))
+
+
+# --- full sizes, sampled -------------------------------------------------
+def sample_blocks(nblocks, count, seed):
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, nblocks, size=count)
+    return np.unique(np.concatenate([idx, [0, 1, nblocks - 2, nblocks - 1]]))
+
+
+def check_sampled(O, out_dev, master, index, rk, nr, op, ctr0, idx, what):
+    got = out_dev.view(-1, 16)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+    for r, j in enumerate(idx):
+        x = seedgen.data_np(master, index, 16, offset=16 * int(j))
+        if op == "enc":
+            want = O.encrypt_block(rk, nr, x)
+        elif op == "dec":
+            want = O.decrypt_block(rk, nr, x)
+        else:
+            want = O.ctr(rk, nr, ctr0, x, first_block=int(j))
+        if not np.array_equal(got[r], want):
+            raise AssertionError("%s: block %d differs" % (what, j))
+
+
+@pytest.mark.parametrize("bits,nbytes,ops", [
+    (128, 1 << 30, ("enc", "ctr")),          # the throughput workload: 1 GiB, AES-128
+    (256, 1 << 24, ("enc", "ctr")),
+    (256, 1 << 28, ("enc", "ctr")),
+    (256, 1 << 32, ("enc", "ctr")),
+], ids=["aes128-1GiB", "aes256-16MiB", "aes256-256MiB", "aes256-4GiB"])
+def test_full_size_sampled(A, O, bits, nbytes, ops):
+    master, index = 2 if bits == 128 else 3, 0
+    k = seedgen.key(master, index, bits)
+    rk, nr = A.aes_expand_key(k)
+    ctr0 = seedgen.nonce(master, index)
+    x = seedgen.data_torch(master, index, nbytes, "cuda")
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    idx = sample_blocks(nbytes // 16, 2048, nbytes)
+    for op in ops:
+        mode = "ecb" if op == "enc" else "ctr"
+        A.aes_encrypt(x, y, nbytes, rk, nr, mode, ctr0=ctr0)
+        torch.cuda.synchronize()
+        check_sampled(O, y, master, index, rk, nr, op, ctr0, idx, "%s %d bytes" % (op, nbytes))
+        if op == "enc":
+            # the decryption kernel on its own, applied to the random input
+            A.aes_decrypt(x, z, nbytes, rk, nr, mode)
+            torch.cuda.synchronize()
+            check_sampled(O, z, master, index, rk, nr, "dec", ctr0, idx, "dec %d bytes" % nbytes)
+        A.aes_decrypt(y, z, nbytes, rk, nr, mode, ctr0=ctr0)
+        torch.cuda.synchronize()
+        assert torch.equal(z, x), "%s: decrypt(encrypt(x)) != x" % op
+    del x, y, z
+    torch.cuda.empty_cache()
+
+
+def test_aes256_16mib_whole_buffer(A, O):
+    k = seedgen.key(3, 0, 256)
+    rk, nr = A.aes_expand_key(k)
+    ctr0 = seedgen.nonce(3, 0)
+    x = seedgen.data_np(3, 0, 1 << 24)
+    want, _ = O.par_run(0, rk, nr, x, 16)
+    assert_same(gpu_op(A, "enc", x, rk, nr), want, "AES-256 ECB 16 MiB")
+    want, _ = O.par_run(2, rk, nr, x, 16, ctr0=ctr0)
+    assert_same(gpu_op(A, "ctr", x, rk, nr, ctr0=ctr0), want, "AES-256 CTR 16 MiB")
