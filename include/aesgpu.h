@@ -39,13 +39,13 @@ extern "C" {
 
 typedef enum {
     AES_OK = 0,
-    AES_E_NULL = 1,     /* a required pointer is NULL                        */
+    AES_E_NULL = 1,     /* a required pointer is NULL (ctr0 in CTR mode too) */
     AES_E_KEYBITS = 2,  /* key size not 128, 192 or 256                      */
     AES_E_NR = 3,       /* Nr not 10, 12 or 14                               */
     AES_E_LENGTH = 4,   /* ECB length not a multiple of 16, or size too big  */
     AES_E_ALIGN = 5,    /* device pointer not 16-byte aligned                */
     AES_E_OVERLAP = 6,  /* in and out overlap without being identical        */
-    AES_E_MODE = 7,     /* unknown mode, or a CTR call without a counter     */
+    AES_E_MODE = 7,     /* unknown mode                                      */
     AES_E_DEVICE = 8,   /* no usable gfx950 device, or a HIP call failed     */
     AES_E_ARG = 9       /* any other invalid argument                        */
 } aes_status;
@@ -139,6 +139,93 @@ int aes_get_launch(size_t nbytes, int mode, int decrypt, aes_launch *cfg);
  * byte counts.  Errors as for aes_encrypt.
  */
 int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
+
+
+/* ---------------------------------------------------------------------- */
+/* Batches: many independent messages, each with its own key, length and  */
+/* mode, in one launch sequence.                                           */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * One message of a batch (48 bytes, device-resident array).  The message is
+ * nbytes bytes at in_base + in_off, written to out_base + out_off; both
+ * offsets are multiples of 16.  Its key is the first 16/24/32 bytes of the
+ * 32-byte slot key_idx of the key array.  ECB messages are whole blocks;
+ * CTR messages may end in a partial block.  For CTR, ctr0 is the initial
+ * counter block exactly as for aes_encrypt.
+ */
+typedef struct {
+    uint64_t in_off;
+    uint64_t out_off;
+    uint64_t nbytes;
+    uint32_t key_idx;
+    uint8_t keybits_code;  /* 0 = 128, 1 = 192, 2 = 256 */
+    uint8_t mode;          /* AES_MODE_ECB or AES_MODE_CTR */
+    uint8_t decrypt;       /* 0 = encrypt, 1 = decrypt */
+    uint8_t reserved;
+    uint8_t ctr0[16];
+} aes_msg_desc;
+
+/*
+ * A batch.  Every pointer is a device pointer owned by the caller.
+ *   desc, nmsg       the messages.  If d_nmsg is not NULL the count is read
+ *                    from that device int at run time instead (it must stay
+ *                    <= max_msgs), so a captured graph can be replayed with a
+ *                    different number of messages.
+ *   keys, nkeys      raw keys, 32-byte slots.
+ *   in_base/in_bytes, out_base/out_bytes   the buffers messages live in; a
+ *                    message that does not fit inside them is rejected.
+ *   workspace        256-byte aligned scratch of workspace_bytes, sized by
+ *                    aes_batch_workspace_size for (max_msgs, max_total_blocks,
+ *                    tile_blocks).  It holds the expanded key schedules, the
+ *                    tile table and the counters.
+ *   tile_blocks      16-byte blocks per unit of work (a tile never spans two
+ *                    messages); 0 = library choice.
+ * The sequence is: on-device Key Expansion for every message (FIPS-197
+ * section 5.2; the decryption schedule of section 5.3.5 where needed); a plan
+ * that cuts messages into tiles (the paper's chunking, Section IV-A, applied
+ * per message); then persistent kernels whose waves take tiles off a counter
+ * until none is left.  A message with an invalid descriptor (bad key code or
+ * mode, ECB length not a multiple of 16, misaligned offset, outside the
+ * buffers, key_idx >= nkeys) is skipped and counted (aes_batch_query).
+ */
+typedef struct {
+    const aes_msg_desc *desc;
+    int nmsg;
+    const int *d_nmsg;
+    const uint8_t *keys;
+    int nkeys;
+    const void *in_base;
+    uint64_t in_bytes;
+    void *out_base;
+    uint64_t out_bytes;
+    void *workspace;
+    size_t workspace_bytes;
+    int max_msgs;
+    uint64_t max_total_blocks;
+    int tile_blocks;
+} aes_batch;
+
+/* Workspace bytes for up to max_msgs messages holding up to
+ * max_total_blocks 16-byte blocks (partial blocks count as whole) in tiles
+ * of tile_blocks blocks (0 = library choice).  Host only. */
+int aes_batch_workspace_size(int max_msgs, uint64_t max_total_blocks, int tile_blocks,
+                             size_t *bytes);
+
+/* Enqueue the whole batch on `stream`.  Errors are found on the host from
+ * the aes_batch fields; descriptor contents are checked on the device. */
+int aes_batch_run(const aes_batch *b, void *stream);
+
+/* After the stream has run the batch: tiles processed and messages
+ * rejected by the device-side checks.  Synchronous (waits for `stream`). */
+int aes_batch_query(const aes_batch *b, void *stream, uint64_t *tiles, uint64_t *rejected);
+
+/* The same sequence captured once as a HIP graph for repeated launches on
+ * any stream.  Descriptors, keys and (through d_nmsg) the message count may
+ * be rewritten between launches; the pointers and sizes in *b may not. */
+int aes_batch_graph_create(const aes_batch *b, void **graph);
+int aes_batch_graph_launch(void *graph, void *stream);
+int aes_batch_graph_destroy(void *graph);
 
 #ifdef __cplusplus
 }

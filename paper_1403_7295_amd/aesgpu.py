@@ -48,6 +48,15 @@ _SIGNATURES = {
                                       ctypes.c_void_p]),
     "aes_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                 ctypes.c_void_p]),
+    "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "aes_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "aes_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64)]),
+    "aes_batch_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "aes_batch_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "aes_batch_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 
@@ -63,6 +72,24 @@ class aes_launch(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# aes_msg_desc, as a numpy record so that whole descriptor tables are built
+# with array operations
+MSG_DESC_DTYPE = np.dtype([("in_off", "<u8"), ("out_off", "<u8"), ("nbytes", "<u8"),
+                           ("key_idx", "<u4"), ("keybits_code", "u1"), ("mode", "u1"),
+                           ("decrypt", "u1"), ("reserved", "u1"), ("ctr0", "u1", (16,))])
+assert MSG_DESC_DTYPE.itemsize == 48
+
+
+class aes_batch(ctypes.Structure):
+    _fields_ = [("desc", ctypes.c_void_p), ("nmsg", ctypes.c_int), ("d_nmsg", ctypes.c_void_p),
+                ("keys", ctypes.c_void_p), ("nkeys", ctypes.c_int),
+                ("in_base", ctypes.c_void_p), ("in_bytes", ctypes.c_uint64),
+                ("out_base", ctypes.c_void_p), ("out_bytes", ctypes.c_uint64),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("max_msgs", ctypes.c_int), ("max_total_blocks", ctypes.c_uint64),
+                ("tile_blocks", ctypes.c_int)]
 
 
 def _load():
@@ -198,3 +225,143 @@ def decrypt(x, roundkeys, Nr, mode="ecb", ctr0=None, out=None, stream=None):
     import torch
     out = torch.empty_like(x) if out is None else out
     return aes_decrypt(x, out, x.numel() * x.element_size(), roundkeys, Nr, mode, ctr0, stream)
+
+
+# --- batches ----------------------------------------------------------------
+def aes_batch_workspace_size(max_msgs, max_total_blocks, tile_blocks=0):
+    n = ctypes.c_size_t(0)
+    _check(lib.aes_batch_workspace_size(max_msgs, max_total_blocks, tile_blocks, ctypes.byref(n)))
+    return n.value
+
+
+def aes_batch_run(batch, stream=None):
+    _check(lib.aes_batch_run(ctypes.byref(batch), _stream_handle(stream)))
+
+
+def aes_batch_query(batch, stream=None):
+    """Waits for `stream`; returns (tiles processed, messages rejected)."""
+    t, r = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(lib.aes_batch_query(ctypes.byref(batch), _stream_handle(stream), ctypes.byref(t),
+                               ctypes.byref(r)))
+    return t.value, r.value
+
+
+def aes_batch_graph_create(batch):
+    g = ctypes.c_void_p(0)
+    _check(lib.aes_batch_graph_create(ctypes.byref(batch), ctypes.byref(g)))
+    return g
+
+
+def aes_batch_graph_launch(graph, stream=None):
+    _check(lib.aes_batch_graph_launch(graph, _stream_handle(stream)))
+
+
+def aes_batch_graph_destroy(graph):
+    _check(lib.aes_batch_graph_destroy(graph))
+
+
+def make_descs(nbytes, in_off=None, out_off=None, key_idx=None, keybits=128, mode="ecb",
+               decrypt=False, ctr0=None):
+    """Descriptor table (numpy, MSG_DESC_DTYPE) for messages of the given
+    lengths.  Offsets default to the messages packed back to back, each
+    starting on a 16-byte boundary; scalars broadcast over messages."""
+    nbytes = np.asarray(nbytes, dtype=np.uint64).reshape(-1)
+    n = nbytes.size
+    d = np.zeros(n, MSG_DESC_DTYPE)
+    d["nbytes"] = nbytes
+    if in_off is None:
+        padded = (nbytes + np.uint64(15)) // np.uint64(16) * np.uint64(16)
+        in_off = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.uint64) if n else padded
+    d["in_off"] = in_off
+    d["out_off"] = in_off if out_off is None else out_off
+    d["key_idx"] = np.arange(n) if key_idx is None else key_idx
+    kb = np.broadcast_to(np.asarray(keybits), (n,))
+    d["keybits_code"] = (kb.astype(np.int64) - 128) // 64
+    md = np.broadcast_to(np.asarray(mode), (n,))
+    d["mode"] = [_mode(m) for m in md] if md.dtype.kind in "UO" else md
+    d["decrypt"] = np.broadcast_to(np.asarray(decrypt, dtype=np.uint8), (n,))
+    if ctr0 is not None:
+        d["ctr0"] = np.broadcast_to(np.asarray(ctr0, dtype=np.uint8), (n, 16))
+    return d
+
+
+class Batch:
+    """A batch of messages on the device: descriptors, keys and workspace held
+    in torch tensors (torch supplies the memory), run through
+    aes_batch_run or a captured graph.
+
+    descs      numpy MSG_DESC_DTYPE array (see make_descs)
+    keys       numpy uint8 array (nkeys, 32): one key per 32-byte slot
+    inp, out   device tensors the descriptors' offsets point into
+    """
+
+    def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None,
+                 max_total_blocks=None, device=None):
+        import torch
+        self.device = device or inp.device
+        descs = np.ascontiguousarray(descs, dtype=MSG_DESC_DTYPE)
+        keys = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
+        self.max_msgs = max(1, int(max_msgs or len(descs)))
+        blocks = int(((descs["nbytes"].astype(np.uint64) + 15) // 16).sum()) if len(descs) else 0
+        self.max_total_blocks = int(max_total_blocks if max_total_blocks is not None else blocks)
+        self.tile_blocks = int(tile_blocks)
+        self.d_desc = torch.zeros(self.max_msgs * 48, dtype=torch.uint8, device=self.device)
+        self.d_nmsg = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.d_keys = torch.from_numpy(keys.reshape(-1).copy()).to(self.device)
+        ws = aes_batch_workspace_size(self.max_msgs, self.max_total_blocks, self.tile_blocks)
+        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.inp, self.out = inp, out
+        self.c = aes_batch(desc=self.d_desc.data_ptr(), nmsg=0, d_nmsg=None,
+                           keys=self.d_keys.data_ptr(), nkeys=keys.shape[0],
+                           in_base=inp.data_ptr(), in_bytes=inp.numel() * inp.element_size(),
+                           out_base=out.data_ptr(), out_bytes=out.numel() * out.element_size(),
+                           workspace=aligned, workspace_bytes=ws, max_msgs=self.max_msgs,
+                           max_total_blocks=self.max_total_blocks, tile_blocks=self.tile_blocks)
+        self.graph = None
+        self.set_descs(descs)
+
+    def set_descs(self, descs, keys=None, stream=None):
+        """Rewrite the descriptors (and optionally the keys) in place."""
+        import torch
+        descs = np.ascontiguousarray(descs, dtype=MSG_DESC_DTYPE)
+        if len(descs) > self.max_msgs:
+            raise ValueError("batch holds at most %d messages" % self.max_msgs)
+        raw = torch.from_numpy(descs.view(np.uint8).reshape(-1).copy())
+        self.d_desc[:raw.numel()].copy_(raw)
+        self.d_nmsg.fill_(len(descs))
+        self.c.nmsg = len(descs)
+        if keys is not None:
+            k = torch.from_numpy(np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1).copy())
+            self.d_keys[:k.numel()].copy_(k)
+
+    def run(self, stream=None):
+        aes_batch_run(self.c, stream)
+
+    def query(self, stream=None):
+        return aes_batch_query(self.c, stream)
+
+    def capture(self):
+        """Capture the batch as a graph whose message count is read from the
+        device at each launch."""
+        if self.graph is None:
+            c = aes_batch.from_buffer_copy(self.c)
+            c.d_nmsg = self.d_nmsg.data_ptr()
+            self.graph_c = c
+            self.graph = aes_batch_graph_create(c)
+        return self.graph
+
+    def launch_graph(self, stream=None):
+        aes_batch_graph_launch(self.capture(), stream)
+
+    def close(self):
+        if self.graph is not None:
+            aes_batch_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

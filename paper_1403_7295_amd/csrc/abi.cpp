@@ -50,6 +50,8 @@ void init_device(int dev) {
         return;
     }
     e = upload_tables(host_tables());
+    if (e == hipSuccess)
+        e = upload_tables_batch(host_tables());
     if (e != hipSuccess) {
         d.error = std::string("table upload: ") + hipGetErrorString(e);
         return;
@@ -177,6 +179,58 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
     return AES_OK;
 }
 
+constexpr int kDefaultTileBlocks = 8192;  // 128 KiB of data per tile
+
+// Tile capacity and workspace bytes for a batch shape; 0 bytes if too big.
+size_t batch_layout(int max_msgs, uint64_t max_total_blocks, int tile_blocks, uint64_t *capacity) {
+    const uint64_t t = uint64_t(tile_blocks);
+    const uint64_t cap = uint64_t(max_msgs) + (max_total_blocks + t - 1) / t;
+    if (capacity)
+        *capacity = cap;
+    if (cap >= (uint64_t(1) << 32))
+        return 0;
+    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 2 * size_t(cap) * sizeof(BatchTile);
+}
+
+int batch_args(const aes_batch *b, BatchKArgs *a) {
+    if (!b)
+        return fail(AES_E_NULL, "batch must not be NULL");
+    if (!b->desc || !b->keys || !b->in_base || !b->out_base || !b->workspace)
+        return fail(AES_E_NULL, "desc, keys, in_base, out_base and workspace must not be NULL");
+    if (b->max_msgs < 1 || b->nmsg < 0 || b->nmsg > b->max_msgs || b->nkeys < 1)
+        return fail(AES_E_ARG, "need 1 <= max_msgs, 0 <= nmsg <= max_msgs and nkeys >= 1");
+    if (b->tile_blocks < 0)
+        return fail(AES_E_ARG, "tile_blocks must be >= 0");
+    if ((reinterpret_cast<uintptr_t>(b->in_base) | reinterpret_cast<uintptr_t>(b->out_base)) & 15u)
+        return fail(AES_E_ALIGN, "in_base and out_base must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(b->workspace) & 255u)
+        return fail(AES_E_ALIGN, "workspace must be 256-byte aligned");
+    const int tile = b->tile_blocks ? b->tile_blocks : kDefaultTileBlocks;
+    uint64_t cap = 0;
+    const size_t need = batch_layout(b->max_msgs, b->max_total_blocks, tile, &cap);
+    if (need == 0)
+        return fail(AES_E_LENGTH, "batch too large for one workspace");
+    if (b->workspace_bytes < need)
+        return fail(AES_E_LENGTH, "workspace smaller than aes_batch_workspace_size reports");
+    char *ws = static_cast<char *>(b->workspace);
+    a->desc = b->desc;
+    a->nmsg = b->nmsg;
+    a->d_nmsg = b->d_nmsg;
+    a->max_msgs = b->max_msgs;
+    a->keys = b->keys;
+    a->nkeys = b->nkeys;
+    a->in_base = b->in_base;
+    a->in_bytes = b->in_bytes;
+    a->out_base = b->out_base;
+    a->out_bytes = b->out_bytes;
+    a->header = reinterpret_cast<BatchHeader *>(ws);
+    a->keytab = reinterpret_cast<uint32_t *>(ws + sizeof(BatchHeader));
+    a->tiles = reinterpret_cast<BatchTile *>(ws + sizeof(BatchHeader) + size_t(b->max_msgs) * kKeySlotWords * 4);
+    a->tile_capacity = cap;
+    a->tile_blocks = uint32_t(tile);
+    return AES_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -251,6 +305,106 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream) {
     hipError_t e = launch_copy(in, out, nbytes, d->cus, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
+int aes_batch_workspace_size(int max_msgs, uint64_t max_total_blocks, int tile_blocks, size_t *bytes) {
+    if (!bytes)
+        return fail(AES_E_NULL, "bytes must not be NULL");
+    if (max_msgs < 1 || tile_blocks < 0)
+        return fail(AES_E_ARG, "need max_msgs >= 1 and tile_blocks >= 0");
+    const size_t n = batch_layout(max_msgs, max_total_blocks, tile_blocks ? tile_blocks : kDefaultTileBlocks,
+                                  nullptr);
+    if (n == 0)
+        return fail(AES_E_LENGTH, "batch too large for one workspace");
+    *bytes = n;
+    return AES_OK;
+}
+
+int aes_batch_run(const aes_batch *b, void *stream) {
+    BatchKArgs a;
+    int st = batch_args(b, &a);
+    if (st != AES_OK)
+        return st;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+    hipError_t e = launch_batch(a, d->cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
+int aes_batch_query(const aes_batch *b, void *stream, uint64_t *tiles, uint64_t *rejected) {
+    BatchKArgs a;
+    int st = batch_args(b, &a);
+    if (st != AES_OK)
+        return st;
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    BatchHeader h;
+    if (e == hipSuccess)
+        e = hipMemcpy(&h, a.header, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("batch query: ") + hipGetErrorString(e));
+    if (tiles)
+        *tiles = uint64_t(h.ntiles[0]) + h.ntiles[1];
+    if (rejected)
+        *rejected = h.rejected;
+    if (h.overflow)
+        return fail(AES_E_LENGTH, "the batch's tiles did not fit the workspace; nothing was processed for "
+                                  "the list that overflowed");
+    return AES_OK;
+}
+
+int aes_batch_graph_create(const aes_batch *b, void **graph) {
+    if (!graph)
+        return fail(AES_E_NULL, "graph must not be NULL");
+    BatchKArgs a;
+    int st = batch_args(b, &a);
+    if (st != AES_OK)
+        return st;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+    hipStream_t s = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_batch(a, d->cus, s);
+        e = hipStreamEndCapture(s, &g);
+        if (le != hipSuccess)
+            e = le;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (g)
+        (void)hipGraphDestroy(g);
+    if (s)
+        (void)hipStreamDestroy(s);
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    *graph = x;
+    return AES_OK;
+}
+
+int aes_batch_graph_launch(void *graph, void *stream) {
+    if (!graph)
+        return fail(AES_E_NULL, "graph must not be NULL");
+    hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(graph), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
+int aes_batch_graph_destroy(void *graph) {
+    if (!graph)
+        return AES_OK;
+    hipError_t e = hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("graph destroy: ") + hipGetErrorString(e));
     return AES_OK;
 }
 

@@ -1,0 +1,275 @@
+// Batches of independent messages (each with its own key, length, mode and
+// direction) in one launch sequence:
+//
+//   keyexp_kernel   one lane per message: Key Expansion on the device
+//                   (FIPS-197 section 5.2), plus the equivalent-inverse
+//                   schedule (section 5.3.5) for ECB decryption.
+//   plan_kernel     one workgroup: checks every descriptor, cuts each message
+//                   into tiles of at most T blocks (a tile never spans two
+//                   messages), and lays the tiles out in two lists: forward
+//                   (ECB encryption and CTR, which use the encryption tables)
+//                   and inverse (ECB decryption, which uses the inverse ones).
+//                   It also zeroes the two tile counters, so the sequence can
+//                   be replayed from a graph without any memset.
+//   batch_kernel    persistent, one per list: every wave takes the next tile
+//                   off its list's counter, reads that message's round keys
+//                   into scalar registers and runs the same block loop as the
+//                   single-buffer kernels, until the list is empty.
+//
+// This is the paper's method (cut the data into chunks, process the chunks
+// in parallel, Section IV) applied per message, with the chunk size chosen
+// for the GPU rather than by the number of cores.
+#include <hip/hip_runtime.h>
+
+#include "aesgpu.h"
+#include "cipher_core.h"
+#include "internal.h"
+
+namespace aesgpu {
+namespace {
+
+constexpr int kPlanThreads = 1024;
+
+__device__ __forceinline__ int desc_nr(const aes_msg_desc &d) { return 10 + 2 * int(d.keybits_code); }
+
+// Same test as the host applies to a single-buffer call, plus bounds.
+__device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKArgs &a) {
+    if (d.keybits_code > 2 || d.mode > 1 || d.decrypt > 1)
+        return false;
+    if (d.mode == AES_MODE_ECB && (d.nbytes & 15u))
+        return false;
+    if ((d.in_off | d.out_off) & 15u)
+        return false;
+    if (d.key_idx >= uint32_t(a.nkeys))
+        return false;
+    if (d.nbytes > a.in_bytes || d.in_off > a.in_bytes - d.nbytes)
+        return false;
+    if (d.nbytes > a.out_bytes || d.out_off > a.out_bytes - d.nbytes)
+        return false;
+    return true;
+}
+
+__device__ __forceinline__ int desc_class(const aes_msg_desc &d) {
+    return (d.mode == AES_MODE_ECB && d.decrypt) ? 1 : 0;
+}
+
+__device__ __forceinline__ uint32_t batch_count(const BatchKArgs &a) {
+    int n = a.d_nmsg ? *a.d_nmsg : a.nmsg;
+    if (n < 0)
+        n = 0;
+    if (n > a.max_msgs)
+        n = a.max_msgs;
+    return uint32_t(n);
+}
+
+__device__ __forceinline__ uint32_t sbox(uint32_t x) { return (g_base[x & 255u] >> 8) & 255u; }
+
+__device__ __forceinline__ uint32_t sub_word(uint32_t w) {
+    return sbox(w) | (sbox(w >> 8) << 8) | (sbox(w >> 16) << 16) | (sbox(w >> 24) << 24);
+}
+
+// InvMixColumns of a column word, through the inverse round table:
+// td0[S[b]] is InvMixColumns of the column (b, 0, 0, 0).
+__device__ __forceinline__ uint32_t inv_mix_column(uint32_t w) {
+    return g_base[256 + sbox(w)] ^ rotl(g_base[256 + sbox(w >> 8)], 8) ^
+           rotl(g_base[256 + sbox(w >> 16)], 16) ^ rotl(g_base[256 + sbox(w >> 24)], 24);
+}
+
+__global__ __launch_bounds__(256) void keyexp_kernel(const BatchKArgs a) {
+    const uint32_t n = batch_count(a);
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n)
+        return;
+    const aes_msg_desc d = a.desc[m];
+    if (!desc_valid(d, a))
+        return;
+    const int nk = 4 + 2 * int(d.keybits_code), nr = nk + 6;
+    uint32_t *w = a.keytab + size_t(m) * kKeySlotWords;
+    const uint8_t *key = a.keys + size_t(d.key_idx) * 32;
+    uint32_t prev = 0;
+    for (int i = 0; i < nk; i++) {
+        prev = uint32_t(key[4 * i]) | (uint32_t(key[4 * i + 1]) << 8) | (uint32_t(key[4 * i + 2]) << 16) |
+               (uint32_t(key[4 * i + 3]) << 24);
+        w[i] = prev;
+    }
+    uint32_t rcon = 1;
+    for (int i = nk; i < 4 * (nr + 1); i++) {
+        uint32_t t = prev;
+        if (i % nk == 0) {
+            t = sub_word(rotl(t, 24)) ^ rcon;  // RotWord is a right rotation of a little-endian word
+            rcon = ((rcon << 1) ^ ((rcon & 0x80u) ? 0x1bu : 0u)) & 0xffu;
+        } else if (nk > 6 && i % nk == 4) {
+            t = sub_word(t);
+        }
+        prev = w[i - nk] ^ t;
+        w[i] = prev;
+    }
+    if (desc_class(d) == 1) {
+        uint32_t *dk = w + kKeySlotWords / 2;
+        for (int c = 0; c < 4; c++) {
+            dk[c] = w[4 * nr + c];
+            dk[4 * nr + c] = w[c];
+        }
+        for (int r = 1; r < nr; r++)
+            for (int c = 0; c < 4; c++)
+                dk[4 * r + c] = inv_mix_column(w[4 * (nr - r) + c]);
+    }
+}
+
+__device__ __forceinline__ uint64_t tiles_of(const aes_msg_desc &d, uint32_t tile_blocks) {
+    const uint64_t nblk = (d.nbytes + 15) >> 4;
+    return (nblk + tile_blocks - 1) / tile_blocks;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) {
+    __shared__ uint64_t cnt[2][kPlanThreads];
+    __shared__ uint64_t base[2];
+    __shared__ uint32_t bad[kPlanThreads];
+    const uint32_t n = batch_count(a);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (n + kPlanThreads - 1) / kPlanThreads;
+    const uint32_t m0 = min(n, tid * per), m1 = min(n, m0 + per);
+    uint64_t c[2] = {0, 0};
+    uint32_t rejected = 0;
+    for (uint32_t m = m0; m < m1; m++) {
+        const aes_msg_desc d = a.desc[m];
+        if (!desc_valid(d, a)) {
+            rejected++;
+            continue;
+        }
+        c[desc_class(d)] += tiles_of(d, a.tile_blocks);
+    }
+    cnt[0][tid] = c[0];
+    cnt[1][tid] = c[1];
+    bad[tid] = rejected;
+    __syncthreads();
+    if (tid < 2) {
+        // exclusive scan of one class's per-thread counts (1024 adds)
+        uint64_t run = 0;
+        for (int t = 0; t < kPlanThreads; t++) {
+            const uint64_t v = cnt[tid][t];
+            cnt[tid][t] = run;
+            run += v;
+        }
+        base[tid] = run;
+    }
+    __syncthreads();
+    const bool fits0 = base[0] <= a.tile_capacity, fits1 = base[1] <= a.tile_capacity;
+    uint64_t off[2] = {cnt[0][tid], cnt[1][tid]};
+    for (uint32_t m = m0; m < m1; m++) {
+        const aes_msg_desc d = a.desc[m];
+        if (!desc_valid(d, a))
+            continue;
+        const int k = desc_class(d);
+        if (!(k == 0 ? fits0 : fits1))
+            continue;
+        const uint64_t nblk = (d.nbytes + 15) >> 4;
+        BatchTile *list = a.tiles + size_t(k) * a.tile_capacity;
+        for (uint64_t first = 0; first < nblk; first += a.tile_blocks) {
+            BatchTile t;
+            t.msg = m;
+            t.count = uint32_t(min<uint64_t>(a.tile_blocks, nblk - first));
+            t.first = first;
+            list[off[k]++] = t;
+        }
+    }
+    if (tid == 0) {
+        uint32_t r = 0;
+        for (int t = 0; t < kPlanThreads; t++)
+            r += bad[t];
+        BatchHeader *h = a.header;
+        h->ntiles[0] = fits0 ? uint32_t(base[0]) : 0u;
+        h->ntiles[1] = fits1 ? uint32_t(base[1]) : 0u;
+        h->next[0] = 0;
+        h->next[1] = 0;
+        h->rejected = r;
+        h->overflow = (fits0 && fits1) ? 0u : 1u;
+    }
+}
+
+template <int NR, int MODE, int DIR, int BPT>
+__device__ __forceinline__ void run_tile(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
+                                         const aes_msg_desc &d, const BatchTile &t) {
+    // The round keys are the same for the whole wave: read them once per
+    // tile and keep them in scalar registers.  (The compiler cannot use
+    // scalar loads itself here: the kernel also stores to memory that it
+    // cannot prove distinct from the key table.)
+    const uint32_t *rkp = a.keytab + size_t(t.msg) * kKeySlotWords + (DIR == DIR_DEC ? kKeySlotWords / 2 : 0);
+    uint32_t rk[4 * (NR + 1)];
+#pragma unroll
+    for (int i = 0; i < 4 * (NR + 1); i++)
+        rk[i] = __builtin_amdgcn_readfirstlane(rkp[i]);
+    uint32_t ctr[4] = {0, 0, 0, 0};
+    if (MODE == MODE_CTR) {
+        for (int i = 0; i < 3; i++)
+            ctr[i] = uint32_t(d.ctr0[4 * i]) | (uint32_t(d.ctr0[4 * i + 1]) << 8) |
+                     (uint32_t(d.ctr0[4 * i + 2]) << 16) | (uint32_t(d.ctr0[4 * i + 3]) << 24);
+        ctr[3] = (uint32_t(d.ctr0[12]) << 24) | (uint32_t(d.ctr0[13]) << 16) | (uint32_t(d.ctr0[14]) << 8) |
+                 uint32_t(d.ctr0[15]);
+    }
+    const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
+    uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
+    process_blocks<NR, MODE, DIR, LAYOUT_T4X32, BPT>(lds, lc, rk, ctr, in, out, d.nbytes, t.first,
+                                                     t.first + t.count, 64u * BPT);
+}
+
+template <int CLASS, int BPT>
+__global__ __launch_bounds__(1024) void batch_kernel(const BatchKArgs a) {
+    constexpr int DIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
+    const uint32_t ntiles = a.header->ntiles[CLASS];
+    if (ntiles == 0)
+        return;
+    __shared__ uint32_t lds[lds_words<DIR>()];
+    stage_tables<LAYOUT_T4X32, DIR>(lds);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
+    const BatchTile *list = a.tiles + size_t(CLASS) * a.tile_capacity;
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0)
+            t = atomicAdd(&a.header->next[CLASS], 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntiles)
+            break;
+        const BatchTile tile = list[t];
+        const aes_msg_desc d = a.desc[tile.msg];
+        const int nr = desc_nr(d);
+        if (CLASS == 1) {
+            if (nr == 10) run_tile<10, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
+            else if (nr == 12) run_tile<12, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
+            else run_tile<14, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
+        } else if (d.mode == AES_MODE_ECB) {
+            if (nr == 10) run_tile<10, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, tile);
+            else if (nr == 12) run_tile<12, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, tile);
+            else run_tile<14, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, tile);
+        } else {
+            if (nr == 10) run_tile<10, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, tile);
+            else if (nr == 12) run_tile<12, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, tile);
+            else run_tile<14, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, tile);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t upload_tables_batch(const HostTables &t) { return upload_base_tables(t); }
+
+hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(keyexp_kernel, dim3((a.max_msgs + 255) / 256), dim3(256), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((batch_kernel<0, 2>), dim3(grid), dim3(1024), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((batch_kernel<1, 2>), dim3(grid), dim3(1024), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace aesgpu

@@ -1,0 +1,340 @@
+// Device-side building blocks shared by the buffer kernels and the batch
+// kernels: LDS table staging, table lookups, the AES rounds, 16-byte loads
+// and stores, and the loop that carries a range of blocks through the cipher.
+//
+// One thread carries BPT independent 16-byte blocks through all rounds; a
+// wave's 64 lanes hold 64 consecutive blocks per slot, so every global load
+// and store is one 16-byte-per-lane, fully coalesced access (1 KiB per wave).
+// The grid is persistent: a fixed number of workgroups sweeps the buffer, so
+// the round tables are staged into LDS once per workgroup and not once per
+// tile.
+//
+// A full round (SubBytes, ShiftRows, MixColumns, AddRoundKey; FIPS-197
+// sections 5.1.1 - 5.1.4) is computed per output column c as
+//     T0[s_c.b0] ^ T1[s_{c+1}.b1] ^ T2[s_{c+2}.b2] ^ T3[s_{c+3}.b3] ^ k_c
+// where s_c is column c as a little-endian word (row r in byte r) and Ti is
+// the table of row i: the column that MixColumns makes of S[x] placed in
+// row i (so T_i is T0 rotated left by 8i bits).  Decryption uses the
+// equivalent inverse cipher (FIPS-197 section 5.3.5): the same shape with
+// the inverse tables, ShiftRows taken the other way (s_{c-r}) and the
+// decryption key schedule.
+//
+// LDS layout.  A lookup by a random byte from 64 lanes would pile onto a few
+// LDS banks, so every table entry is stored once per bank: the copy a lane
+// reads always sits in that lane's own bank, and no two lanes of a
+// half-wave ever collide.  The byte address of entry x is built by ONE
+// v_perm_b32 from the state word (which supplies x as byte 1 of the
+// address) and a per-lane constant (which supplies the copy offset in byte 0
+// and the table bank in byte 2):
+//   layout T4X32: four tables, 32 copies;  addr = pair<<16 | x<<8 | (t&1)<<7 | (lane&31)<<2
+//   layout T2X64: two tables (T0, T1), 64 copies; addr = t<<16 | x<<8 | lane<<2,
+//                 and T2, T3 are T0, T1 rotated by 16 bits.
+// Both use 128 KiB.  Decryption adds the inverse S-box for the last round
+// (32 copies, 32 KiB at 0x20000), so a decryption workgroup uses all 160 KiB.
+// The last encryption round reads S[x] out of the round tables (byte 2 of
+// T0[x] and byte 3 of T1[x] are S[x]) and assembles the column with two
+// v_perm_b32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace aesgpu {
+
+// te0 | td0 | isw, 256 words each, uploaded from the host tables once per
+// device.  Each translation unit that includes this header has its own copy
+// and uploads it with upload_base_tables().
+static __device__ uint32_t g_base[768];
+
+namespace {
+
+constexpr uint32_t kTableWords = 32768;       // 128 KiB of round tables
+constexpr uint32_t kInvSboxWords = 8192;      // 32 KiB: inverse S-box, 32 copies
+constexpr uint32_t kInvSboxAddr = 0x20000;
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // a ^ b ^ c in one VALU op
+}
+
+__device__ __forceinline__ uint32_t rotl(uint32_t x, int n) {
+    return n == 0 ? x : (x << n) | (x >> (32 - n));
+}
+
+__device__ __forceinline__ uint32_t bswap(uint32_t x) {
+    return __builtin_amdgcn_perm(0u, x, 0x00010203u);
+}
+
+// Byte address of a table entry: byte 0 and byte 2 from the lane constant,
+// byte 1 = byte K of the state word, byte 3 = 0.
+template <int K>
+__device__ __forceinline__ uint32_t entry_addr(uint32_t w, uint32_t lane_const) {
+    return __builtin_amdgcn_perm(w, lane_const, 0x0C010400u | (uint32_t(K) << 8));
+}
+
+__device__ __forceinline__ uint32_t lds_word(const uint32_t *lds, uint32_t byte_addr) {
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + byte_addr);
+}
+
+struct LaneConsts {
+    uint32_t t[4];   // per physical table
+    uint32_t isb;    // inverse S-box (address is built shifted left by one)
+};
+
+template <int LAYOUT>
+__device__ __forceinline__ LaneConsts lane_consts(uint32_t lane) {
+    LaneConsts c;
+    if (LAYOUT == LAYOUT_T4X32) {
+        for (int t = 0; t < 4; t++)
+            c.t[t] = ((lane & 31u) << 2) | (uint32_t(t & 1) << 7) | (uint32_t(t >> 1) << 8);
+    } else {
+        for (int t = 0; t < 4; t++)
+            c.t[t] = (lane << 2) | (uint32_t(t & 1) << 8);
+    }
+    // (x<<8 | (lane&31)<<3 | 0x40000) >> 1 = 0x20000 | x<<7 | (lane&31)<<2
+    c.isb = ((lane & 31u) << 3) | (4u << 8);
+    return c;
+}
+
+// Logical table T (0..3) looked up with byte K of w.
+template <int LAYOUT, int T, int K>
+__device__ __forceinline__ uint32_t tl(const uint32_t *lds, const LaneConsts &lc, uint32_t w) {
+    if (LAYOUT == LAYOUT_T4X32) {
+        return lds_word(lds, entry_addr<K>(w, lc.t[T]));
+    } else {
+        uint32_t v = lds_word(lds, entry_addr<K>(w, lc.t[T & 1]));
+        return (T >> 1) ? rotl(v, 16) : v;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t inv_sbox_word(const uint32_t *lds, const LaneConsts &lc, uint32_t w) {
+    return lds_word(lds, entry_addr<K>(w, lc.isb) >> 1);
+}
+
+// One full round for one output column: the four bytes come from columns
+// a, b, c, d (already ShiftRows-selected by the caller).
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t round_col(const uint32_t *lds, const LaneConsts &lc, uint32_t a,
+                                              uint32_t b, uint32_t c, uint32_t d, uint32_t k) {
+    if (LAYOUT == LAYOUT_T4X32) {
+        return xor3(tl<LAYOUT, 0, 0>(lds, lc, a), tl<LAYOUT, 1, 1>(lds, lc, b),
+                    xor3(tl<LAYOUT, 2, 2>(lds, lc, c), tl<LAYOUT, 3, 3>(lds, lc, d), k));
+    } else {
+        // T2 ^ T3 = rotl16(T0' ^ T1'): one rotation per column
+        uint32_t hi = lds_word(lds, entry_addr<2>(c, lc.t[0])) ^ lds_word(lds, entry_addr<3>(d, lc.t[1]));
+        return xor3(tl<LAYOUT, 0, 0>(lds, lc, a), tl<LAYOUT, 1, 1>(lds, lc, b), k) ^ rotl(hi, 16);
+    }
+}
+
+// Last encryption round for one column: S[a.b0] | S[b.b1]<<8 | S[c.b2]<<16 | S[d.b3]<<24, ^ k.
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t final_enc_col(const uint32_t *lds, const LaneConsts &lc, uint32_t a,
+                                                  uint32_t b, uint32_t c, uint32_t d, uint32_t k) {
+    // physical tables 0 and 1 are T0 and T1 in both layouts
+    uint32_t ea = lds_word(lds, entry_addr<0>(a, lc.t[0]));
+    uint32_t eb = lds_word(lds, entry_addr<1>(b, lc.t[1]));
+    uint32_t ec = lds_word(lds, entry_addr<2>(c, lc.t[0]));
+    uint32_t ed = lds_word(lds, entry_addr<3>(d, lc.t[1]));
+    uint32_t lo = __builtin_amdgcn_perm(ea, eb, 0x0C0C0306u);  // S from byte 2 of T0, byte 3 of T1
+    uint32_t hi = __builtin_amdgcn_perm(ec, ed, 0x03060C0Cu);
+    return xor3(lo, hi, k);
+}
+
+__device__ __forceinline__ uint32_t final_dec_col(const uint32_t *lds, const LaneConsts &lc, uint32_t a,
+                                                  uint32_t b, uint32_t c, uint32_t d, uint32_t k) {
+    uint32_t ea = inv_sbox_word<0>(lds, lc, a);
+    uint32_t eb = inv_sbox_word<1>(lds, lc, b);
+    uint32_t ec = inv_sbox_word<2>(lds, lc, c);
+    uint32_t ed = inv_sbox_word<3>(lds, lc, d);
+    uint32_t lo = __builtin_amdgcn_perm(ea, eb, 0x0C0C0104u);
+    uint32_t hi = __builtin_amdgcn_perm(ec, ed, 0x03060C0Cu);
+    return xor3(lo, hi, k);
+}
+
+template <int NR, int DIR, int LAYOUT, int BPT>
+__device__ __forceinline__ void rounds(uint32_t (&s)[BPT][4], const uint32_t *lds, const LaneConsts &lc,
+                                       const uint32_t *rk, int first_round) {
+#pragma unroll
+    for (int r = 1; r < NR; r++) {
+        if (r < first_round)
+            continue;
+        const uint32_t k0 = rk[4 * r], k1 = rk[4 * r + 1], k2 = rk[4 * r + 2], k3 = rk[4 * r + 3];
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            const uint32_t a0 = s[i][0], a1 = s[i][1], a2 = s[i][2], a3 = s[i][3];
+            if (DIR == DIR_ENC) {
+                s[i][0] = round_col<LAYOUT>(lds, lc, a0, a1, a2, a3, k0);
+                s[i][1] = round_col<LAYOUT>(lds, lc, a1, a2, a3, a0, k1);
+                s[i][2] = round_col<LAYOUT>(lds, lc, a2, a3, a0, a1, k2);
+                s[i][3] = round_col<LAYOUT>(lds, lc, a3, a0, a1, a2, k3);
+            } else {
+                s[i][0] = round_col<LAYOUT>(lds, lc, a0, a3, a2, a1, k0);
+                s[i][1] = round_col<LAYOUT>(lds, lc, a1, a0, a3, a2, k1);
+                s[i][2] = round_col<LAYOUT>(lds, lc, a2, a1, a0, a3, k2);
+                s[i][3] = round_col<LAYOUT>(lds, lc, a3, a2, a1, a0, k3);
+            }
+        }
+    }
+    const uint32_t k0 = rk[4 * NR], k1 = rk[4 * NR + 1], k2 = rk[4 * NR + 2], k3 = rk[4 * NR + 3];
+#pragma unroll
+    for (int i = 0; i < BPT; i++) {
+        const uint32_t a0 = s[i][0], a1 = s[i][1], a2 = s[i][2], a3 = s[i][3];
+        if (DIR == DIR_ENC) {
+            s[i][0] = final_enc_col<LAYOUT>(lds, lc, a0, a1, a2, a3, k0);
+            s[i][1] = final_enc_col<LAYOUT>(lds, lc, a1, a2, a3, a0, k1);
+            s[i][2] = final_enc_col<LAYOUT>(lds, lc, a2, a3, a0, a1, k2);
+            s[i][3] = final_enc_col<LAYOUT>(lds, lc, a3, a0, a1, a2, k3);
+        } else {
+            s[i][0] = final_dec_col(lds, lc, a0, a3, a2, a1, k0);
+            s[i][1] = final_dec_col(lds, lc, a1, a0, a3, a2, k1);
+            s[i][2] = final_dec_col(lds, lc, a2, a1, a0, a3, k2);
+            s[i][3] = final_dec_col(lds, lc, a3, a2, a1, a0, k3);
+        }
+    }
+}
+
+template <int LAYOUT, int DIR>
+__device__ __forceinline__ void stage_tables(uint32_t *lds) {
+    const uint32_t *base = g_base + (DIR == DIR_ENC ? 0 : 256);
+    for (uint32_t i = threadIdx.x; i < kTableWords; i += blockDim.x) {
+        // word index i = table<<14 | x<<6 | copy (T2X64) or
+        //                pair<<14 | x<<6 | (t&1)<<5 | copy (T4X32)
+        const uint32_t x = (i >> 6) & 255u;
+        const uint32_t t = (LAYOUT == LAYOUT_T4X32) ? (((i >> 14) << 1) | ((i >> 5) & 1u)) : (i >> 14);
+        lds[i] = rotl(base[x], 8 * int(t));
+    }
+    if (DIR == DIR_DEC) {
+        for (uint32_t i = threadIdx.x; i < kInvSboxWords; i += blockDim.x)
+            lds[(kInvSboxAddr >> 2) + i] = g_base[512 + (i >> 5)];
+    }
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32x4 vec4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    u32x4 v;
+    v.x = a; v.y = b; v.z = c; v.w = d;
+    return v;
+}
+
+// Streaming 16-byte accesses: every byte is touched exactly once, so they are
+// marked non-temporal to keep them from evicting the (reused) table lines.
+__device__ __forceinline__ u32x4 load16(const uint8_t *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+}
+
+__device__ __forceinline__ void store16(uint8_t *p, u32x4 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+}
+
+// The partial final block of a CTR message, one byte at a time.
+__device__ __forceinline__ u32x4 load_tail(const uint8_t *p, uint32_t n) {
+    uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (uint32_t b = 0; b < 16; b++)
+        if (b < n)
+            w[b >> 2] |= uint32_t(p[b]) << (8 * (b & 3));
+    return vec4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ void store_tail(uint8_t *p, u32x4 v, uint32_t n) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (uint32_t b = 0; b < 16; b++)
+        if (b < n)
+            p[b] = uint8_t(w[b >> 2] >> (8 * (b & 3)));
+}
+
+// Carries blocks j = base + 64*i + lane (i < BPT) through the cipher for
+// every wave-uniform base in [begin, end) stepping by `step`; only blocks
+// below `limit` exist.  Blocks are 16-byte units of a message of `nbytes`
+// bytes at `in` / `out`; in CTR a final partial block is read and written
+// byte by byte.  `rk` points at the round keys in the order the rounds use
+// them (wave-uniform, so they are read into scalar registers); `ctr` holds
+// the nonce words 0..2 and the initial counter value c0.
+template <int NR, int MODE, int DIR, int LAYOUT, int BPT>
+__device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneConsts &lc,
+                                               const uint32_t *rk, const uint32_t *ctr,
+                                               const uint8_t *in, uint8_t *out, uint64_t nbytes,
+                                               uint64_t begin, uint64_t limit, uint64_t step) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t nfull = nbytes >> 4;
+    const uint32_t tail = uint32_t(nbytes & 15u);
+
+    // CTR: after the first AddRoundKey, columns 0..2 of every counter block
+    // are the same (the nonce), so 12 of round 1's 16 lookups are the same
+    // for every block; they are summed once here.
+    uint32_t pre0 = 0, pre1 = 0, pre2 = 0, pre3 = 0;
+    if (MODE == MODE_CTR) {
+        const uint32_t u0 = ctr[0] ^ rk[0], u1 = ctr[1] ^ rk[1], u2 = ctr[2] ^ rk[2];
+        pre0 = tl<LAYOUT, 0, 0>(lds, lc, u0) ^ tl<LAYOUT, 1, 1>(lds, lc, u1) ^ tl<LAYOUT, 2, 2>(lds, lc, u2) ^ rk[4];
+        pre1 = tl<LAYOUT, 0, 0>(lds, lc, u1) ^ tl<LAYOUT, 1, 1>(lds, lc, u2) ^ tl<LAYOUT, 3, 3>(lds, lc, u0) ^ rk[5];
+        pre2 = tl<LAYOUT, 0, 0>(lds, lc, u2) ^ tl<LAYOUT, 2, 2>(lds, lc, u0) ^ tl<LAYOUT, 3, 3>(lds, lc, u1) ^ rk[6];
+        pre3 = tl<LAYOUT, 1, 1>(lds, lc, u0) ^ tl<LAYOUT, 2, 2>(lds, lc, u1) ^ tl<LAYOUT, 3, 3>(lds, lc, u2) ^ rk[7];
+    }
+    const uint32_t c0 = MODE == MODE_CTR ? ctr[3] : 0u;
+
+    for (uint64_t base = begin; base < limit; base += step) {
+        uint32_t s[BPT][4];
+        u32x4 x[BPT];
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            const uint64_t j = base + uint64_t(i) * 64u + lane;
+            x[i] = vec4(0, 0, 0, 0);
+            if (j < nfull && j < limit)
+                x[i] = load16(in + 16 * j);
+            else if (MODE == MODE_CTR && j == nfull && tail && j < limit)
+                x[i] = load_tail(in + 16 * j, tail);
+            if (MODE == MODE_ECB) {
+                s[i][0] = x[i].x ^ rk[0];
+                s[i][1] = x[i].y ^ rk[1];
+                s[i][2] = x[i].z ^ rk[2];
+                s[i][3] = x[i].w ^ rk[3];
+            } else {
+                // counter block j: nonce || big-endian (c0 + j) mod 2^32;
+                // round 1 needs only the four lookups on column 3.
+                const uint32_t v3 = bswap(c0 + uint32_t(j)) ^ rk[3];
+                s[i][0] = pre0 ^ tl<LAYOUT, 3, 3>(lds, lc, v3);
+                s[i][1] = pre1 ^ tl<LAYOUT, 2, 2>(lds, lc, v3);
+                s[i][2] = pre2 ^ tl<LAYOUT, 1, 1>(lds, lc, v3);
+                s[i][3] = pre3 ^ tl<LAYOUT, 0, 0>(lds, lc, v3);
+            }
+        }
+        rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, MODE == MODE_CTR ? 2 : 1);
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            const uint64_t j = base + uint64_t(i) * 64u + lane;
+            u32x4 o;
+            if (MODE == MODE_ECB)
+                o = vec4(s[i][0], s[i][1], s[i][2], s[i][3]);
+            else
+                o = vec4(s[i][0] ^ x[i].x, s[i][1] ^ x[i].y, s[i][2] ^ x[i].z, s[i][3] ^ x[i].w);
+            if (j < nfull && j < limit)
+                store16(out + 16 * j, o);
+            else if (MODE == MODE_CTR && j == nfull && tail && j < limit)
+                store_tail(out + 16 * j, o, tail);
+        }
+    }
+}
+
+template <int DIR>
+constexpr uint32_t lds_words() {
+    return DIR == DIR_DEC ? kTableWords + kInvSboxWords : kTableWords;
+}
+
+}  // namespace
+
+// Copies the host-built base tables into this translation unit's g_base on
+// the current device.
+static inline hipError_t upload_base_tables(const HostTables &t) {
+    uint32_t words[768];
+    for (int i = 0; i < 256; i++) {
+        words[i] = t.te0[i];
+        words[256 + i] = t.td0[i];
+        words[512 + i] = t.isw[i];
+    }
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_base), words, sizeof(words), 0, hipMemcpyHostToDevice);
+}
+
+}  // namespace aesgpu

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "aesgpu.h"
+
 namespace aesgpu {
 
 // ---- host arithmetic (tables.cpp) ----------------------------------------
@@ -52,5 +54,45 @@ hipError_t upload_tables(const HostTables &t);
 hipError_t launch_cipher(int nr, int mode, int dir, const LaunchCfg &cfg, const CipherArgs &a,
                          hipStream_t stream);
 hipError_t launch_copy(const void *in, void *out, uint64_t nbytes, int grid, hipStream_t stream);
+
+// ---- batches (batch_kernels.hip) -------------------------------------------
+// Workspace = header | key schedules (max_msgs slots) | tiles[2][capacity].
+struct BatchHeader {
+    uint32_t ntiles[2];   // forward list (ECB encrypt, CTR), inverse list (ECB decrypt)
+    uint32_t next[2];     // next tile to hand out, per list
+    uint32_t rejected;    // messages whose descriptor failed the checks
+    uint32_t overflow;    // 1 if the tiles did not fit the workspace
+    uint32_t pad[58];
+};
+static_assert(sizeof(BatchHeader) == 256, "header is one 256-byte line");
+
+struct BatchTile {
+    uint32_t msg;     // message index
+    uint32_t count;   // blocks in this tile
+    uint64_t first;   // first block of the tile within its message
+};
+
+constexpr int kKeySlotWords = 128;  // encryption schedule at 0, decryption schedule at 64
+
+struct BatchKArgs {
+    const aes_msg_desc *desc;
+    int nmsg;
+    const int *d_nmsg;
+    int max_msgs;
+    const uint8_t *keys;
+    int nkeys;
+    const void *in_base;
+    uint64_t in_bytes;
+    void *out_base;
+    uint64_t out_bytes;
+    BatchHeader *header;
+    uint32_t *keytab;
+    BatchTile *tiles;
+    uint64_t tile_capacity;
+    uint32_t tile_blocks;
+};
+
+hipError_t upload_tables_batch(const HostTables &t);
+hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream);
 
 }  // namespace aesgpu

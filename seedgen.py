@@ -115,3 +115,30 @@ def nonce(master, index):
     """A 16-byte initial counter block: 12 random nonce bytes, counter 0."""
     n = bytes_np(stream_seed(master, TAG_NONCE, index), 12)
     return np.concatenate([n, np.zeros(4, np.uint8)])
+
+
+# --- workload shapes -------------------------------------------------------
+def log_uniform_lengths(rng, n, lo, hi, multiple=1):
+    """n lengths with log2(length) uniform between log2(lo) and log2(hi),
+    rounded to the nearest multiple of `multiple` (at least `multiple`)."""
+    u = rng.random(n)
+    raw = lo * (hi / lo) ** u
+    out = np.maximum(np.rint(raw / multiple), 1).astype(np.int64) * multiple
+    return np.minimum(out, hi)
+
+
+def ragged_batch(master, n, lo=16, hi=1 << 24, multiple=16):
+    """The ragged multi-message workload: n messages with lengths
+    log-uniform in [lo, hi] (multiples of 16 by default), AES-128 or AES-256
+    with probability 1/2 each.  Returns (lengths, keybits, keys[n, 32],
+    nonces[n, 16]); key and nonce m come from the KEY / NONCE streams with
+    index m."""
+    rng = np.random.default_rng(master)
+    lengths = log_uniform_lengths(rng, n, lo, hi, multiple)
+    keybits = np.where(rng.random(n) < 0.5, 128, 256)
+    keys = np.zeros((n, 32), np.uint8)
+    nonces = np.zeros((n, 16), np.uint8)
+    for m in range(n):
+        keys[m, :keybits[m] // 8] = key(master, m, int(keybits[m]))
+        nonces[m] = nonce(master, m)
+    return lengths, keybits, keys, nonces

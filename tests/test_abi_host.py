@@ -95,3 +95,55 @@ def test_launch_config_validation(A):
         assert e.value.code == A.AES_E_ARG
     A.aes_set_launch({"layout": 1, "blocks_per_thread": 4, "wg_size": 512, "grid": 3})
     A.aes_set_launch(None)
+
+
+def test_batch_workspace_size(A):
+    n = A.aes_batch_workspace_size(10, 1000, 100)
+    # header + 10 key slots of 512 bytes + two tile lists of (10 + 10) 16-byte tiles
+    assert n == 256 + 10 * 512 + 2 * 20 * 16
+    assert A.aes_batch_workspace_size(10, 1000, 0) == 256 + 10 * 512 + 2 * (10 + 1) * 16
+    for bad in ((0, 10, 0), (5, 10, -1)):
+        with pytest.raises(A.AESError) as e:
+            A.aes_batch_workspace_size(*bad)
+        assert e.value.code == A.AES_E_ARG
+    with pytest.raises(A.AESError) as e:
+        A.aes_batch_workspace_size(1, 1 << 62, 1)
+    assert e.value.code == A.AES_E_LENGTH
+
+
+def test_batch_argument_checks(A):
+    ws = A.aes_batch_workspace_size(4, 64, 0)
+
+    def batch(**kw):
+        f = dict(desc=0x100000, nmsg=4, d_nmsg=None, keys=0x200000, nkeys=4,
+                 in_base=0x300000, in_bytes=4096, out_base=0x400000, out_bytes=4096,
+                 workspace=0x500000, workspace_bytes=ws, max_msgs=4, max_total_blocks=64,
+                 tile_blocks=0)
+        f.update(kw)
+        return A.aes_batch(**f)
+
+    def code(b):
+        with pytest.raises(A.AESError) as e:
+            A.aes_batch_run(b, stream=0)
+        return e.value.code
+
+    assert code(batch(desc=None)) == A.AES_E_NULL
+    assert code(batch(workspace=None)) == A.AES_E_NULL
+    assert code(batch(nmsg=5)) == A.AES_E_ARG
+    assert code(batch(max_msgs=0, nmsg=0)) == A.AES_E_ARG
+    assert code(batch(nkeys=0)) == A.AES_E_ARG
+    assert code(batch(in_base=0x300008)) == A.AES_E_ALIGN
+    assert code(batch(workspace=0x500010)) == A.AES_E_ALIGN
+    assert code(batch(workspace_bytes=ws - 1)) == A.AES_E_LENGTH
+
+
+def test_descriptor_layout(A):
+    d = A.make_descs([16, 17, 0, 100], keybits=[128, 192, 256, 128], mode=["ecb", "ctr", "ctr", "ecb"],
+                     decrypt=[0, 1, 0, 1])
+    assert d.dtype.itemsize == 48
+    assert list(d["in_off"]) == [0, 16, 48, 48]
+    assert list(d["keybits_code"]) == [0, 1, 2, 0]
+    assert list(d["mode"]) == [0, 1, 1, 0]
+    raw = d.view(np.uint8).reshape(4, 48)
+    assert raw[1, 8:16].view("<u8")[0] == 16       # out_off follows in_off
+    assert raw[1, 28] == 1                          # keybits_code at byte 28

@@ -1,0 +1,192 @@
+"""The batched path (on-device key expansion, tile plan, persistent kernels,
+graph replay) against the oracle and against the single-buffer path, bit for
+bit, through the C ABI."""
+import numpy as np
+import pytest
+
+import seedgen
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SENTINEL = 0xA5
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1403_7295_amd import aesgpu
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return aesgpu
+
+
+@pytest.fixture(scope="module")
+def O():
+    return ref.default()
+
+
+def mixed_messages(A, n, seed, max_len=1 << 16, min_len=0, mode=None, decrypt=None):
+    """n messages of every kind: ECB encrypt/decrypt and CTR, 128/192/256-bit
+    keys, lengths log-uniform in [1, max_len] (ECB rounded up to whole
+    blocks), a few empty ones (unless min_len > 0), counters that wrap."""
+    rng = np.random.default_rng(seed)
+    lens = np.maximum(seedgen.log_uniform_lengths(rng, n, 1, max_len), min_len)
+    mode = rng.integers(0, 2, n) if mode is None else np.full(n, mode)
+    decrypt = rng.integers(0, 2, n) if decrypt is None else np.full(n, decrypt)
+    keybits = rng.choice([128, 192, 256], n)
+    lens = np.where(mode == 0, (lens + 15) // 16 * 16, lens)
+    if min_len == 0:
+        lens[rng.choice(n, 3, replace=False)] = 0
+    keys = np.zeros((n, 32), np.uint8)
+    ctr0 = np.zeros((n, 16), np.uint8)
+    for m in range(n):
+        keys[m, :keybits[m] // 8] = seedgen.key(seed, m, int(keybits[m]))
+        ctr0[m] = seedgen.nonce(seed, m)
+        if m % 7 == 0:
+            ctr0[m, 12:16] = [0xFF, 0xFF, 0xFF, 0xF8]   # wraps inside the message
+    descs = A.make_descs(lens, keybits=keybits, mode=mode, decrypt=decrypt, ctr0=ctr0)
+    return descs, keys
+
+
+def buffers(descs, seed):
+    end = int((descs["in_off"] + descs["nbytes"]).max()) if len(descs) else 0
+    total = (end + 15) // 16 * 16 + 16
+    x = seedgen.data_np(seed, 99, total)
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.full_like(xd, SENTINEL)
+    return x, xd, yd
+
+
+def oracle_message(O, d, key, x):
+    bits = 128 + 64 * int(d["keybits_code"])
+    rk, nr = O.expand_key(key[:bits // 8])
+    if d["mode"] == 0:
+        return O.ecb_decrypt(rk, nr, x) if d["decrypt"] else O.ecb_encrypt(rk, nr, x)
+    return O.ctr(rk, nr, d["ctr0"], x)
+
+
+def check_against_oracle(O, descs, keys, x, y):
+    for m, d in enumerate(descs):
+        n = int(d["nbytes"])
+        i, o = int(d["in_off"]), int(d["out_off"])
+        want = oracle_message(O, d, keys[int(d["key_idx"])], x[i:i + n])
+        if not np.array_equal(y[o:o + n], want):
+            raise AssertionError("message %d (%s) differs" % (m, d))
+
+
+def test_batch_matches_oracle(A, O):
+    descs, keys = mixed_messages(A, 300, 41)
+    x, xd, yd = buffers(descs, 41)
+    b = A.Batch(descs, keys, xd, yd)
+    b.run()
+    tiles, rejected = b.query()
+    assert rejected == 0 and tiles > 0
+    check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
+
+
+@pytest.mark.parametrize("tile_blocks", [1, 64, 777, 8192])
+def test_tile_size_and_order_do_not_matter(A, tile_blocks):
+    descs, keys = mixed_messages(A, 120, 42, max_len=1 << 18)
+    x, xd, y0 = buffers(descs, 42)
+    A.Batch(descs, keys, xd, y0).run()
+    y1 = torch.full_like(y0, SENTINEL)
+    perm = np.random.default_rng(tile_blocks).permutation(len(descs))
+    A.Batch(descs[perm], keys, xd, y1, tile_blocks=tile_blocks).run()
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+
+
+def test_in_place(A, O):
+    descs, keys = mixed_messages(A, 50, 43)
+    x, xd, _ = buffers(descs, 43)
+    A.Batch(descs, keys, xd, xd).run()
+    check_against_oracle(O, descs, keys, x, xd.cpu().numpy())
+
+
+def test_graph_replay_with_rewritten_descriptors(A, O):
+    descs, keys = mixed_messages(A, 80, 44)
+    x, xd, yd = buffers(descs, 44)
+    b = A.Batch(descs, keys, xd, yd, max_msgs=80)
+    for rep in range(3):
+        yd.fill_(SENTINEL)
+        b.launch_graph()
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
+    # fewer messages, new keys: the graph reads the count from the device
+    descs2, keys2 = mixed_messages(A, 30, 45)
+    descs2["in_off"] = descs["in_off"][:30]
+    descs2["out_off"] = descs["out_off"][:30]
+    descs2["nbytes"] = np.minimum(descs2["nbytes"], descs["nbytes"][:30])
+    descs2["nbytes"] = np.where(descs2["mode"] == 0, descs2["nbytes"] // 16 * 16, descs2["nbytes"])
+    b.set_descs(descs2, keys2)
+    yd.fill_(SENTINEL)
+    b.launch_graph()
+    torch.cuda.synchronize()
+    check_against_oracle(O, descs2, keys2, x, yd.cpu().numpy())
+    b.close()
+
+
+def test_invalid_descriptors_are_skipped(A, O):
+    descs, keys = mixed_messages(A, 40, 46, min_len=32)
+    bad = descs.copy()
+    bad["keybits_code"][0] = 3                     # no such key size
+    bad["mode"][1] = 0
+    bad["nbytes"][1] = 17                          # ECB, not whole blocks
+    bad["in_off"][2] += 8                          # misaligned
+    bad["key_idx"][3] = len(keys)                  # no such key
+    x, xd, yd = buffers(descs, 46)
+    bad["nbytes"][4] = xd.numel() + 16             # outside the buffers
+    b = A.Batch(bad, keys, xd, yd)
+    b.run()
+    tiles, rejected = b.query()
+    assert rejected == 5
+    y = yd.cpu().numpy()
+    for m in range(5):
+        o, n = int(descs["out_off"][m]), int(descs["nbytes"][m])
+        assert (y[o:o + n] == SENTINEL).all(), "rejected message %d was written" % m
+    check_against_oracle(O, descs[5:], keys, x, y)
+
+
+def test_tile_overflow_is_reported(A):
+    descs, keys = mixed_messages(A, 20, 47, max_len=4096, min_len=4096, mode=0, decrypt=0)
+    x, xd, yd = buffers(descs, 47)
+    # the caller under-declares the batch: 20 messages of 256 blocks in tiles of
+    # 64 blocks need 80 tiles, the workspace has room for 20 + 1
+    b = A.Batch(descs, keys, xd, yd, tile_blocks=64, max_total_blocks=64)
+    b.run()
+    with pytest.raises(A.AESError) as e:
+        b.query()
+    assert e.value.code == A.AES_E_LENGTH
+    assert (yd.cpu().numpy() == SENTINEL).all()
+
+
+def test_batch_equals_plain_on_ragged_workload(A, O):
+    """The ragged multi-message workload at full size (10,000 messages,
+    log-uniform 16 B .. 16 MiB, half AES-128, half AES-256, ECB encrypt):
+    batched output equals per-message single-buffer launches byte for byte,
+    and sampled blocks equal the oracle."""
+    lens, keybits, keys, _ = seedgen.ragged_batch(4, 10000)
+    descs = A.make_descs(lens, keybits=keybits, mode="ecb")
+    total = int(lens.sum())
+    x = seedgen.data_torch(4, 0, total, "cuda")
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    b = A.Batch(descs, keys, x, y)
+    b.launch_graph()
+    for m in range(len(descs)):
+        o, n = int(descs["in_off"][m]), int(lens[m])
+        rk, nr = A.aes_expand_key(keys[m][:keybits[m] // 8])
+        A.aes_encrypt(x[o:o + n], z[o:o + n], n, rk, nr, "ecb")
+    torch.cuda.synchronize()
+    assert torch.equal(y, z)
+    rng = np.random.default_rng(5)
+    for m in rng.choice(len(descs), 300, replace=False):
+        o, nblk = int(descs["in_off"][m]), int(lens[m]) // 16
+        j = int(rng.integers(0, nblk))
+        rk, nr = O.expand_key(keys[m][:keybits[m] // 8])
+        want = O.encrypt_block(rk, nr, seedgen.data_np(4, 0, 16, offset=o + 16 * j))
+        assert np.array_equal(y[o + 16 * j:o + 16 * j + 16].cpu().numpy(), want), (m, j)
+    b.close()
