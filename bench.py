@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=32)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -154,6 +156,49 @@ def bench_batched(torch, A, dev, stream, reps=5):
             "batched_vs_plain": round((total * reps / wall) / (total * 2 / pwall), 3)}
 
 
+def bench_served(torch, A, dev, capacity_gbs, nreq, warm=1000,
+                 loads=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
+    """The served workload: Poisson arrivals of CTR requests (70 % encrypt,
+    30 % decrypt), sizes log-uniform in [64 B, 64 MiB], AES-128/256 half and
+    half, each with its own key and nonce, admitted against an 8 GiB HBM
+    budget on 4 streams.  The arrival rate is swept over offered loads
+    rho = rate x mean size / capacity, capacity being the plain-kernel CTR
+    rate measured above.  Latency runs from arrival to completion seen by the
+    loop; the first `warm` requests of each run are excluded."""
+    import numpy as np
+    lo, hi = 64, 1 << 26
+    mean = (hi - lo) / np.log(hi / lo)
+    f, keys = seedgen.served_requests(5, nreq + warm, rate=1.0, lo=lo, hi=hi)
+    base = np.zeros(nreq + warm, A.REQUEST_DTYPE)
+    for k, v in f.items():
+        base[k] = v
+    cfg = A.serve_cfg(streams=4, budget_bytes=8 << 30, max_batch_msgs=4096)
+    srv = A.Server(keys, cfg, device=dev)
+    points = []
+    for rho in loads:
+        rate = rho * capacity_gbs * 1e9 / mean
+        r = base.copy()
+        r["arrival_s"] = base["arrival_s"] / rate
+        res, st = srv.run(r)
+        m = res[warm:]
+        rm = r[warm:]
+        t_first = float(rm["arrival_s"][0])
+        t_last = float((rm["arrival_s"] + m["latency_s"]).max())
+        points.append({"offered_load": rho, "arrival_rate_per_s": round(rate, 1),
+                       "offered_GB/s": round(rho * capacity_gbs, 1),
+                       "completed_GB/s": round(float(rm["nbytes"].sum()) / (t_last - t_first) / 1e9, 1),
+                       "p50_ms": round(float(np.percentile(m["latency_s"], 50)) * 1e3, 3),
+                       "p99_ms": round(float(np.percentile(m["latency_s"], 99)) * 1e3, 3),
+                       "p50_admit_wait_ms": round(float(np.percentile(m["admit_s"], 50)) * 1e3, 3),
+                       "launches": st["launches"], "max_inflight_reqs": st["max_inflight_reqs"]})
+    del srv
+    torch.cuda.empty_cache()
+    return {"workload": "Poisson CTR requests, 70/30 encrypt/decrypt, log-uniform 64 B..64 MiB, "
+                        "AES-128/256 50/50, per-request key and nonce, 8 GiB HBM budget, 4 streams",
+            "requests_per_point": nreq, "warmup_requests": warm,
+            "capacity_GB/s": round(capacity_gbs, 1), "points": points}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -242,6 +287,13 @@ def main():
 
     if not args.no_batched:
         out["batched"] = bench_batched(torch, A, dev, stream)
+
+    if not args.no_served:
+        cap = None
+        if "secondary" in out:
+            a, b = out["secondary"]["aes128_ctr_enc"]["GB/s"], out["secondary"]["aes256_ctr_enc"]["GB/s"]
+            cap = 2.0 / (1.0 / a + 1.0 / b)     # half the bytes at each key size
+        out["served"] = bench_served(torch, A, dev, cap or 1000.0, args.served_requests)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_mib << 20)

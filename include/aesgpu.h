@@ -227,6 +227,95 @@ int aes_batch_graph_create(const aes_batch *b, void **graph);
 int aes_batch_graph_launch(void *graph, void *stream);
 int aes_batch_graph_destroy(void *graph);
 
+/* ---------------------------------------------------------------------- */
+/* Serving: a request loop with admission by HBM budget and continuous     */
+/* batching over several streams.                                         */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * One request.  It arrives arrival_s seconds after the run starts.  Its
+ * payload is nbytes bytes of the SplitMix64 stream with seed payload_seed
+ * (word i = mix64(seed + (i+1) * 0x9E3779B97F4A7C15), bytes little-endian),
+ * written on the device when the request is launched: the synthetic stand-in
+ * for data arriving over the network.  Key, mode, direction and counter are
+ * as in aes_msg_desc.
+ */
+typedef struct {
+    double arrival_s;
+    uint64_t nbytes;
+    uint64_t payload_seed;
+    uint32_t key_idx;
+    uint8_t keybits_code;
+    uint8_t mode;
+    uint8_t decrypt;
+    uint8_t reserved;
+    uint8_t ctr0[16];
+} aes_request;
+
+/*
+ * streams          batches in flight at once (1..16), one HIP stream each.
+ * budget_bytes     admission budget: the input and output buffers of all
+ *                  requests admitted and not yet finished (each rounded up to
+ *                  256 bytes) never exceed it.  It is also the size of the
+ *                  device arena they are carved from.  A request that alone
+ *                  exceeds it is rejected (status AES_E_LENGTH), never queued.
+ * max_batch_msgs   requests per launch (1..65536).
+ * tile_blocks      as for aes_batch (0 = library choice).
+ * timeout_s        the run fails with AES_E_DEVICE if nothing completes for
+ *                  this long while work is in flight (0 = 60 s).
+ * simulate_gbps    > 0: no device is touched; every launch is taken to finish
+ *                  after its bytes at this rate plus 20 us, so the admission
+ *                  and batching logic can run without a GPU.  d_keys and
+ *                  d_scratch are then ignored and may be NULL.
+ */
+typedef struct {
+    int streams;
+    uint64_t budget_bytes;
+    int max_batch_msgs;
+    int tile_blocks;
+    double timeout_s;
+    double simulate_gbps;
+} aes_serve_cfg;
+
+typedef struct {
+    double latency_s;   /* completion seen by the loop minus arrival */
+    double admit_s;     /* admission time minus arrival (queueing for budget) */
+    uint64_t in_off;    /* input and output location in the arena */
+    uint64_t out_off;
+    int status;         /* AES_OK, or AES_E_LENGTH if larger than the budget */
+    int launch;         /* sequence number of the launch it ran in */
+} aes_request_result;
+
+typedef struct {
+    double span_s;            /* first arrival to last completion */
+    uint64_t bytes_done;      /* payload bytes of completed requests */
+    int completed;
+    int rejected;
+    int launches;
+    int max_inflight_reqs;    /* most requests admitted at once */
+    uint64_t max_inflight_bytes;
+} aes_serve_stats;
+
+/* Device scratch bytes aes_serve_run needs for cfg (the arena plus per-stream
+ * descriptor tables and batch workspaces).  Host only. */
+int aes_serve_scratch_size(const aes_serve_cfg *cfg, size_t *bytes);
+
+/*
+ * Run the requests (sorted by arrival_s) to completion on the current
+ * device.  The loop, on one host thread: finish launches whose events have
+ * completed (their requests' latencies are taken then and their memory
+ * returns to the budget); admit arrived requests in arrival order while the
+ * budget has room; when a stream is free, launch everything admitted and not
+ * yet launched as one batch (payload fill, Key Expansion, tile plan,
+ * persistent cipher kernels) on it.  Batches on different streams overlap on
+ * the device.  results[i] describes reqs[i].  d_scratch (256-byte aligned)
+ * holds aes_serve_scratch_size(cfg) bytes; the results stay in its arena at
+ * out_off until the next call.
+ */
+int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int nkeys,
+                  void *d_scratch, size_t scratch_bytes, const aes_serve_cfg *cfg,
+                  aes_request_result *results, aes_serve_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,10 @@ _SIGNATURES = {
     "aes_batch_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "aes_batch_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "aes_batch_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "aes_serve_scratch_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "aes_serve_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -90,6 +94,31 @@ class aes_batch(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("max_msgs", ctypes.c_int), ("max_total_blocks", ctypes.c_uint64),
                 ("tile_blocks", ctypes.c_int)]
+
+
+# aes_request and aes_request_result, as numpy records
+REQUEST_DTYPE = np.dtype([("arrival_s", "<f8"), ("nbytes", "<u8"), ("payload_seed", "<u8"),
+                          ("key_idx", "<u4"), ("keybits_code", "u1"), ("mode", "u1"),
+                          ("decrypt", "u1"), ("reserved", "u1"), ("ctr0", "u1", (16,))])
+RESULT_DTYPE = np.dtype([("latency_s", "<f8"), ("admit_s", "<f8"), ("in_off", "<u8"),
+                         ("out_off", "<u8"), ("status", "<i4"), ("launch", "<i4")])
+assert REQUEST_DTYPE.itemsize == 48 and RESULT_DTYPE.itemsize == 40
+
+
+class aes_serve_cfg(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int), ("budget_bytes", ctypes.c_uint64),
+                ("max_batch_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int),
+                ("timeout_s", ctypes.c_double), ("simulate_gbps", ctypes.c_double)]
+
+
+class aes_serve_stats(ctypes.Structure):
+    _fields_ = [("span_s", ctypes.c_double), ("bytes_done", ctypes.c_uint64),
+                ("completed", ctypes.c_int), ("rejected", ctypes.c_int),
+                ("launches", ctypes.c_int), ("max_inflight_reqs", ctypes.c_int),
+                ("max_inflight_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def _load():
@@ -365,3 +394,59 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# --- serving ----------------------------------------------------------------
+def serve_cfg(streams=4, budget_bytes=8 << 30, max_batch_msgs=4096, tile_blocks=0,
+              timeout_s=0.0, simulate_gbps=0.0):
+    return aes_serve_cfg(streams=streams, budget_bytes=budget_bytes,
+                         max_batch_msgs=max_batch_msgs, tile_blocks=tile_blocks,
+                         timeout_s=timeout_s, simulate_gbps=simulate_gbps)
+
+
+def aes_serve_scratch_size(cfg):
+    n = ctypes.c_size_t(0)
+    _check(lib.aes_serve_scratch_size(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def aes_serve_run(reqs, cfg, d_keys=None, nkeys=None, scratch=None):
+    """Run the request loop.  reqs: numpy REQUEST_DTYPE array sorted by
+    arrival; d_keys: device tensor of 32-byte key slots; scratch: device
+    tensor of at least aes_serve_scratch_size(cfg) bytes (256-byte aligned
+    address).  Returns (results as RESULT_DTYPE array, stats dict)."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+    res = np.zeros(len(reqs), RESULT_DTYPE)
+    st = aes_serve_stats()
+    if nkeys is None:
+        nkeys = (d_keys.numel() // 32) if d_keys is not None else 1 << 30
+    sptr = _dptr(scratch)
+    sbytes = 0 if scratch is None else scratch.numel() * scratch.element_size()
+    _check(lib.aes_serve_run(reqs.ctypes.data_as(ctypes.c_void_p), len(reqs), _dptr(d_keys), nkeys,
+                             sptr, sbytes, ctypes.byref(cfg), res.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(st)))
+    return res, st.as_dict()
+
+
+class Server:
+    """Device memory for the request loop (keys and scratch as torch tensors)
+    and a run() that replays a request schedule through aes_serve_run."""
+
+    def __init__(self, keys, cfg, device="cuda"):
+        import torch
+        self.cfg = cfg
+        keys = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
+        self.nkeys = keys.shape[0]
+        self.d_keys = torch.from_numpy(keys.reshape(-1).copy()).to(device)
+        n = aes_serve_scratch_size(cfg)
+        self._raw = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        off = (-self._raw.data_ptr()) % 256
+        self.scratch = self._raw[off:off + n]
+
+    def run(self, reqs):
+        return aes_serve_run(reqs, self.cfg, self.d_keys, self.nkeys, self.scratch)
+
+    def output(self, result, nbytes):
+        """The output bytes of one finished request (a view into the arena)."""
+        o = int(result["out_off"])
+        return self.scratch[o:o + int(nbytes)]

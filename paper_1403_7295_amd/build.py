@@ -15,7 +15,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libaesgpu.so")
 ARCH = "gfx950"
 
-SOURCES = ("aes_kernels.hip", "batch_kernels.hip", "tables.cpp", "abi.cpp")
+SOURCES = ("aes_kernels.hip", "batch_kernels.hip", "tables.cpp", "abi.cpp", "serve.cpp")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
@@ -23,9 +23,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+def _rocm():
+    return os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
 def _hipcc():
-    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
-    return os.path.join(rocm, "bin", "hipcc")
+    return os.path.join(_rocm(), "bin", "hipcc")
 
 
 def _compile(src):
@@ -33,6 +36,9 @@ def _compile(src):
     cmd = [_hipcc()] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE + ["-x", "hip"]
+    else:
+        # host-only translation unit
+        cmd += ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(_rocm(), "include")]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

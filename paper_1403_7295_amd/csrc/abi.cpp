@@ -233,6 +233,22 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
 
 }  // namespace
 
+// Helpers the request loop (serve.cpp) shares with this file.
+namespace aesgpu {
+int serve_fail(int status, const std::string &msg) { return fail(status, msg); }
+int serve_device(int *cus) {
+    int st;
+    const DeviceState *d = current_device(&st);
+    if (d)
+        *cus = d->cus;
+    return st;
+}
+size_t serve_batch_layout(int max_msgs, uint64_t max_total_blocks, int tile_blocks, uint64_t *cap) {
+    return batch_layout(max_msgs, max_total_blocks, tile_blocks, cap);
+}
+int serve_batch_args(const aes_batch *b, BatchKArgs *a) { return batch_args(b, a); }
+}  // namespace aesgpu
+
 extern "C" {
 
 int aes_expand_key(const uint8_t *key, int keybits, uint8_t *roundkeys, int *Nr) {

@@ -251,6 +251,45 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchKArgs a) {
     }
 }
 
+
+// ---- synthetic payloads for the request loop ------------------------------
+// The payload of a request is the SplitMix64 stream of its seed: word i =
+// mix64(seed + (i + 1) * 0x9E3779B97F4A7C15), stored little-endian (Steele,
+// Lea and Flood 2014; mix64 is that generator's published output function).
+__device__ __forceinline__ uint64_t splitmix_word(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Chunks of kFillChunk bytes, numbered across the batch's messages; every
+// workgroup fills whole chunks, rounding each message up to 16 bytes (the
+// arena rounds every buffer up to 256).
+__global__ __launch_bounds__(256) void fill_kernel(const FillKArgs a) {
+    const uint32_t n = uint32_t(*a.d_nmsg);
+    const uint64_t nchunks = *a.d_nchunks;
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        // the message holding chunk c: the last one whose first chunk is <= c
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (a.fd[mid].chunk_first <= c)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const FillDesc d = a.fd[lo];
+        const uint64_t start = (c - d.chunk_first) * kFillChunk;
+        const uint64_t padded = (d.nbytes + 15) & ~uint64_t(15);
+        const uint64_t end = min(start + kFillChunk, padded);
+        for (uint64_t b = start + 16u * threadIdx.x; b < end; b += 16u * blockDim.x) {
+            const uint64_t w0 = splitmix_word(d.seed, b >> 3), w1 = splitmix_word(d.seed, (b >> 3) + 1);
+            store16(a.base + d.off + b, vec4(uint32_t(w0), uint32_t(w0 >> 32), uint32_t(w1), uint32_t(w1 >> 32)));
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t upload_tables_batch(const HostTables &t) { return upload_base_tables(t); }
@@ -269,6 +308,11 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream) {
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL((batch_kernel<1, 2>), dim3(grid), dim3(1024), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -92,6 +92,22 @@ struct BatchKArgs {
     uint32_t tile_blocks;
 };
 
+// Synthetic payloads of the request loop (batch_kernels.hip).
+constexpr uint64_t kFillChunk = 65536;
+struct FillDesc {
+    uint64_t off;          // byte offset of the payload in the arena
+    uint64_t nbytes;
+    uint64_t seed;         // SplitMix64 seed
+    uint64_t chunk_first;  // index of the message's first fill chunk in the batch
+};
+struct FillKArgs {
+    const FillDesc *fd;
+    const int *d_nmsg;
+    const uint64_t *d_nchunks;
+    uint8_t *base;
+};
+hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream);
+
 hipError_t upload_tables_batch(const HostTables &t);
 hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream);
 

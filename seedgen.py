@@ -142,3 +142,28 @@ def ragged_batch(master, n, lo=16, hi=1 << 24, multiple=16):
         keys[m, :keybits[m] // 8] = key(master, m, int(keybits[m]))
         nonces[m] = nonce(master, m)
     return lengths, keybits, keys, nonces
+
+
+def served_requests(master, n, rate, lo=64, hi=1 << 26, enc_fraction=0.7, start=0.0):
+    """The served workload: n requests with Poisson arrivals at `rate` per
+    second, sizes log-uniform in [lo, hi] bytes (byte-granular), encrypt with
+    probability enc_fraction else decrypt, AES-128 or AES-256 (1/2 each), all
+    CTR, each with its own key slot, nonce and payload stream.  Returns
+    (fields dict of numpy arrays, keys[n, 32]); request m uses key slot m,
+    nonce m and payload seed stream_seed(master, DATA, m)."""
+    rng = np.random.default_rng(master)
+    gaps = rng.exponential(1.0 / rate, n)
+    arrival = start + np.cumsum(gaps) - gaps[0]
+    nbytes = log_uniform_lengths(rng, n, lo, hi, 1)
+    decrypt = (rng.random(n) >= enc_fraction).astype(np.uint8)
+    keybits = np.where(rng.random(n) < 0.5, 128, 256)
+    keys = np.zeros((n, 32), np.uint8)
+    ctr0 = np.zeros((n, 16), np.uint8)
+    seeds = np.zeros(n, np.uint64)
+    for m in range(n):
+        keys[m, :keybits[m] // 8] = key(master, m, int(keybits[m]))
+        ctr0[m] = nonce(master, m)
+        seeds[m] = stream_seed(master, TAG_DATA, m)
+    return {"arrival_s": arrival, "nbytes": nbytes, "payload_seed": seeds, "key_idx": np.arange(n),
+            "keybits_code": (keybits - 128) // 64, "mode": np.ones(n, np.uint8),
+            "decrypt": decrypt, "ctr0": ctr0}, keys

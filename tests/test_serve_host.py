@@ -1,0 +1,108 @@
+"""The request loop's admission and batching logic on the CPU, with its
+simulated device (every launch finishes after its bytes at a fixed rate), so
+no GPU is touched."""
+import numpy as np
+import pytest
+
+import seedgen
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1403_7295_amd import aesgpu
+    return aesgpu
+
+
+def requests(A, n, rate, seed=5, lo=64, hi=1 << 22):
+    f, keys = seedgen.served_requests(seed, n, rate, lo=lo, hi=hi)
+    r = np.zeros(n, A.REQUEST_DTYPE)
+    for k, v in f.items():
+        r[k] = v
+    return r, keys
+
+
+def test_all_complete_and_budget_holds(A):
+    r, _ = requests(A, 3000, rate=50000.0)
+    budget = 64 << 20
+    cfg = A.serve_cfg(streams=4, budget_bytes=budget, max_batch_msgs=256, simulate_gbps=200.0)
+    res, st = A.aes_serve_run(r, cfg)
+    fp = 2 * ((r["nbytes"] + 255) // 256 * 256)
+    big = fp > budget
+    assert st["completed"] == (~big).sum() and st["rejected"] == big.sum()
+    assert (res["status"][big] == A.AES_E_LENGTH).all()
+    assert (res["status"][~big] == A.AES_OK).all()
+    assert st["max_inflight_bytes"] <= budget
+    ok = ~big
+    assert (res["latency_s"][ok] > 0).all()
+    assert (res["admit_s"][ok] >= 0).all()
+    assert (res["latency_s"][ok] >= res["admit_s"][ok]).all()
+    assert st["bytes_done"] == int(r["nbytes"][ok].sum())
+
+
+def test_overload_runs_at_device_rate_and_batches(A):
+    # offered ~10x the simulated device rate: the loop must batch and keep
+    # the device busy, so completed bytes / span approaches the device rate
+    r, _ = requests(A, 4000, rate=400000.0, hi=1 << 20)
+    rate = 20.0
+    cfg = A.serve_cfg(streams=4, budget_bytes=1 << 30, max_batch_msgs=512, simulate_gbps=rate)
+    res, st = A.aes_serve_run(r, cfg)
+    achieved = st["bytes_done"] / st["span_s"] / 1e9
+    assert 0.8 * rate < achieved <= rate * 1.01
+    assert st["launches"] < len(r) / 4          # many requests per launch
+    lat = res["latency_s"]
+    assert np.percentile(lat, 99) > np.percentile(lat, 50) > 0
+
+
+def test_light_load_latency_is_service_time(A):
+    r, _ = requests(A, 500, rate=2000.0, hi=1 << 16)
+    cfg = A.serve_cfg(streams=4, budget_bytes=1 << 30, max_batch_msgs=64, simulate_gbps=100.0)
+    res, st = A.aes_serve_run(r, cfg)
+    service = r["nbytes"] / 100e9 + 20e-6
+    # at 2,000 requests/s each request is nearly alone: latency is its own
+    # service time plus loop overhead
+    assert np.median(res["latency_s"] - service) < 200e-6
+    assert st["completed"] == 500
+
+
+def test_small_budget_makes_requests_wait(A):
+    r, _ = requests(A, 400, rate=200000.0, lo=1 << 20, hi=1 << 20)
+    budget = 8 * (2 << 20)                       # room for 8 requests at once
+    cfg = A.serve_cfg(streams=2, budget_bytes=budget, max_batch_msgs=64, simulate_gbps=50.0)
+    res, st = A.aes_serve_run(r, cfg)
+    assert st["max_inflight_reqs"] <= 8 and st["max_inflight_bytes"] <= budget
+    assert (res["admit_s"] > 1e-4).sum() > 100    # most requests queued for memory
+    assert st["completed"] == 400
+
+
+def test_argument_checks(A):
+    r, _ = requests(A, 10, rate=1000.0)
+    cfg = A.serve_cfg(simulate_gbps=10.0)
+    bad = r.copy()
+    bad["arrival_s"][3] = -1.0
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, cfg)
+    assert e.value.code == A.AES_E_ARG
+    bad = r.copy()
+    bad["keybits_code"][0] = 3
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, cfg)
+    assert e.value.code == A.AES_E_ARG
+    bad = r.copy()
+    bad["mode"][0] = 0
+    bad["nbytes"][0] = 17
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, cfg)
+    assert e.value.code == A.AES_E_LENGTH
+    for kw in ({"streams": 0}, {"streams": 17}, {"max_batch_msgs": 0}, {"budget_bytes": 100}):
+        with pytest.raises(A.AESError) as e:
+            A.aes_serve_scratch_size(A.serve_cfg(**kw))
+        assert e.value.code == A.AES_E_ARG
+    # without simulation a device is required: scratch must be given
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(r, A.serve_cfg())
+    assert e.value.code == A.AES_E_NULL
+
+
+def test_empty_run(A):
+    res, st = A.aes_serve_run(np.zeros(0, A.REQUEST_DTYPE), A.serve_cfg(simulate_gbps=1.0))
+    assert st["completed"] == 0 and len(res) == 0
