@@ -72,21 +72,30 @@ bool make_layout(const aes_serve_cfg &c, ServeLayout *L) {
     return true;
 }
 
-// First-fit arena allocator with coalescing of free neighbours.
+// Next-fit arena allocator with coalescing of free neighbours: the search
+// starts where the previous allocation ended and wraps around, so memory is
+// reused in roughly the order it was taken (requests finish roughly in
+// arrival order) and a freed region is not handed out again at once.
 class Arena {
   public:
     explicit Arena(uint64_t size) { free_[0] = size; }
     bool alloc(uint64_t n, uint64_t *off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                *off = it->first;
-                const uint64_t rest = it->second - n, at = it->first + n;
-                free_.erase(it);
-                if (rest)
-                    free_[at] = rest;
-                return true;
-            }
-        }
+        auto take = [&](std::map<uint64_t, uint64_t>::iterator it) {
+            *off = it->first;
+            const uint64_t rest = it->second - n, at = it->first + n;
+            free_.erase(it);
+            if (rest)
+                free_[at] = rest;
+            cursor_ = at;
+            return true;
+        };
+        for (auto it = free_.lower_bound(cursor_); it != free_.end(); ++it)
+            if (it->second >= n)
+                return take(it);
+        // the free block that contains the cursor starts before it
+        for (auto it = free_.begin(); it != free_.end() && it->first < cursor_; ++it)
+            if (it->second >= n)
+                return take(it);
         return false;
     }
     void release(uint64_t off, uint64_t n) {
@@ -107,6 +116,7 @@ class Arena {
 
   private:
     std::map<uint64_t, uint64_t> free_;
+    uint64_t cursor_ = 0;
 };
 
 struct Slot {

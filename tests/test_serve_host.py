@@ -106,3 +106,16 @@ def test_argument_checks(A):
 def test_empty_run(A):
     res, st = A.aes_serve_run(np.zeros(0, A.REQUEST_DTYPE), A.serve_cfg(simulate_gbps=1.0))
     assert st["completed"] == 0 and len(res) == 0
+
+
+def test_arena_is_not_reused_while_space_remains(A):
+    # next-fit: with room for everything, no two requests share memory, even
+    # though early requests finish (and free theirs) before late ones arrive
+    r, _ = requests(A, 500, rate=100000.0, hi=1 << 18)
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 255) // 256 * 256)
+    cfg = A.serve_cfg(streams=3, budget_bytes=int(fp.sum()), max_batch_msgs=16, simulate_gbps=50.0)
+    res, st = A.aes_serve_run(r, cfg)
+    assert st["completed"] == 500
+    spans = sorted(zip(res["in_off"].tolist(), fp.tolist()))
+    for (a, na), (b, _) in zip(spans, spans[1:]):
+        assert a + na <= b
