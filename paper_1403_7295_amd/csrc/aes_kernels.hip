@@ -23,7 +23,9 @@ __global__ __launch_bounds__(1024) void cipher_kernel(const CipherArgs a) {
 
     const LaneConsts lc = lane_consts<LAYOUT>(threadIdx.x & 63u);
     const uint64_t nblk = (a.nbytes + 15) >> 4;
-    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    // the wave index is the same in all 64 lanes; saying so lets the block
+    // loop keep its base address in scalar registers
+    const uint64_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint64_t sweep = uint64_t(gridDim.x) * blockDim.x * BPT;  // blocks per pass of the grid
     process_blocks<NR, MODE, DIR, LAYOUT, BPT>(lds, lc, a.rk, a.ctr, a.in, a.out, a.nbytes,
                                                wave * 64u * BPT, nblk, sweep);

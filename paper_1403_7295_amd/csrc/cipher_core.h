@@ -246,6 +246,14 @@ __device__ __forceinline__ void store_tail(uint8_t *p, u32x4 v, uint32_t n) {
             p[b] = uint8_t(w[b >> 2] >> (8 * (b & 3)));
 }
 
+// min(v, 64 * BPT) for a 64-bit v, written on 32-bit halves (the scalar unit
+// has no 64-bit less-than).
+template <int BPT>
+__device__ __forceinline__ uint32_t clamp_step(uint64_t v) {
+    const uint32_t hi = uint32_t(v >> 32), lo = uint32_t(v);
+    return (hi != 0 || lo > 64u * BPT) ? 64u * BPT : lo;
+}
+
 // Carries blocks j = base + 64*i + lane (i < BPT) through the cipher for
 // every wave-uniform base in [begin, end) stepping by `step`; only blocks
 // below `limit` exist.  Blocks are 16-byte units of a message of `nbytes`
@@ -261,6 +269,8 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t nfull = nbytes >> 4;
     const uint32_t tail = uint32_t(nbytes & 15u);
+    // The loop below assumes `step` >= 64 * BPT: each step is a private
+    // range of at most 64 * BPT blocks for the wave.
 
     // CTR: after the first AddRoundKey, columns 0..2 of every counter block
     // are the same (the nonce), so 12 of round 1's 16 lookups are the same
@@ -276,16 +286,28 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
     const uint32_t c0 = MODE == MODE_CTR ? ctr[3] : 0u;
 
     for (uint64_t base = begin; base < limit; base += step) {
+        // Wave-uniform per step: pointers to block `base` and how many blocks
+        // from there exist (whole ones, and the index of a partial tail), so
+        // every lane works with a 32-bit offset from a scalar base address.
+        const uint8_t *inb = in + 16 * base;
+        uint8_t *outb = out + 16 * base;
+        const uint64_t room = limit - base;
+        const uint64_t whole = nfull > base ? min(nfull, limit) - base : 0;
+        const uint32_t nwhole = clamp_step<BPT>(whole);
+        const uint32_t tail_at = (MODE == MODE_CTR && tail && nfull >= base && nfull - base < room &&
+                                  clamp_step<BPT>(nfull - base) == uint32_t(nfull - base) &&
+                                  uint32_t(nfull - base) < 64u * BPT)
+                                     ? uint32_t(nfull - base) : 0xFFFFFFFFu;
         uint32_t s[BPT][4];
         u32x4 x[BPT];
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
-            const uint64_t j = base + uint64_t(i) * 64u + lane;
+            const uint32_t jj = uint32_t(i) * 64u + lane;
             x[i] = vec4(0, 0, 0, 0);
-            if (j < nfull && j < limit)
-                x[i] = load16(in + 16 * j);
-            else if (MODE == MODE_CTR && j == nfull && tail && j < limit)
-                x[i] = load_tail(in + 16 * j, tail);
+            if (jj < nwhole)
+                x[i] = load16(inb + 16u * jj);
+            else if (MODE == MODE_CTR && jj == tail_at)
+                x[i] = load_tail(inb + 16u * jj, tail);
             if (MODE == MODE_ECB) {
                 s[i][0] = x[i].x ^ rk[0];
                 s[i][1] = x[i].y ^ rk[1];
@@ -294,7 +316,7 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
             } else {
                 // counter block j: nonce || big-endian (c0 + j) mod 2^32;
                 // round 1 needs only the four lookups on column 3.
-                const uint32_t v3 = bswap(c0 + uint32_t(j)) ^ rk[3];
+                const uint32_t v3 = bswap(c0 + uint32_t(base) + jj) ^ rk[3];
                 s[i][0] = pre0 ^ tl<LAYOUT, 3, 3>(lds, lc, v3);
                 s[i][1] = pre1 ^ tl<LAYOUT, 2, 2>(lds, lc, v3);
                 s[i][2] = pre2 ^ tl<LAYOUT, 1, 1>(lds, lc, v3);
@@ -304,16 +326,16 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
         rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, MODE == MODE_CTR ? 2 : 1);
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
-            const uint64_t j = base + uint64_t(i) * 64u + lane;
+            const uint32_t jj = uint32_t(i) * 64u + lane;
             u32x4 o;
             if (MODE == MODE_ECB)
                 o = vec4(s[i][0], s[i][1], s[i][2], s[i][3]);
             else
                 o = vec4(s[i][0] ^ x[i].x, s[i][1] ^ x[i].y, s[i][2] ^ x[i].z, s[i][3] ^ x[i].w);
-            if (j < nfull && j < limit)
-                store16(out + 16 * j, o);
-            else if (MODE == MODE_CTR && j == nfull && tail && j < limit)
-                store_tail(out + 16 * j, o, tail);
+            if (jj < nwhole)
+                store16(outb + 16u * jj, o);
+            else if (MODE == MODE_CTR && jj == tail_at)
+                store_tail(outb + 16u * jj, o, tail);
         }
     }
 }

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "aesgpu.h"
+#include "arena.h"
 #include "internal.h"
 
 namespace aesgpu {
@@ -71,53 +72,6 @@ bool make_layout(const aes_serve_cfg &c, ServeLayout *L) {
     L->total = L->arena + size_t(c.streams) * L->slot_bytes;
     return true;
 }
-
-// Next-fit arena allocator with coalescing of free neighbours: the search
-// starts where the previous allocation ended and wraps around, so memory is
-// reused in roughly the order it was taken (requests finish roughly in
-// arrival order) and a freed region is not handed out again at once.
-class Arena {
-  public:
-    explicit Arena(uint64_t size) { free_[0] = size; }
-    bool alloc(uint64_t n, uint64_t *off) {
-        auto take = [&](std::map<uint64_t, uint64_t>::iterator it) {
-            *off = it->first;
-            const uint64_t rest = it->second - n, at = it->first + n;
-            free_.erase(it);
-            if (rest)
-                free_[at] = rest;
-            cursor_ = at;
-            return true;
-        };
-        for (auto it = free_.lower_bound(cursor_); it != free_.end(); ++it)
-            if (it->second >= n)
-                return take(it);
-        // the free block that contains the cursor starts before it
-        for (auto it = free_.begin(); it != free_.end() && it->first < cursor_; ++it)
-            if (it->second >= n)
-                return take(it);
-        return false;
-    }
-    void release(uint64_t off, uint64_t n) {
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + n == next->first) {
-            n += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += n;
-                return;
-            }
-        }
-        free_[off] = n;
-    }
-
-  private:
-    std::map<uint64_t, uint64_t> free_;
-    uint64_t cursor_ = 0;
-};
 
 struct Slot {
     bool busy = false;
