@@ -281,6 +281,16 @@ def main():
                                   lambda: fn(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream), 10, 2)
             sec[name] = {"GB/s": round(n / k / 1e9, 1),
                          "Tlookup/s": round(lookups_per_block(nr, mode == A.AES_MODE_CTR) * nblocks / k / 1e12, 3)}
+        rk, nr = A.aes_expand_key(key128)
+        A.aes_set_launch(layout=2)
+        try:
+            for name, mode in (("aes128_ecb_enc_bitsliced", A.AES_MODE_ECB),
+                               ("aes128_ctr_enc_bitsliced", A.AES_MODE_CTR)):
+                w, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0,
+                                                                            stream=stream), 10, 2)
+                sec[name] = {"GB/s": round(n / k / 1e9, 1)}
+        finally:
+            A.aes_set_launch(None)
         w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, 2)
         sec["copy_kernel"] = {"GB/s (read+write)": round(2 * n / k / 1e9, 1)}
         out["secondary"] = sec

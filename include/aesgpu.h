@@ -110,9 +110,15 @@ const char *aes_last_error(void);
  * on it.  All fields 0 mean "the library's choice".
  *   layout            0 = four round tables, 32 copies each, in LDS;
  *                     1 = two round tables, 64 copies each (the other two
- *                         are rotations of them).
- *   blocks_per_thread 1, 2 or 4 16-byte blocks in flight per thread.
- *   wg_size           256, 512 or 1024 threads per workgroup.
+ *                         are rotations of them);
+ *                     2 = bitsliced: no tables, 32 blocks per lane as 128
+ *                         bit-planes, S-box as a Boolean circuit (constant
+ *                         time; encryption only: ECB decryption with this
+ *                         layout returns AES_E_ARG).
+ *   blocks_per_thread 1, 2 or 4 16-byte blocks in flight per thread (table
+ *                     layouts; the bitsliced layout always carries 32).
+ *   wg_size           256, 512 or 1024 threads per workgroup (table layouts;
+ *                     the bitsliced layout uses 256).
  *   grid              workgroups launched (each loops over the buffer); 0 =
  *                     one per compute unit.
  */

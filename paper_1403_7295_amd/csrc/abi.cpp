@@ -83,7 +83,7 @@ aes_launch g_launch = {0, 0, 0, 0};
 bool g_launch_set = false;
 
 bool valid_launch(const aes_launch &c) {
-    return (c.layout == 0 || c.layout == 1) &&
+    return (c.layout == 0 || c.layout == 1 || c.layout == LAYOUT_BITSLICED) &&
            (c.blocks_per_thread == 0 || c.blocks_per_thread == 1 || c.blocks_per_thread == 2 ||
             c.blocks_per_thread == 4) &&
            (c.wg_size == 0 || c.wg_size == 256 || c.wg_size == 512 || c.wg_size == 1024) &&
@@ -102,6 +102,18 @@ LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes) {
     c.layout = set ? o.layout : LAYOUT_T4X32;
     c.bpt = set && o.blocks_per_thread ? o.blocks_per_thread : 2;
     c.wg = set && o.wg_size ? o.wg_size : 1024;
+    if (c.layout == LAYOUT_BITSLICED) {
+        // 256-thread workgroups, two per CU (no LDS, up to 256 VGPRs per
+        // lane); each lane carries 32 blocks
+        c.bpt = 32;
+        c.wg = 256;
+        uint64_t grid = set && o.grid ? uint64_t(o.grid) : uint64_t(d.cus) * 2;
+        const uint64_t useful = ((nbytes + 15) / 16 + 256 * 32 - 1) / (256 * 32);
+        if (!(set && o.grid) && useful < grid)
+            grid = useful;
+        c.grid = int(grid < 1 ? 1 : grid > 0x7fffffff ? 0x7fffffff : grid);
+        return c;
+    }
     // The round tables fill most of the LDS, so one workgroup runs per
     // compute unit; a persistent grid of one workgroup per CU sweeps the
     // buffer.  Small buffers get only as many workgroups as they can keep busy.
@@ -171,7 +183,17 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
                    (uint32_t(ctr0[14]) << 8) | uint32_t(ctr0[15]);
     }
     const LaunchCfg cfg = choose_launch(*d, nbytes);
-    hipError_t e = launch_cipher(Nr, mode == AES_MODE_CTR ? MODE_CTR : MODE_ECB,
+    hipError_t e;
+    if (cfg.layout == LAYOUT_BITSLICED) {
+        if (dec_cipher)
+            return fail(AES_E_ARG, "the bitsliced kernel encrypts only (ECB encrypt, CTR)");
+        e = launch_bitslice(Nr, mode == AES_MODE_CTR ? MODE_CTR : MODE_ECB, cfg.grid, a,
+                            static_cast<hipStream_t>(stream));
+        if (e != hipSuccess)
+            return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        return AES_OK;
+    }
+    e = launch_cipher(Nr, mode == AES_MODE_CTR ? MODE_CTR : MODE_ECB,
                                  dec_cipher ? DIR_DEC : DIR_ENC, cfg, a,
                                  static_cast<hipStream_t>(stream));
     if (e != hipSuccess)

@@ -54,6 +54,9 @@ hipError_t upload_tables(const HostTables &t);
 hipError_t launch_cipher(int nr, int mode, int dir, const LaunchCfg &cfg, const CipherArgs &a,
                          hipStream_t stream);
 hipError_t launch_copy(const void *in, void *out, uint64_t nbytes, int grid, hipStream_t stream);
+// The bitsliced comparison kernel (bitslice.hip): encryption only.
+constexpr int LAYOUT_BITSLICED = 2;
+hipError_t launch_bitslice(int nr, int mode, int grid, const CipherArgs &a, hipStream_t stream);
 
 // ---- batches (batch_kernels.hip) -------------------------------------------
 // Workspace = header | key schedules (max_msgs slots) | tiles[2][capacity].

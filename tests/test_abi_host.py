@@ -89,7 +89,7 @@ def test_argument_checks(A, fn):
 
 
 def test_launch_config_validation(A):
-    for bad in ({"layout": 2}, {"blocks_per_thread": 3}, {"wg_size": 100}, {"grid": -1}):
+    for bad in ({"layout": 3}, {"blocks_per_thread": 3}, {"wg_size": 100}, {"grid": -1}):
         with pytest.raises(A.AESError) as e:
             A.aes_set_launch(bad)
         assert e.value.code == A.AES_E_ARG

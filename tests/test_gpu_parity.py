@@ -251,3 +251,47 @@ def test_aes256_16mib_whole_buffer(A, O):
     assert_same(gpu_op(A, "enc", x, rk, nr), want, "AES-256 ECB 16 MiB")
     want, _ = O.par_run(2, rk, nr, x, 16, ctr0=ctr0)
     assert_same(gpu_op(A, "ctr", x, rk, nr, ctr0=ctr0), want, "AES-256 CTR 16 MiB")
+
+
+# --- the bitsliced comparison kernel (launch layout 2) ----------------------
+@pytest.mark.parametrize("bits", [128, 192, 256])
+@pytest.mark.parametrize("grid", [0, 1, 7])
+def test_bitsliced_matches_oracle(A, O, bits, grid):
+    k = seedgen.key(11, bits, bits)
+    rk, nr = A.aes_expand_key(k)
+    x = seedgen.data_np(11, bits, 5 * 2048 * 16 + 777 * 16 + 9)   # several waves' worth and a ragged tail
+    ctr0 = seedgen.nonce(11, bits)
+    ctr0[12:16] = [0x00, 0x00, 0xFF, 0x80]                        # counter crosses byte boundaries
+    n16 = x.size - 9
+    A.aes_set_launch(layout=2, grid=grid)
+    try:
+        assert_same(gpu_op(A, "enc", x[:n16], rk, nr), O.ecb_encrypt(rk, nr, x[:n16]), "bitsliced ECB")
+        assert_same(gpu_op(A, "ctr", x, rk, nr, ctr0=ctr0), O.ctr(rk, nr, ctr0, x), "bitsliced CTR")
+        assert_same(gpu_op(A, "ctr_dec", x[:100], rk, nr, ctr0=ctr0), O.ctr(rk, nr, ctr0, x[:100]),
+                    "bitsliced CTR decrypt")
+        with pytest.raises(A.AESError) as e:
+            gpu_op(A, "dec", x[:n16], rk, nr)
+        assert e.value.code == A.AES_E_ARG
+    finally:
+        A.aes_set_launch(None)
+
+
+def test_bitsliced_1gib_equals_table_kernel(A, O):
+    k = seedgen.key(2, 0, 128)
+    rk, nr = A.aes_expand_key(k)
+    ctr0 = seedgen.nonce(2, 0)
+    n = 1 << 30
+    x = seedgen.data_torch(2, 0, n, "cuda")
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    for mode in ("ecb", "ctr"):
+        A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0)
+        A.aes_set_launch(layout=2)
+        try:
+            A.aes_encrypt(x, z, n, rk, nr, mode, ctr0=ctr0)
+        finally:
+            A.aes_set_launch(None)
+        torch.cuda.synchronize()
+        assert torch.equal(y, z), mode
+    idx = sample_blocks(n // 16, 256, 7)
+    check_sampled(O, z, 2, 0, rk, nr, "ctr", ctr0, idx, "bitsliced CTR 1 GiB")
