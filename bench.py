@@ -80,22 +80,23 @@ def timed_launches(torch, stream, launch, steps, warmup):
 
 
 def kernel_source_sha():
+    """Hash of the device code of the buffer kernels."""
     h = hashlib.sha256()
-    for name in ("aes_kernels.hip", "abi.cpp", "internal.h"):
+    for name in ("aes_kernels.hip", "cipher_core.h"):
         with open(os.path.join(os.path.dirname(KERNEL_SRC), name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(launch):
     """HBM bytes per launch from committed hardware-counter runs, if they were
-    taken on the kernel source as it is now; else None."""
+    taken on the kernel source and launch configuration in use now; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha() or t.get("launch") != launch:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -226,14 +227,14 @@ def main():
         A.aes_encrypt(x, y, n, rk, nr, A.AES_MODE_ECB, stream=stream)
 
     wall, kern = timed_launches(torch, stream, step, args.steps, args.warmup)
-    launch = A.aes_get_launch(n, A.AES_MODE_ECB, False)
+    launch = A.aes_get_launch(n, A.AES_MODE_ECB, False, 10)
     value = n * args.steps / wall / 1e9
     nblocks = n // 16
 
     hbm_achieved = 2 * n / kern / 1e9
     lk = lookups_per_block(10) * nblocks
     issue_achieved = lk / kern / 1e12
-    traffic = measured_traffic()
+    traffic = measured_traffic(launch)
     roof_hbm = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}

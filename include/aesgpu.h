@@ -134,8 +134,27 @@ typedef struct {
  * AES_E_ARG for values outside the lists above. */
 int aes_set_launch(const aes_launch *cfg);
 
+/*
+ * Tuned launch configurations.  An entry applies to calls with its mode,
+ * direction and Nr whose length is at least min_bytes; among matching
+ * entries the one with the largest min_bytes wins.  A configuration set with
+ * aes_set_launch overrides the table.  aes_set_tuned replaces the whole
+ * table (n = 0 clears it); at most 256 entries.  Errors: AES_E_ARG for an
+ * entry with values outside the aes_launch lists, or the bitsliced layout
+ * for ECB decryption.
+ */
+typedef struct {
+    int mode;          /* AES_MODE_ECB or AES_MODE_CTR */
+    int decrypt;       /* 0 or 1 */
+    int Nr;            /* 10, 12 or 14 */
+    uint64_t min_bytes;
+    aes_launch cfg;
+} aes_tuned_entry;
+
+int aes_set_tuned(const aes_tuned_entry *entries, int n);
+
 /* The configuration the next call with these arguments would use. */
-int aes_get_launch(size_t nbytes, int mode, int decrypt, aes_launch *cfg);
+int aes_get_launch(size_t nbytes, int mode, int decrypt, int Nr, aes_launch *cfg);
 
 /*
  * Measurement helper (not part of the cipher): copies nbytes (a multiple of

@@ -8,6 +8,7 @@ There is no fallback: if the library is missing or fails to load, importing
 this module raises.
 """
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -44,8 +45,9 @@ _SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "aes_last_error": (ctypes.c_char_p, []),
     "aes_set_launch": (ctypes.c_int, [ctypes.c_void_p]),
-    "aes_get_launch": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+    "aes_get_launch": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_void_p]),
+    "aes_set_tuned": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "aes_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                 ctypes.c_void_p]),
     "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
@@ -134,6 +136,8 @@ def _load():
 
 
 lib = _load()
+TUNED_TABLE = os.path.join(HERE, "tuned_gfx950.json")
+TUNED_TILE_BLOCKS = 0      # batch tile size picked by the autotuner (0 = library default)
 
 
 def _check(status):
@@ -230,10 +234,29 @@ def aes_set_launch(cfg=None, **fields):
     _check(lib.aes_set_launch(ctypes.byref(c)))
 
 
-def aes_get_launch(nbytes, mode=AES_MODE_ECB, decrypt=False):
+def aes_get_launch(nbytes, mode=AES_MODE_ECB, decrypt=False, Nr=10):
     c = aes_launch()
-    _check(lib.aes_get_launch(nbytes, _mode(mode), int(bool(decrypt)), ctypes.byref(c)))
+    _check(lib.aes_get_launch(nbytes, _mode(mode), int(bool(decrypt)), Nr, ctypes.byref(c)))
     return c.as_dict()
+
+
+class aes_tuned_entry(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("decrypt", ctypes.c_int), ("Nr", ctypes.c_int),
+                ("min_bytes", ctypes.c_uint64), ("cfg", aes_launch)]
+
+
+def aes_set_tuned(entries):
+    """Install a tuned table: entries are dicts with mode, decrypt, Nr,
+    min_bytes and cfg (an aes_launch dict)."""
+    arr = (aes_tuned_entry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i].mode = _mode(e["mode"])
+        arr[i].decrypt = int(e["decrypt"])
+        arr[i].Nr = int(e["Nr"])
+        arr[i].min_bytes = int(e["min_bytes"])
+        for k, v in e["cfg"].items():
+            setattr(arr[i].cfg, k, int(v))
+    _check(lib.aes_set_tuned(arr, len(entries)))
 
 
 def aes_copy(inp, out, nbytes=None, stream=None):
@@ -333,7 +356,7 @@ class Batch:
         self.max_msgs = max(1, int(max_msgs or len(descs)))
         blocks = int(((descs["nbytes"].astype(np.uint64) + 15) // 16).sum()) if len(descs) else 0
         self.max_total_blocks = int(max_total_blocks if max_total_blocks is not None else blocks)
-        self.tile_blocks = int(tile_blocks)
+        self.tile_blocks = int(tile_blocks or TUNED_TILE_BLOCKS)
         self.d_desc = torch.zeros(self.max_msgs * 48, dtype=torch.uint8, device=self.device)
         self.d_nmsg = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.d_keys = torch.from_numpy(keys.reshape(-1).copy()).to(self.device)
@@ -450,3 +473,19 @@ class Server:
         """The output bytes of one finished request (a view into the arena)."""
         o = int(result["out_off"])
         return self.scratch[o:o + int(nbytes)]
+
+
+def _install_tuned():
+    """Install the autotuner's committed launch table for gfx950 (the only
+    device the library runs on); host-side only, no device is touched."""
+    global TUNED_TILE_BLOCKS
+    if not os.path.exists(TUNED_TABLE):
+        return
+    with open(TUNED_TABLE) as f:
+        table = json.load(f)
+    aes_set_tuned([dict(mode=e["mode"], decrypt=e["decrypt"], Nr=e["Nr"], min_bytes=e["min_bytes"],
+                        cfg=e["cfg"]) for e in table.get("entries", [])])
+    TUNED_TILE_BLOCKS = int(table.get("batch_tile_blocks", 0))
+
+
+_install_tuned()

@@ -1,0 +1,153 @@
+"""Launch autotuner for the buffer kernels and the batch tile size.
+
+For every operation (ECB encrypt, ECB decrypt, CTR), key size and buffer
+size bucket it times every candidate launch configuration (table layout,
+blocks per thread -- i.e. blocks per wave step = 64 x blocks_per_thread --,
+workgroup size, or the bitsliced kernel) with HIP events on the current
+stream, keeps the fastest, and installs the result in the library with
+aes_set_tuned.  For batches it times the tile size (blocks per unit of
+work) on a ragged multi-message workload.  Results are saved as JSON keyed
+by the GPU's architecture and compute-unit count; the binding installs the
+committed table for gfx950 when it is imported.
+
+    python -m paper_1403_7295_amd.autotune --out paper_1403_7295_amd/tuned_gfx950.json
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tuned_gfx950.json")
+
+TABLE_CANDIDATES = [dict(layout=l, blocks_per_thread=b, wg_size=w, grid=0)
+                    for l in (0, 1) for b in (1, 2, 4) for w in (512, 1024)]
+BITSLICED = dict(layout=2, blocks_per_thread=0, wg_size=0, grid=0)
+# (label, mode, decrypt)
+OPS = (("ecb_enc", "ecb", 0), ("ecb_dec", "ecb", 1), ("ctr", "ctr", 0))
+# size buckets: the size tuned at, and the smallest size the result applies to
+BUCKETS = ((1 << 16, 0), (1 << 20, 1 << 18), (1 << 24, 1 << 22), (1 << 30, 1 << 27))
+TILE_CANDIDATES = (1024, 2048, 4096, 8192, 16384, 32768)
+
+
+def _time(torch, fn, reps, warm=2):
+    s = torch.cuda.current_stream()
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps / 1e3
+
+
+def tune_plain(A, torch, nrs=(10, 12, 14), buckets=BUCKETS, verbose=False):
+    """Returns (entries for aes_set_tuned, measurements)."""
+    import seedgen
+    big = max(sz for sz, _ in buckets)
+    x = seedgen.data_torch(77, 0, big, "cuda")
+    y = torch.empty_like(x)
+    ctr0 = seedgen.nonce(77, 0)
+    entries, log = [], []
+    A.aes_set_tuned([])
+    try:
+        for nr in nrs:
+            rk, _ = A.aes_expand_key(seedgen.key(77, nr, {10: 128, 12: 192, 14: 256}[nr]))
+            for label, mode, dec in OPS:
+                fn = A.aes_decrypt if dec else A.aes_encrypt
+                cands = TABLE_CANDIDATES + ([] if (mode == "ecb" and dec) else [BITSLICED])
+                for size, min_bytes in buckets:
+                    reps = max(3, min(200, (1 << 28) // size))
+                    best = None
+                    for cfg in cands:
+                        A.aes_set_launch(cfg)
+                        t = _time(torch, lambda: fn(x, y, size, rk, nr, mode, ctr0=ctr0), reps)
+                        log.append(dict(op=label, Nr=nr, bytes=size, cfg=cfg, seconds=t,
+                                        GBps=size / t / 1e9))
+                        if best is None or t < best[0]:
+                            best = (t, cfg)
+                    A.aes_set_launch(None)
+                    entries.append(dict(mode=mode, decrypt=dec, Nr=nr, min_bytes=min_bytes,
+                                        cfg=best[1], tuned_at_bytes=size,
+                                        GBps=round(size / best[0] / 1e9, 1)))
+                    if verbose:
+                        print("%s Nr=%d %10d B: %s %.1f GB/s" % (label, nr, size, best[1],
+                                                                  size / best[0] / 1e9), flush=True)
+    finally:
+        A.aes_set_launch(None)
+    return entries, log
+
+
+def tune_batch(A, torch, nmsg=2000, verbose=False):
+    """Best tile size for the ragged multi-message workload (a 2,000-message
+    slice of it)."""
+    import seedgen
+    lens, keybits, keys, _ = seedgen.ragged_batch(4, nmsg)
+    descs = A.make_descs(lens, keybits=keybits, mode="ecb")
+    total = int(lens.sum())
+    x = seedgen.data_torch(4, 0, total, "cuda")
+    y = torch.empty_like(x)
+    results = []
+    for tile in TILE_CANDIDATES:
+        b = A.Batch(descs, keys, x, y, tile_blocks=tile)
+        t = _time(torch, lambda: b.launch_graph(), 5)
+        b.close()
+        results.append(dict(tile_blocks=tile, seconds=t, GBps=total / t / 1e9))
+        if verbose:
+            print("batch tile %6d: %.1f GB/s" % (tile, total / t / 1e9), flush=True)
+    best = min(results, key=lambda r: r["seconds"])
+    return best["tile_blocks"], results
+
+
+def device_key(torch):
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
+    return "%s_%dcu" % (arch, p.multi_processor_count)
+
+
+def save(path, table):
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+
+
+def load(path=DEFAULT_TABLE):
+    with open(path) as f:
+        return json.load(f)
+
+
+def apply(A, table):
+    """Install a saved table's launch entries in the library."""
+    A.aes_set_tuned([dict(mode=e["mode"], decrypt=e["decrypt"], Nr=e["Nr"], min_bytes=e["min_bytes"],
+                          cfg=e["cfg"]) for e in table["entries"]])
+
+
+def main():
+    ap = argparse.ArgumentParser(description="tune launch configurations on this GPU")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--nr", type=int, nargs="*", default=[10, 12, 14])
+    ap.add_argument("--no-batch", action="store_true")
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    from paper_1403_7295_amd import aesgpu as A
+    t0 = time.time()
+    entries, log = tune_plain(A, torch, tuple(args.nr), verbose=True)
+    table = {"device": device_key(torch), "entries": entries, "measurements": log}
+    if not args.no_batch:
+        tile, blog = tune_batch(A, torch, verbose=True)
+        table["batch_tile_blocks"] = tile
+        table["batch_measurements"] = blog
+    table["seconds"] = round(time.time() - t0, 1)
+    if args.out:
+        save(args.out, table)
+    print(json.dumps({k: v for k, v in table.items() if "measurements" not in k}, indent=1))
+
+
+if __name__ == "__main__":
+    main()

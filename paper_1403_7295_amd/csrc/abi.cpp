@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -90,13 +91,26 @@ bool valid_launch(const aes_launch &c) {
            c.grid >= 0;
 }
 
-LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes) {
+std::vector<aes_tuned_entry> g_tuned;  // guarded by g_launch_mu
+
+LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes, int mode, int decrypt, int nr) {
     aes_launch o;
     bool set;
     {
         std::lock_guard<std::mutex> lk(g_launch_mu);
         o = g_launch;
         set = g_launch_set;
+        if (!set) {
+            const aes_tuned_entry *best = nullptr;
+            for (const aes_tuned_entry &e : g_tuned)
+                if (e.mode == mode && e.decrypt == decrypt && e.Nr == nr && e.min_bytes <= nbytes &&
+                    (!best || e.min_bytes > best->min_bytes))
+                    best = &e;
+            if (best) {
+                o = best->cfg;
+                set = true;
+            }
+        }
     }
     LaunchCfg c;
     c.layout = set ? o.layout : LAYOUT_T4X32;
@@ -182,7 +196,7 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
         a.ctr[3] = (uint32_t(ctr0[12]) << 24) | (uint32_t(ctr0[13]) << 16) |
                    (uint32_t(ctr0[14]) << 8) | uint32_t(ctr0[15]);
     }
-    const LaunchCfg cfg = choose_launch(*d, nbytes);
+    const LaunchCfg cfg = choose_launch(*d, nbytes, mode, decrypt && mode == AES_MODE_ECB, Nr);
     hipError_t e;
     if (cfg.layout == LAYOUT_BITSLICED) {
         if (dec_cipher)
@@ -312,16 +326,30 @@ int aes_set_launch(const aes_launch *cfg) {
     return AES_OK;
 }
 
-int aes_get_launch(size_t nbytes, int mode, int decrypt, aes_launch *cfg) {
-    (void)mode;
-    (void)decrypt;
+int aes_set_tuned(const aes_tuned_entry *entries, int n) {
+    if (n < 0 || n > 256 || (n > 0 && !entries))
+        return fail(AES_E_ARG, "0 <= n <= 256 entries, entries not NULL");
+    for (int i = 0; i < n; i++) {
+        const aes_tuned_entry &e = entries[i];
+        if ((e.mode != AES_MODE_ECB && e.mode != AES_MODE_CTR) || (e.decrypt != 0 && e.decrypt != 1) ||
+            (e.Nr != 10 && e.Nr != 12 && e.Nr != 14) || !valid_launch(e.cfg))
+            return fail(AES_E_ARG, "tuned entry " + std::to_string(i) + " out of range");
+        if (e.cfg.layout == LAYOUT_BITSLICED && e.mode == AES_MODE_ECB && e.decrypt)
+            return fail(AES_E_ARG, "tuned entry " + std::to_string(i) + ": bitsliced layout cannot decrypt ECB");
+    }
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    g_tuned.assign(entries, entries + n);
+    return AES_OK;
+}
+
+int aes_get_launch(size_t nbytes, int mode, int decrypt, int Nr, aes_launch *cfg) {
     if (!cfg)
         return fail(AES_E_NULL, "cfg must not be NULL");
     int st;
     const DeviceState *d = current_device(&st);
     if (!d)
         return st;
-    const LaunchCfg c = choose_launch(*d, nbytes);
+    const LaunchCfg c = choose_launch(*d, nbytes, mode, decrypt && mode == AES_MODE_ECB, Nr);
     cfg->layout = c.layout;
     cfg->blocks_per_thread = c.bpt;
     cfg->wg_size = c.wg;

@@ -194,28 +194,34 @@ __device__ __forceinline__ void rounds(uint32_t (&s)[BPT][4], const uint32_t *ld
     }
 }
 
-template <int LAYOUT, int DIR>
-__device__ __forceinline__ void stage_tables(uint32_t *lds) {
-    const uint32_t *base = g_base + (DIR == DIR_ENC ? 0 : 256);
-    for (uint32_t i = threadIdx.x; i < kTableWords; i += blockDim.x) {
-        // word index i = table<<14 | x<<6 | copy (T2X64) or
-        //                pair<<14 | x<<6 | (t&1)<<5 | copy (T4X32)
-        const uint32_t x = (i >> 6) & 255u;
-        const uint32_t t = (LAYOUT == LAYOUT_T4X32) ? (((i >> 14) << 1) | ((i >> 5) & 1u)) : (i >> 14);
-        lds[i] = rotl(base[x], 8 * int(t));
-    }
-    if (DIR == DIR_DEC) {
-        for (uint32_t i = threadIdx.x; i < kInvSboxWords; i += blockDim.x)
-            lds[(kInvSboxAddr >> 2) + i] = g_base[512 + (i >> 5)];
-    }
-}
-
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32x4 vec4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
     u32x4 v;
     v.x = a; v.y = b; v.z = c; v.w = d;
     return v;
+}
+
+// Fills the LDS tables from the 1 KiB base tables.  Words i..i+3 of a table
+// are copies of the same entry in neighbouring banks (the copy index is the
+// low bits of i), so every thread writes four of them with one 16-byte store.
+template <int LAYOUT, int DIR>
+__device__ __forceinline__ void stage_tables(uint32_t *lds) {
+    const uint32_t *base = g_base + (DIR == DIR_ENC ? 0 : 256);
+    for (uint32_t i = 4 * threadIdx.x; i < kTableWords; i += 4 * blockDim.x) {
+        // word index i = table<<14 | x<<6 | copy (T2X64) or
+        //                pair<<14 | x<<6 | (t&1)<<5 | copy (T4X32)
+        const uint32_t x = (i >> 6) & 255u;
+        const uint32_t t = (LAYOUT == LAYOUT_T4X32) ? (((i >> 14) << 1) | ((i >> 5) & 1u)) : (i >> 14);
+        const uint32_t v = rotl(base[x], 8 * int(t));
+        *reinterpret_cast<u32x4 *>(lds + i) = vec4(v, v, v, v);
+    }
+    if (DIR == DIR_DEC) {
+        for (uint32_t i = 4 * threadIdx.x; i < kInvSboxWords; i += 4 * blockDim.x) {
+            const uint32_t v = g_base[512 + (i >> 5)];
+            *reinterpret_cast<u32x4 *>(lds + (kInvSboxAddr >> 2) + i) = vec4(v, v, v, v);
+        }
+    }
 }
 
 // Streaming 16-byte accesses: every byte is touched exactly once, so they are
