@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--cpu-sample-mib", type=int, default=32)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--served-requests", type=int, default=20000)
     return ap.parse_args()
 
@@ -121,6 +122,27 @@ def cpu_baseline(sample_bytes):
             "sample": "AES-128 ECB encrypt of the first %d MiB of the same seeded input, "
                       "%d pthreads (contiguous whole-block chunks), median of 3 runs, %.2f s each"
                       % (sample_bytes >> 20, threads, s)}
+
+
+def bench_size_sweep(torch, A, dev, stream, sizes=(1 << 24, 1 << 28, 1 << 32)):
+    """AES-256 ECB and CTR encryption of 16 MiB, 256 MiB and 4 GiB buffers of
+    seeded random bytes, as the paper sweeps file size: GB/s per size."""
+    key = seedgen.key(3, 0, 256)
+    ctr0 = seedgen.nonce(3, 0)
+    rk, nr = A.aes_expand_key(key)
+    x = seedgen.data_torch(3, 0, max(sizes), dev)
+    y = torch.empty_like(x)
+    rows = []
+    for n in sizes:
+        for mode in ("ecb", "ctr"):
+            reps = max(5, min(200, (1 << 31) // n))
+            _, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0,
+                                                                       stream=stream), reps, 3)
+            rows.append({"bytes": n, "mode": mode, "GB/s": round(n / k / 1e9, 1),
+                         "launch": A.aes_get_launch(n, mode, False, nr)})
+    del x, y
+    torch.cuda.empty_cache()
+    return {"workload": "AES-256 encrypt, ECB and CTR, 16 MiB / 256 MiB / 4 GiB", "points": rows}
 
 
 def bench_batched(torch, A, dev, stream, reps=5):
@@ -295,6 +317,9 @@ def main():
         w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, 2)
         sec["copy_kernel"] = {"GB/s (read+write)": round(2 * n / k / 1e9, 1)}
         out["secondary"] = sec
+
+    if not args.no_sweep:
+        out["size_sweep"] = bench_size_sweep(torch, A, dev, stream)
 
     if not args.no_batched:
         out["batched"] = bench_batched(torch, A, dev, stream)
