@@ -176,9 +176,12 @@ __device__ __forceinline__ void encrypt_planes(uint32_t (&st)[128], const uint32
 
 // Every wave takes 2048 consecutive blocks per step: lane l holds blocks
 // base + 64 t + l for t = 0..31, so each of the 32 loads per word position is
-// one coalesced 1 KiB access of the wave.
+// one coalesced 1 KiB access of the wave.  One wave per SIMD: the 128-plane
+// state plus the circuit's temporaries then fit in the unified register file
+// (what does not fit in VGPRs goes to AGPRs rather than to scratch memory),
+// which measured faster than two waves per SIMD with scratch spills.
 template <int NR, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void bitslice_kernel(const CipherArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t nfull = a.nbytes >> 4;

@@ -306,6 +306,7 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
                                      ? uint32_t(nfull - base) : 0xFFFFFFFFu;
         uint32_t s[BPT][4];
         u32x4 x[BPT];
+        const uint32_t cstep = c0 + uint32_t(base);   // CTR: counter value of block `base`
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
             const uint32_t jj = uint32_t(i) * 64u + lane;
@@ -319,17 +320,47 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
                 s[i][1] = x[i].y ^ rk[1];
                 s[i][2] = x[i].z ^ rk[2];
                 s[i][3] = x[i].w ^ rk[3];
-            } else {
-                // counter block j: nonce || big-endian (c0 + j) mod 2^32;
-                // round 1 needs only the four lookups on column 3.
-                const uint32_t v3 = bswap(c0 + uint32_t(base) + jj) ^ rk[3];
+            }
+        }
+        if (MODE == MODE_ECB) {
+            rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, 1);
+        } else if (((cstep & 255u) + 64u * BPT) <= 256u) {
+            // All counters of this step share bytes 0..2 (the top 24 bits of
+            // c0 + j): columns 1..3 after round 1 are the same for every
+            // block, and so are 12 of round 2's 16 lookups.  Those 15
+            // lookups are done once for the step; each block needs one
+            // lookup in round 1 and four in round 2.
+            const uint32_t g3 = bswap(cstep) ^ rk[3];
+            const uint32_t t1 = pre1 ^ tl<LAYOUT, 2, 2>(lds, lc, g3);
+            const uint32_t t2 = pre2 ^ tl<LAYOUT, 1, 1>(lds, lc, g3);
+            const uint32_t t3 = pre3 ^ tl<LAYOUT, 0, 0>(lds, lc, g3);
+            const uint32_t q0 = tl<LAYOUT, 1, 1>(lds, lc, t1) ^ tl<LAYOUT, 2, 2>(lds, lc, t2) ^ tl<LAYOUT, 3, 3>(lds, lc, t3) ^ rk[8];
+            const uint32_t q1 = tl<LAYOUT, 0, 0>(lds, lc, t1) ^ tl<LAYOUT, 1, 1>(lds, lc, t2) ^ tl<LAYOUT, 2, 2>(lds, lc, t3) ^ rk[9];
+            const uint32_t q2 = tl<LAYOUT, 0, 0>(lds, lc, t2) ^ tl<LAYOUT, 1, 1>(lds, lc, t3) ^ tl<LAYOUT, 3, 3>(lds, lc, t1) ^ rk[10];
+            const uint32_t q3 = tl<LAYOUT, 0, 0>(lds, lc, t3) ^ tl<LAYOUT, 2, 2>(lds, lc, t1) ^ tl<LAYOUT, 3, 3>(lds, lc, t2) ^ rk[11];
+#pragma unroll
+            for (int i = 0; i < BPT; i++) {
+                const uint32_t v3 = bswap(cstep + uint32_t(i) * 64u + lane) ^ rk[3];
+                const uint32_t t0 = pre0 ^ tl<LAYOUT, 3, 3>(lds, lc, v3);
+                s[i][0] = q0 ^ tl<LAYOUT, 0, 0>(lds, lc, t0);
+                s[i][1] = q1 ^ tl<LAYOUT, 3, 3>(lds, lc, t0);
+                s[i][2] = q2 ^ tl<LAYOUT, 2, 2>(lds, lc, t0);
+                s[i][3] = q3 ^ tl<LAYOUT, 1, 1>(lds, lc, t0);
+            }
+            rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, 3);
+        } else {
+            // counter block j: nonce || big-endian (c0 + j) mod 2^32;
+            // round 1 needs only the four lookups on column 3.
+#pragma unroll
+            for (int i = 0; i < BPT; i++) {
+                const uint32_t v3 = bswap(cstep + uint32_t(i) * 64u + lane) ^ rk[3];
                 s[i][0] = pre0 ^ tl<LAYOUT, 3, 3>(lds, lc, v3);
                 s[i][1] = pre1 ^ tl<LAYOUT, 2, 2>(lds, lc, v3);
                 s[i][2] = pre2 ^ tl<LAYOUT, 1, 1>(lds, lc, v3);
                 s[i][3] = pre3 ^ tl<LAYOUT, 0, 0>(lds, lc, v3);
             }
+            rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, 2);
         }
-        rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, MODE == MODE_CTR ? 2 : 1);
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
             const uint32_t jj = uint32_t(i) * 64u + lane;
