@@ -422,3 +422,34 @@ void ref_ctr(const uint8_t *w, int Nr, const uint8_t ctr0[16], uint64_t first_bl
             out[off + b] = in[off + b] ^ K[b];
     }
 }
+
+/* CBC (SP 800-38A section 6.2).  Encryption: C_j = Cipher(P_j XOR C_{j-1}),
+ * with C_{-1} = IV.  Decryption: P_j = InvCipher(C_j) XOR C_{j-1}.  nbytes
+ * must be a multiple of 16 (no padding); returns -1 otherwise.  dir = 0
+ * encrypts, 1 decrypts.  `in` and `out` must not overlap. */
+int ref_cbc(int dir, const uint8_t *w, int Nr, const uint8_t iv[16], const uint8_t *in, uint8_t *out,
+            size_t nbytes)
+{
+    if (nbytes % 16 != 0)
+        return -1;
+    uint8_t prev[16], x[16];
+    memcpy(prev, iv, 16);
+    for (size_t off = 0; off < nbytes; off += 16) {
+        if (dir == 0) {
+            for (int b = 0; b < 16; b++)
+#ifdef REF_PLANT_CBC_PLAIN
+                x[b] = in[off + b] ^ (off ? in[off - 16 + b] : iv[b]);  /* planted: chains plaintext */
+#else
+                x[b] = in[off + b] ^ prev[b];
+#endif
+            ref_encrypt_block(w, Nr, x, out + off);
+            memcpy(prev, out + off, 16);
+        } else {
+            ref_decrypt_block(w, Nr, in + off, x);
+            for (int b = 0; b < 16; b++)
+                out[off + b] = x[b] ^ prev[b];
+            memcpy(prev, in + off, 16);
+        }
+    }
+    return 0;
+}

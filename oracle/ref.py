@@ -61,6 +61,8 @@ class Oracle:
         lib.ref_ctr_block.argtypes = [_u8p, ctypes.c_uint64, _u8p]
         lib.ref_ctr.argtypes = [_u8p, ctypes.c_int, _u8p, ctypes.c_uint64, _u8p, _u8p,
                                 ctypes.c_size_t]
+        lib.ref_cbc.restype = ctypes.c_int
+        lib.ref_cbc.argtypes = [ctypes.c_int, _u8p, ctypes.c_int, _u8p, _u8p, _u8p, ctypes.c_size_t]
         lib.ref_par_run.restype = ctypes.c_int
         lib.ref_par_run.argtypes = [ctypes.c_int, _u8p, ctypes.c_int, _u8p, _u8p, _u8p,
                                     ctypes.c_size_t, ctypes.c_int,
@@ -140,6 +142,20 @@ class Oracle:
         self.lib.ref_ctr(_ptr(_as_u8(rk)), nr, _ptr(_as_u8(ctr0)), first_block, _ptr(d),
                          _ptr(out), d.size)
         return out
+
+    def cbc(self, decrypt, rk, nr, iv, data):
+        d = _as_u8(data)
+        out = np.empty_like(d)
+        if self.lib.ref_cbc(1 if decrypt else 0, _ptr(_as_u8(rk)), nr, _ptr(_as_u8(iv)), _ptr(d),
+                            _ptr(out), d.size):
+            raise ValueError("CBC length must be a multiple of 16")
+        return out
+
+    def cbc_encrypt(self, rk, nr, iv, data):
+        return self.cbc(False, rk, nr, iv, data)
+
+    def cbc_decrypt(self, rk, nr, iv, data):
+        return self.cbc(True, rk, nr, iv, data)
 
     def par_run(self, op, rk, nr, data, nthreads, ctr0=None, out=None):
         """The paper's pthreads method; returns (output, seconds)."""

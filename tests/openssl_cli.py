@@ -25,7 +25,7 @@ def enc(mode, key, data, iv=None, decrypt=False):
     """``openssl enc -aes-<bits>-<mode>`` on `data`; returns numpy uint8."""
     key = bytes(np.asarray(key, dtype=np.uint8))
     cmd = [OPENSSL, "enc", "-aes-%d-%s" % (8 * len(key), mode), "-K", key.hex()]
-    if mode == "ecb":
+    if mode in ("ecb", "cbc"):
         cmd.append("-nopad")
     if iv is not None:
         cmd += ["-iv", bytes(np.asarray(iv, dtype=np.uint8)).hex()]

@@ -246,8 +246,41 @@ def pin_chunking(o):
     return fails
 
 
+def pin_cbc(o, nkeys=4, blocks=64):
+    """CBC against the openssl executable, both directions, every key size,
+    plus decrypt(encrypt(x)) = x and the structure of the chaining: flipping
+    one ciphertext bit garbles that block and flips the same bit of the next
+    plaintext block only."""
+    fails = []
+    have_openssl = openssl_cli.available()
+    for bits in (128, 192, 256):
+        for i in range(nkeys):
+            k = seedgen.key(71, 100 * bits + i, bits)
+            w, nr = o.expand_key(k)
+            iv = seedgen.bytes_np(seedgen.stream_seed(71, seedgen.TAG_NONCE, 100 * bits + i), 16)
+            pt = seedgen.data_np(71, 100 * bits + i, 16 * blocks)
+            ct = o.cbc_encrypt(w, nr, iv, pt)
+            if have_openssl:
+                if not np.array_equal(ct, openssl_cli.enc("cbc", k, pt, iv=iv)):
+                    fails.append("CBC-%d encrypt vs openssl, key %d" % (bits, i))
+                    break
+                if not np.array_equal(o.cbc_decrypt(w, nr, iv, pt), openssl_cli.enc("cbc", k, pt, iv=iv, decrypt=True)):
+                    fails.append("CBC-%d decrypt vs openssl, key %d" % (bits, i))
+                    break
+            if not np.array_equal(o.cbc_decrypt(w, nr, iv, ct), pt):
+                fails.append("CBC-%d decrypt(encrypt(x)) != x" % bits)
+            bad = ct.copy()
+            bad[16 * 5 + 3] ^= 0x10
+            d = o.cbc_decrypt(w, nr, iv, bad)
+            diff = np.nonzero(d != pt)[0]
+            if not (diff.min() >= 16 * 5 and diff.max() < 16 * 7 and d[16 * 6 + 3] == pt[16 * 6 + 3] ^ 0x10
+                    and (d[16 * 6:16 * 7] != pt[16 * 6:16 * 7]).sum() == 1):
+                fails.append("CBC-%d error propagation" % bits)
+    return fails
+
+
 ALL_PINS = (pin_gf, pin_sbox, pin_mix_columns, pin_shift_rows, pin_key_expansion,
-            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking)
+            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking, pin_cbc)
 
 
 def run_all(o, fast=False):

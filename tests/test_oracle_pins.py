@@ -72,3 +72,7 @@ def test_bad_arguments(o):
         o.ecb_encrypt(w, nr, np.zeros(17, np.uint8))
     with pytest.raises(ValueError):
         o.par_run(0, w, nr, np.zeros(17, np.uint8), 2)
+
+
+def test_cbc(o):
+    assert pins.pin_cbc(o) == []
