@@ -50,7 +50,11 @@ typedef enum {
     AES_E_ARG = 9       /* any other invalid argument                        */
 } aes_status;
 
-typedef enum { AES_MODE_ECB = 0, AES_MODE_CTR = 1 } aes_mode;
+/* ECB and CTR: every block independent.  CBC (SP 800-38A section 6.2, one of
+ * the modes after the paper's): decryption is block-parallel (each block
+ * needs the previous ciphertext block); encryption is serial by definition
+ * and runs on one lane per message. */
+typedef enum { AES_MODE_ECB = 0, AES_MODE_CTR = 1, AES_MODE_CBC = 2 } aes_mode;
 
 /*
  * Key Expansion (FIPS-197 section 5.2; the paper's first step,
@@ -72,8 +76,8 @@ int aes_expand_key(const uint8_t *key, int keybits, uint8_t *roundkeys, int *Nr)
  * applied to every 16-byte block; the paper's Section III-A step list).
  *   in, out    device pointers, 16-byte aligned.  in == out (in place) is
  *              allowed; any other overlap is AES_E_OVERLAP.
- *   nbytes     ECB: a multiple of 16.  CTR: any length; a final partial
- *              block uses the leading bytes of its keystream block.
+ *   nbytes     ECB and CBC: a multiple of 16.  CTR: any length; a final
+ *              partial block uses the leading bytes of its keystream block.
  *              nbytes == 0 returns AES_OK and enqueues nothing.
  *   roundkeys  host pointer to the 16*(Nr+1)-byte ENCRYPTION schedule as
  *              written by aes_expand_key.
@@ -82,8 +86,9 @@ int aes_expand_key(const uint8_t *key, int keybits, uint8_t *roundkeys, int *Nr)
  *   ctr0       CTR: host pointer to the 16-byte initial counter block; block
  *              j uses bytes 0..11 of ctr0 followed by (c0 + j) mod 2^32 in
  *              big-endian order, c0 being the big-endian value of
- *              ctr0[12..15] (no carry into bytes 0..11).  ECB: ignored, may
- *              be NULL.
+ *              ctr0[12..15] (no carry into bytes 0..11).  CBC: host pointer
+ *              to the 16-byte initialization vector.  ECB: ignored, may be
+ *              NULL.
  *   stream     hipStream_t to enqueue on, or NULL.
  */
 int aes_encrypt(const void *in, void *out, size_t nbytes,
@@ -95,7 +100,9 @@ int aes_encrypt(const void *in, void *out, size_t nbytes,
  * equivalent-inverse-cipher form of section 5.3.5.  Same arguments as
  * aes_encrypt; `roundkeys` is still the ENCRYPTION schedule (the decryption
  * schedule is derived inside).  For CTR, decryption is the same operation
- * as encryption.
+ * as encryption.  CBC decryption cannot run in place (in == out gives
+ * AES_E_OVERLAP): block j needs ciphertext block j-1 after other workgroups
+ * may have written their outputs.
  */
 int aes_decrypt(const void *in, void *out, size_t nbytes,
                 const uint8_t *roundkeys, int Nr, int mode,
@@ -175,9 +182,11 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
  * One message of a batch (48 bytes, device-resident array).  The message is
  * nbytes bytes at in_base + in_off, written to out_base + out_off; both
  * offsets are multiples of 16.  Its key is the first 16/24/32 bytes of the
- * 32-byte slot key_idx of the key array.  ECB messages are whole blocks;
- * CTR messages may end in a partial block.  For CTR, ctr0 is the initial
- * counter block exactly as for aes_encrypt.
+ * 32-byte slot key_idx of the key array.  ECB and CBC messages are whole
+ * blocks; CTR messages may end in a partial block.  ctr0 is the initial
+ * counter block (CTR) or the IV (CBC) exactly as for aes_encrypt.  A CBC
+ * decryption whose input and output share bytes is rejected; a CBC
+ * encryption runs serially on one lane.
  */
 typedef struct {
     uint64_t in_off;

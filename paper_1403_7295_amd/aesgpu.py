@@ -29,9 +29,9 @@ AES_E_ARG = 9
 
 AES_MODE_ECB = 0
 AES_MODE_CTR = 1
+AES_MODE_CBC = 2
 
-MODES = {"ecb": AES_MODE_ECB, "ctr": AES_MODE_CTR, AES_MODE_ECB: AES_MODE_ECB,
-         AES_MODE_CTR: AES_MODE_CTR}
+MODES = {"ecb": AES_MODE_ECB, "ctr": AES_MODE_CTR, "cbc": AES_MODE_CBC}
 
 # every function the header declares, with its ctypes signature
 _SIGNATURES = {

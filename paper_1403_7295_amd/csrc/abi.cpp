@@ -160,19 +160,23 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
           int mode, const uint8_t *ctr0, void *stream) {
     if (Nr != 10 && Nr != 12 && Nr != 14)
         return fail(AES_E_NR, "Nr must be 10, 12 or 14");
-    if (mode != AES_MODE_ECB && mode != AES_MODE_CTR)
-        return fail(AES_E_MODE, "mode must be AES_MODE_ECB or AES_MODE_CTR");
+    if (mode != AES_MODE_ECB && mode != AES_MODE_CTR && mode != AES_MODE_CBC)
+        return fail(AES_E_MODE, "mode must be AES_MODE_ECB, AES_MODE_CTR or AES_MODE_CBC");
     if (!roundkeys)
         return fail(AES_E_NULL, "roundkeys must not be NULL");
     if (mode == AES_MODE_CTR && !ctr0)
         return fail(AES_E_NULL, "CTR needs the initial counter block ctr0");
-    if (mode == AES_MODE_ECB && nbytes % 16 != 0)
-        return fail(AES_E_LENGTH, "ECB length must be a multiple of 16 bytes");
+    if (mode == AES_MODE_CBC && !ctr0)
+        return fail(AES_E_NULL, "CBC needs the initialization vector in ctr0");
+    if ((mode == AES_MODE_ECB || mode == AES_MODE_CBC) && nbytes % 16 != 0)
+        return fail(AES_E_LENGTH, "ECB and CBC lengths must be a multiple of 16 bytes");
     if (nbytes == 0)
         return AES_OK;
     int st = check_buffers(in, out, nbytes);
     if (st != AES_OK)
         return st;
+    if (mode == AES_MODE_CBC && decrypt && in == out)
+        return fail(AES_E_OVERLAP, "CBC decryption cannot run in place (block j needs ciphertext j-1)");
     const DeviceState *d = current_device(&st);
     if (!d)
         return st;
@@ -186,7 +190,7 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
     const int nwords = 4 * (Nr + 1);
     for (int i = 0; i < nwords; i++)
         std::memcpy(&w[i], roundkeys + 4 * i, 4);  // bytes in order = little-endian column word
-    const bool dec_cipher = decrypt && mode == AES_MODE_ECB;
+    const bool dec_cipher = decrypt && mode != AES_MODE_CTR;
     if (dec_cipher)
         decryption_schedule(w, Nr, a.rk);
     else
@@ -195,9 +199,19 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
         std::memcpy(a.ctr, ctr0, 12);
         a.ctr[3] = (uint32_t(ctr0[12]) << 24) | (uint32_t(ctr0[13]) << 16) |
                    (uint32_t(ctr0[14]) << 8) | uint32_t(ctr0[15]);
+    } else if (mode == AES_MODE_CBC) {
+        std::memcpy(a.ctr, ctr0, 16);   // the IV as little-endian words
     }
-    const LaunchCfg cfg = choose_launch(*d, nbytes, mode, decrypt && mode == AES_MODE_ECB, Nr);
     hipError_t e;
+    if (mode == AES_MODE_CBC && !decrypt) {
+        // each block depends on the previous ciphertext: one lane, serially
+        e = launch_cbc_encrypt(Nr, a, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess)
+            return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        return AES_OK;
+    }
+    // CBC decryption has the shape of ECB decryption and shares its tuning
+    const LaunchCfg cfg = choose_launch(*d, nbytes, mode == AES_MODE_CBC ? AES_MODE_ECB : mode, dec_cipher, Nr);
     if (cfg.layout == LAYOUT_BITSLICED) {
         if (dec_cipher)
             return fail(AES_E_ARG, "the bitsliced kernel encrypts only (ECB encrypt, CTR)");
@@ -207,9 +221,8 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
             return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
         return AES_OK;
     }
-    e = launch_cipher(Nr, mode == AES_MODE_CTR ? MODE_CTR : MODE_ECB,
-                                 dec_cipher ? DIR_DEC : DIR_ENC, cfg, a,
-                                 static_cast<hipStream_t>(stream));
+    e = launch_cipher(Nr, mode == AES_MODE_CTR ? MODE_CTR : mode == AES_MODE_CBC ? MODE_CBC : MODE_ECB,
+                      dec_cipher ? DIR_DEC : DIR_ENC, cfg, a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     return AES_OK;
@@ -225,7 +238,7 @@ size_t batch_layout(int max_msgs, uint64_t max_total_blocks, int tile_blocks, ui
         *capacity = cap;
     if (cap >= (uint64_t(1) << 32))
         return 0;
-    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 2 * size_t(cap) * sizeof(BatchTile);
+    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(cap) * sizeof(BatchTile);
 }
 
 int batch_args(const aes_batch *b, BatchKArgs *a) {
@@ -413,7 +426,7 @@ int aes_batch_query(const aes_batch *b, void *stream, uint64_t *tiles, uint64_t 
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch query: ") + hipGetErrorString(e));
     if (tiles)
-        *tiles = uint64_t(h.ntiles[0]) + h.ntiles[1];
+        *tiles = uint64_t(h.ntiles[0]) + h.ntiles[1] + h.ntiles[2];
     if (rejected)
         *rejected = h.rejected;
     if (h.overflow)

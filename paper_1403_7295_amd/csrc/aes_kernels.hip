@@ -31,6 +31,19 @@ __global__ __launch_bounds__(1024) void cipher_kernel(const CipherArgs a) {
                                                wave * 64u * BPT, nblk, sweep);
 }
 
+// CBC encryption of one buffer: inherently serial, so lane 0 of the first
+// wave does all of it after the workgroup has staged the tables.
+template <int NR>
+__global__ __launch_bounds__(256) void cbc_encrypt_kernel(const CipherArgs a) {
+    __shared__ uint32_t lds[lds_words<DIR_ENC>()];
+    stage_tables<LAYOUT_T4X32, DIR_ENC>(lds);
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
+    const LaneConsts lc = lane_consts<LAYOUT_T4X32>(0);
+    cbc_encrypt_serial<NR, LAYOUT_T4X32>(lds, lc, a.rk, a.ctr, a.in, a.out, a.nbytes >> 4);
+}
+
 template <int BPT>
 __global__ __launch_bounds__(1024) void copy_kernel(const uint8_t *in, uint8_t *out, uint64_t n16) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -72,6 +85,8 @@ template <int NR>
 KernelFn pick_op(int mode, int dir, int layout, int bi) {
     if (mode == MODE_CTR)
         return pick_layout<NR, MODE_CTR, DIR_ENC>(layout, bi);
+    if (mode == MODE_CBC)   // decryption only: CBC encryption is serial
+        return pick_layout<NR, MODE_CBC, DIR_DEC>(layout, bi);
     return dir == DIR_ENC ? pick_layout<NR, MODE_ECB, DIR_ENC>(layout, bi)
                           : pick_layout<NR, MODE_ECB, DIR_DEC>(layout, bi);
 }
@@ -87,6 +102,13 @@ hipError_t launch_cipher(int nr, int mode, int dir, const LaunchCfg &cfg, const 
                 : nr == 12 ? pick_op<12>(mode, dir, cfg.layout, bi)
                            : pick_op<14>(mode, dir, cfg.layout, bi);
     hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.wg), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cbc_encrypt(int nr, const CipherArgs &a, hipStream_t stream) {
+    void (*fn)(const CipherArgs) = nr == 10 ? cbc_encrypt_kernel<10> : nr == 12 ? cbc_encrypt_kernel<12>
+                                                                               : cbc_encrypt_kernel<14>;
+    hipLaunchKernelGGL(fn, dim3(1), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

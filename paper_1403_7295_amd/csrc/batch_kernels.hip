@@ -34,9 +34,17 @@ __device__ __forceinline__ int desc_nr(const aes_msg_desc &d) { return 10 + 2 * 
 
 // Same test as the host applies to a single-buffer call, plus bounds.
 __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKArgs &a) {
-    if (d.keybits_code > 2 || d.mode > 1 || d.decrypt > 1)
+    if (d.keybits_code > 2 || d.mode > AES_MODE_CBC || d.decrypt > 1)
         return false;
-    if (d.mode == AES_MODE_ECB && (d.nbytes & 15u))
+    if ((d.mode == AES_MODE_ECB || d.mode == AES_MODE_CBC) && (d.nbytes & 15u))
+        return false;
+    // CBC decryption reads block j-1 of the input after other waves may have
+    // written their outputs: input and output must not share bytes
+    if (d.mode == AES_MODE_CBC && d.decrypt && a.in_base == a.out_base && d.nbytes &&
+        d.in_off < d.out_off + d.nbytes && d.out_off < d.in_off + d.nbytes)
+        return false;
+    // a CBC encryption is one serial tile; its block count must fit the tile
+    if (d.mode == AES_MODE_CBC && !d.decrypt && (d.nbytes >> 4) >= 0xFFFFFFFFull)
         return false;
     if ((d.in_off | d.out_off) & 15u)
         return false;
@@ -49,7 +57,11 @@ __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKAr
     return true;
 }
 
+// Forward list (encryption tables): ECB encrypt, CTR.  Inverse list
+// (decryption tables): ECB and CBC decrypt.  Serial list: CBC encrypt.
 __device__ __forceinline__ int desc_class(const aes_msg_desc &d) {
+    if (d.mode == AES_MODE_CBC)
+        return d.decrypt ? 1 : 2;
     return (d.mode == AES_MODE_ECB && d.decrypt) ? 1 : 0;
 }
 
@@ -118,18 +130,20 @@ __global__ __launch_bounds__(256) void keyexp_kernel(const BatchKArgs a) {
 
 __device__ __forceinline__ uint64_t tiles_of(const aes_msg_desc &d, uint32_t tile_blocks) {
     const uint64_t nblk = (d.nbytes + 15) >> 4;
+    if (desc_class(d) == 2)
+        return nblk ? 1 : 0;
     return (nblk + tile_blocks - 1) / tile_blocks;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) {
-    __shared__ uint64_t cnt[2][kPlanThreads];
-    __shared__ uint64_t base[2];
+    __shared__ uint64_t cnt[3][kPlanThreads];
+    __shared__ uint64_t base[3];
     __shared__ uint32_t bad[kPlanThreads];
     const uint32_t n = batch_count(a);
     const uint32_t tid = threadIdx.x;
     const uint32_t per = (n + kPlanThreads - 1) / kPlanThreads;
     const uint32_t m0 = min(n, tid * per), m1 = min(n, m0 + per);
-    uint64_t c[2] = {0, 0};
+    uint64_t c[3] = {0, 0, 0};
     uint32_t rejected = 0;
     for (uint32_t m = m0; m < m1; m++) {
         const aes_msg_desc d = a.desc[m];
@@ -141,9 +155,10 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
     }
     cnt[0][tid] = c[0];
     cnt[1][tid] = c[1];
+    cnt[2][tid] = c[2];
     bad[tid] = rejected;
     __syncthreads();
-    if (tid < 2) {
+    if (tid < 3) {
         // exclusive scan of one class's per-thread counts (1024 adds)
         uint64_t run = 0;
         for (int t = 0; t < kPlanThreads; t++) {
@@ -154,21 +169,24 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
         base[tid] = run;
     }
     __syncthreads();
-    const bool fits0 = base[0] <= a.tile_capacity, fits1 = base[1] <= a.tile_capacity;
-    uint64_t off[2] = {cnt[0][tid], cnt[1][tid]};
+    bool fits[3];
+    for (int k = 0; k < 3; k++)
+        fits[k] = base[k] <= a.tile_capacity;
+    uint64_t off[3] = {cnt[0][tid], cnt[1][tid], cnt[2][tid]};
     for (uint32_t m = m0; m < m1; m++) {
         const aes_msg_desc d = a.desc[m];
         if (!desc_valid(d, a))
             continue;
         const int k = desc_class(d);
-        if (!(k == 0 ? fits0 : fits1))
+        if (!fits[k])
             continue;
         const uint64_t nblk = (d.nbytes + 15) >> 4;
         BatchTile *list = a.tiles + size_t(k) * a.tile_capacity;
-        for (uint64_t first = 0; first < nblk; first += a.tile_blocks) {
+        const uint64_t step = k == 2 ? nblk : a.tile_blocks;   // a serial message is one tile
+        for (uint64_t first = 0; first < nblk; first += step) {
             BatchTile t;
             t.msg = m;
-            t.count = uint32_t(min<uint64_t>(a.tile_blocks, nblk - first));
+            t.count = uint32_t(min<uint64_t>(step, nblk - first));
             t.first = first;
             list[off[k]++] = t;
         }
@@ -178,12 +196,12 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
         for (int t = 0; t < kPlanThreads; t++)
             r += bad[t];
         BatchHeader *h = a.header;
-        h->ntiles[0] = fits0 ? uint32_t(base[0]) : 0u;
-        h->ntiles[1] = fits1 ? uint32_t(base[1]) : 0u;
-        h->next[0] = 0;
-        h->next[1] = 0;
+        for (int k = 0; k < 3; k++) {
+            h->ntiles[k] = fits[k] ? uint32_t(base[k]) : 0u;
+            h->next[k] = 0;
+        }
         h->rejected = r;
-        h->overflow = (fits0 && fits1) ? 0u : 1u;
+        h->overflow = (fits[0] && fits[1] && fits[2]) ? 0u : 1u;
     }
 }
 
@@ -200,6 +218,11 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const LaneConsts &
     for (int i = 0; i < 4 * (NR + 1); i++)
         rk[i] = __builtin_amdgcn_readfirstlane(rkp[i]);
     uint32_t ctr[4] = {0, 0, 0, 0};
+    if (MODE == MODE_CBC) {
+        for (int i = 0; i < 4; i++)
+            ctr[i] = uint32_t(d.ctr0[4 * i]) | (uint32_t(d.ctr0[4 * i + 1]) << 8) |
+                     (uint32_t(d.ctr0[4 * i + 2]) << 16) | (uint32_t(d.ctr0[4 * i + 3]) << 24);
+    }
     if (MODE == MODE_CTR) {
         for (int i = 0; i < 3; i++)
             ctr[i] = uint32_t(d.ctr0[4 * i]) | (uint32_t(d.ctr0[4 * i + 1]) << 8) |
@@ -213,17 +236,68 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const LaneConsts &
                                                      t.first + t.count, 64u * BPT);
 }
 
+// The serial list (CBC encryption): every wave takes 64 messages at a time,
+// one per lane, and each lane encrypts its message block after block with its
+// own round keys.  These run first, so the long serial chains start early and
+// the parallel tiles fill in around them.
+__device__ __forceinline__ void run_serial_tiles(const uint32_t *lds, const BatchKArgs &a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t n = a.header->ntiles[2];
+    const BatchTile *list = a.tiles + size_t(2) * a.tile_capacity;
+    const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
+    for (;;) {
+        uint32_t t0 = 0;
+        if (lane == 0)
+            t0 = atomicAdd(&a.header->next[2], 64u);
+        t0 = __builtin_amdgcn_readfirstlane(t0);
+        if (t0 >= n)
+            break;
+        const uint32_t t = t0 + lane;
+        if (t >= n)
+            continue;
+        const BatchTile tile = list[t];
+        const aes_msg_desc d = a.desc[tile.msg];
+        const uint32_t *rkp = a.keytab + size_t(tile.msg) * kKeySlotWords;
+        uint32_t iv[4];
+        for (int i = 0; i < 4; i++)
+            iv[i] = uint32_t(d.ctr0[4 * i]) | (uint32_t(d.ctr0[4 * i + 1]) << 8) |
+                    (uint32_t(d.ctr0[4 * i + 2]) << 16) | (uint32_t(d.ctr0[4 * i + 3]) << 24);
+        const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
+        uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
+        const int nr = desc_nr(d);
+        uint32_t rk[60];
+        if (nr == 10) {
+#pragma unroll
+            for (int i = 0; i < 44; i++)
+                rk[i] = rkp[i];
+            cbc_encrypt_serial<10, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, tile.count);
+        } else if (nr == 12) {
+#pragma unroll
+            for (int i = 0; i < 52; i++)
+                rk[i] = rkp[i];
+            cbc_encrypt_serial<12, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, tile.count);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 60; i++)
+                rk[i] = rkp[i];
+            cbc_encrypt_serial<14, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, tile.count);
+        }
+    }
+}
+
 template <int CLASS, int BPT>
 __global__ __launch_bounds__(1024) void batch_kernel(const BatchKArgs a) {
     constexpr int DIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
     const uint32_t ntiles = a.header->ntiles[CLASS];
-    if (ntiles == 0)
+    if (ntiles == 0 && (CLASS != 0 || a.header->ntiles[2] == 0))
         return;
     __shared__ uint32_t lds[lds_words<DIR>()];
     stage_tables<LAYOUT_T4X32, DIR>(lds);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
+    if (CLASS == 0)
+        run_serial_tiles(lds, a);
     const BatchTile *list = a.tiles + size_t(CLASS) * a.tile_capacity;
     for (;;) {
         uint32_t t = 0;
@@ -235,7 +309,11 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchKArgs a) {
         const BatchTile tile = list[t];
         const aes_msg_desc d = a.desc[tile.msg];
         const int nr = desc_nr(d);
-        if (CLASS == 1) {
+        if (CLASS == 1 && d.mode == AES_MODE_CBC) {
+            if (nr == 10) run_tile<10, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
+            else if (nr == 12) run_tile<12, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
+            else run_tile<14, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
+        } else if (CLASS == 1) {
             if (nr == 10) run_tile<10, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
             else if (nr == 12) run_tile<12, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
             else run_tile<14, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);

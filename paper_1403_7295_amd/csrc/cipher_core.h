@@ -315,14 +315,14 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
                 x[i] = load16(inb + 16u * jj);
             else if (MODE == MODE_CTR && jj == tail_at)
                 x[i] = load_tail(inb + 16u * jj, tail);
-            if (MODE == MODE_ECB) {
+            if (MODE == MODE_ECB || MODE == MODE_CBC) {
                 s[i][0] = x[i].x ^ rk[0];
                 s[i][1] = x[i].y ^ rk[1];
                 s[i][2] = x[i].z ^ rk[2];
                 s[i][3] = x[i].w ^ rk[3];
             }
         }
-        if (MODE == MODE_ECB) {
+        if (MODE == MODE_ECB || MODE == MODE_CBC) {
             rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, 1);
         } else if (((cstep & 255u) + 64u * BPT) <= 256u) {
             // All counters of this step share bytes 0..2 (the top 24 bits of
@@ -365,15 +365,43 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
         for (int i = 0; i < BPT; i++) {
             const uint32_t jj = uint32_t(i) * 64u + lane;
             u32x4 o;
-            if (MODE == MODE_ECB)
+            if (MODE == MODE_ECB) {
                 o = vec4(s[i][0], s[i][1], s[i][2], s[i][3]);
-            else
+            } else if (MODE == MODE_CBC) {
+                // CBC decryption: P_j = InvCipher(C_j) ^ C_{j-1}, C_{-1} = IV.
+                // The previous block was just loaded by the neighbouring
+                // lane, so this load is served from cache.
+                u32x4 p = vec4(ctr[0], ctr[1], ctr[2], ctr[3]);
+                if (base + jj > 0 && jj < nwhole)
+                    p = load16((inb - 16) + 16u * jj);
+                o = vec4(s[i][0] ^ p.x, s[i][1] ^ p.y, s[i][2] ^ p.z, s[i][3] ^ p.w);
+            } else
                 o = vec4(s[i][0] ^ x[i].x, s[i][1] ^ x[i].y, s[i][2] ^ x[i].z, s[i][3] ^ x[i].w);
             if (jj < nwhole)
                 store16(outb + 16u * jj, o);
             else if (MODE == MODE_CTR && jj == tail_at)
                 store_tail(outb + 16u * jj, o, tail);
         }
+    }
+}
+
+// CBC encryption of one whole message by one lane (each block depends on the
+// previous ciphertext, SP 800-38A section 6.2).  rk holds this lane's round
+// keys (registers), iv the initial chaining value.
+template <int NR, int LAYOUT>
+__device__ __forceinline__ void cbc_encrypt_serial(const uint32_t *lds, const LaneConsts &lc,
+                                                   const uint32_t *rk, const uint32_t *iv,
+                                                   const uint8_t *in, uint8_t *out, uint64_t nblocks) {
+    uint32_t c0 = iv[0], c1 = iv[1], c2 = iv[2], c3 = iv[3];
+    for (uint64_t j = 0; j < nblocks; j++) {
+        const u32x4 x = *reinterpret_cast<const u32x4 *>(in + 16 * j);
+        uint32_t s[1][4] = {{x.x ^ c0 ^ rk[0], x.y ^ c1 ^ rk[1], x.z ^ c2 ^ rk[2], x.w ^ c3 ^ rk[3]}};
+        rounds<NR, DIR_ENC, LAYOUT, 1>(s, lds, lc, rk, 1);
+        c0 = s[0][0];
+        c1 = s[0][1];
+        c2 = s[0][2];
+        c3 = s[0][3];
+        *reinterpret_cast<u32x4 *>(out + 16 * j) = vec4(c0, c1, c2, c3);
     }
 }
 

@@ -27,7 +27,7 @@ uint32_t inv_mix_column_word(uint32_t col);
 void decryption_schedule(const uint32_t *w, int nr, uint32_t *dk);
 
 // ---- kernels (aes_kernels.hip) --------------------------------------------
-enum Mode { MODE_ECB = 0, MODE_CTR = 1 };
+enum Mode { MODE_ECB = 0, MODE_CTR = 1, MODE_CBC = 2 };
 enum Dir { DIR_ENC = 0, DIR_DEC = 1 };
 enum Layout { LAYOUT_T4X32 = 0, LAYOUT_T2X64 = 1 };
 
@@ -38,7 +38,8 @@ struct CipherArgs {
     uint8_t *out;
     uint64_t nbytes;
     uint32_t rk[60];   // round keys in the order the rounds use them
-    uint32_t ctr[4];   // CTR: nonce words 0..2 (little-endian), ctr[3] = c0
+    uint32_t ctr[4];   // CTR: nonce words 0..2 (little-endian), ctr[3] = c0;
+                       // CBC: the IV as four little-endian words
 };
 
 struct LaunchCfg {
@@ -54,18 +55,21 @@ hipError_t upload_tables(const HostTables &t);
 hipError_t launch_cipher(int nr, int mode, int dir, const LaunchCfg &cfg, const CipherArgs &a,
                          hipStream_t stream);
 hipError_t launch_copy(const void *in, void *out, uint64_t nbytes, int grid, hipStream_t stream);
+// CBC encryption is serial: one lane walks the whole buffer.
+hipError_t launch_cbc_encrypt(int nr, const CipherArgs &a, hipStream_t stream);
 // The bitsliced comparison kernel (bitslice.hip): encryption only.
 constexpr int LAYOUT_BITSLICED = 2;
 hipError_t launch_bitslice(int nr, int mode, int grid, const CipherArgs &a, hipStream_t stream);
 
 // ---- batches (batch_kernels.hip) -------------------------------------------
-// Workspace = header | key schedules (max_msgs slots) | tiles[2][capacity].
+// Workspace = header | key schedules (max_msgs slots) | tiles[3][capacity].
 struct BatchHeader {
-    uint32_t ntiles[2];   // forward list (ECB encrypt, CTR), inverse list (ECB decrypt)
-    uint32_t next[2];     // next tile to hand out, per list
+    uint32_t ntiles[3];   // forward list (ECB encrypt, CTR), inverse list (ECB and CBC
+                          // decrypt), serial list (CBC encrypt: one whole message each)
+    uint32_t next[3];     // next tile to hand out, per list
     uint32_t rejected;    // messages whose descriptor failed the checks
     uint32_t overflow;    // 1 if the tiles did not fit the workspace
-    uint32_t pad[58];
+    uint32_t pad[56];
 };
 static_assert(sizeof(BatchHeader) == 256, "header is one 256-byte line");
 

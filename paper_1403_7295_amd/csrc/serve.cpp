@@ -333,10 +333,10 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
         const aes_request &q = reqs[i];
         if (i && q.arrival_s < reqs[i - 1].arrival_s)
             return serve_fail(AES_E_ARG, "requests must be sorted by arrival_s");
-        if (q.keybits_code > 2 || q.mode > 1 || q.decrypt > 1 || int(q.key_idx) >= nkeys)
+        if (q.keybits_code > 2 || q.mode > AES_MODE_CBC || q.decrypt > 1 || int(q.key_idx) >= nkeys)
             return serve_fail(AES_E_ARG, "request " + std::to_string(i) + ": bad key, mode or direction");
-        if (q.mode == AES_MODE_ECB && q.nbytes % 16)
-            return serve_fail(AES_E_LENGTH, "request " + std::to_string(i) + ": ECB length not whole blocks");
+        if (q.mode != AES_MODE_CTR && q.nbytes % 16)
+            return serve_fail(AES_E_LENGTH, "request " + std::to_string(i) + ": ECB/CBC length not whole blocks");
     }
     const bool sim = cfg->simulate_gbps > 0;
     Loop loop(reqs, nreq, *cfg, L, results);

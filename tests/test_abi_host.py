@@ -77,12 +77,16 @@ def test_argument_checks(A, fn):
 
     assert code(IN, OUT, 32, rk, 11, "ecb") == A.AES_E_NR
     assert code(IN, OUT, 32, rk, nr, 5) == A.AES_E_MODE
+    assert code(IN, OUT, 32, rk, nr, "cbc") == A.AES_E_NULL         # no IV
+    assert code(IN, OUT, 24, rk, nr, "cbc", ctr0=bytes(16)) == A.AES_E_LENGTH
     assert code(IN, OUT, 17, rk, nr, "ecb") == A.AES_E_LENGTH
     assert code(IN, OUT, 32, rk, nr, "ctr") == A.AES_E_NULL          # no counter block
     assert code(None, OUT, 32, rk, nr, "ecb") == A.AES_E_NULL
     assert code(IN + 4, OUT, 32, rk, nr, "ecb") == A.AES_E_ALIGN
     assert code(IN, IN + 16, 64, rk, nr, "ecb") == A.AES_E_OVERLAP
     assert code(IN + 16, IN, 64, rk, nr, "ctr", ctr0=bytes(16)) == A.AES_E_OVERLAP
+    if fn == "aes_decrypt":
+        assert code(IN, IN, 64, rk, nr, "cbc", ctr0=bytes(16)) == A.AES_E_OVERLAP   # not in place
     # empty buffers are a no-op, whatever the pointers
     call(None, None, 0, rk, nr, "ecb", stream=0)
     call(None, None, 0, rk, nr, "ctr", ctr0=bytes(16), stream=0)
@@ -99,9 +103,9 @@ def test_launch_config_validation(A):
 
 def test_batch_workspace_size(A):
     n = A.aes_batch_workspace_size(10, 1000, 100)
-    # header + 10 key slots of 512 bytes + two tile lists of (10 + 10) 16-byte tiles
-    assert n == 256 + 10 * 512 + 2 * 20 * 16
-    assert A.aes_batch_workspace_size(10, 1000, 0) == 256 + 10 * 512 + 2 * (10 + 1) * 16
+    # header + 10 key slots of 512 bytes + three tile lists of (10 + 10) 16-byte tiles
+    assert n == 256 + 10 * 512 + 3 * 20 * 16
+    assert A.aes_batch_workspace_size(10, 1000, 0) == 256 + 10 * 512 + 3 * (10 + 1) * 16
     for bad in ((0, 10, 0), (5, 10, -1)):
         with pytest.raises(A.AESError) as e:
             A.aes_batch_workspace_size(*bad)

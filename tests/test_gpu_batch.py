@@ -26,16 +26,17 @@ def O():
     return ref.default()
 
 
-def mixed_messages(A, n, seed, max_len=1 << 16, min_len=0, mode=None, decrypt=None):
-    """n messages of every kind: ECB encrypt/decrypt and CTR, 128/192/256-bit
-    keys, lengths log-uniform in [1, max_len] (ECB rounded up to whole
-    blocks), a few empty ones (unless min_len > 0), counters that wrap."""
+def mixed_messages(A, n, seed, max_len=1 << 16, min_len=0, mode=None, decrypt=None, modes=3):
+    """n messages of every kind: ECB encrypt/decrypt, CTR and CBC
+    encrypt/decrypt, 128/192/256-bit keys, lengths log-uniform in
+    [1, max_len] (ECB and CBC rounded up to whole blocks), a few empty ones
+    (unless min_len > 0), counters that wrap."""
     rng = np.random.default_rng(seed)
     lens = np.maximum(seedgen.log_uniform_lengths(rng, n, 1, max_len), min_len)
-    mode = rng.integers(0, 2, n) if mode is None else np.full(n, mode)
+    mode = rng.integers(0, modes, n) if mode is None else np.full(n, mode)
     decrypt = rng.integers(0, 2, n) if decrypt is None else np.full(n, decrypt)
     keybits = rng.choice([128, 192, 256], n)
-    lens = np.where(mode == 0, (lens + 15) // 16 * 16, lens)
+    lens = np.where(mode != 1, (lens + 15) // 16 * 16, lens)
     if min_len == 0:
         lens[rng.choice(n, 3, replace=False)] = 0
     keys = np.zeros((n, 32), np.uint8)
@@ -63,6 +64,8 @@ def oracle_message(O, d, key, x):
     rk, nr = O.expand_key(key[:bits // 8])
     if d["mode"] == 0:
         return O.ecb_decrypt(rk, nr, x) if d["decrypt"] else O.ecb_encrypt(rk, nr, x)
+    if d["mode"] == 2:
+        return O.cbc_decrypt(rk, nr, d["ctr0"], x) if d["decrypt"] else O.cbc_encrypt(rk, nr, d["ctr0"], x)
     return O.ctr(rk, nr, d["ctr0"], x)
 
 
@@ -98,7 +101,7 @@ def test_tile_size_and_order_do_not_matter(A, tile_blocks):
 
 
 def test_in_place(A, O):
-    descs, keys = mixed_messages(A, 50, 43)
+    descs, keys = mixed_messages(A, 50, 43, modes=2)   # CBC decryption cannot run in place
     x, xd, _ = buffers(descs, 43)
     A.Batch(descs, keys, xd, xd).run()
     check_against_oracle(O, descs, keys, x, xd.cpu().numpy())
@@ -120,7 +123,7 @@ def test_graph_replay_with_rewritten_descriptors(A, O):
     descs2["in_off"] = descs["in_off"][:30]
     descs2["out_off"] = descs["out_off"][:30]
     descs2["nbytes"] = np.minimum(descs2["nbytes"], descs["nbytes"][:30])
-    descs2["nbytes"] = np.where(descs2["mode"] == 0, descs2["nbytes"] // 16 * 16, descs2["nbytes"])
+    descs2["nbytes"] = np.where(descs2["mode"] != 1, descs2["nbytes"] // 16 * 16, descs2["nbytes"])
     b.set_descs(descs2, keys2)
     yd.fill_(SENTINEL)
     b.launch_graph()
@@ -190,3 +193,28 @@ def test_batch_equals_plain_on_ragged_workload(A, O):
         want = O.encrypt_block(rk, nr, seedgen.data_np(4, 0, 16, offset=o + 16 * j))
         assert np.array_equal(y[o + 16 * j:o + 16 * j + 16].cpu().numpy(), want), (m, j)
     b.close()
+
+
+def test_cbc_in_place_decryption_is_rejected(A, O):
+    descs, keys = mixed_messages(A, 30, 48, mode=2, decrypt=1, min_len=32)
+    x, xd, _ = buffers(descs, 48)
+    b = A.Batch(descs, keys, xd, xd)
+    b.run()
+    tiles, rejected = b.query()
+    assert rejected == 30 and tiles == 0
+    assert np.array_equal(xd.cpu().numpy(), x)
+
+
+def test_many_serial_cbc_messages(A, O):
+    # more CBC-encrypt messages than one wave takes (64 per claim), with
+    # parallel tiles mixed in
+    descs, keys = mixed_messages(A, 200, 49, max_len=1 << 14, min_len=16)
+    descs["mode"][:150] = 2
+    descs["decrypt"][:150] = 0
+    descs["nbytes"][:150] = descs["nbytes"][:150] // 16 * 16     # whole blocks (was CTR for some)
+    x, xd, yd = buffers(descs, 49)
+    b = A.Batch(descs, keys, xd, yd)
+    b.run()
+    tiles, rejected = b.query()
+    assert rejected == 0
+    check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
