@@ -453,3 +453,61 @@ int ref_cbc(int dir, const uint8_t *w, int Nr, const uint8_t iv[16], const uint8
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* XTS (IEEE 1619; NIST SP 800-38E) without ciphertext stealing.          */
+/* ---------------------------------------------------------------------- */
+
+/* Multiplication of a tweak by the primitive element alpha = x in
+ * GF(2^128) with the reduction polynomial x^128 + x^7 + x^2 + x + 1.  The
+ * 16 bytes are a little-endian 128-bit number (byte 0 holds the lowest
+ * coefficients): shift left by one bit, and if a bit falls out of the top,
+ * add x^7 + x^2 + x + 1 (0x87) to byte 0. */
+void ref_xts_mul_alpha(uint8_t t[16])
+{
+    int carry = t[15] >> 7;
+    for (int b = 15; b > 0; b--)
+        t[b] = (uint8_t)((t[b] << 1) | (t[b - 1] >> 7));
+    t[0] = (uint8_t)(t[0] << 1);
+#ifndef REF_PLANT_XTS_NOREDUCE
+    if (carry)
+        t[0] ^= 0x87;
+#else
+    (void)carry;
+#endif
+}
+
+/* XTS-AES over a buffer of data units of unit_bytes bytes each (the last
+ * one may be shorter; every unit is whole 16-byte blocks).  Unit u has the
+ * tweak value i = first_unit + u, written as a 16-byte little-endian number
+ * and encrypted with key 2; block j of the unit uses T_j = Cipher_K2(i) *
+ * alpha^j, and C_j = Cipher_K1(P_j XOR T_j) XOR T_j (decryption: P_j =
+ * InvCipher_K1(C_j XOR T_j) XOR T_j).  w1/w2 are the two key schedules, both
+ * with Nr rounds.  Returns -1 if nbytes or unit_bytes is not a multiple of
+ * 16 or unit_bytes is 0. */
+int ref_xts(int dir, const uint8_t *w1, const uint8_t *w2, int Nr, size_t unit_bytes, uint64_t first_unit,
+            const uint8_t *in, uint8_t *out, size_t nbytes)
+{
+    if (nbytes % 16 != 0 || unit_bytes == 0 || unit_bytes % 16 != 0)
+        return -1;
+    for (size_t u0 = 0, u = 0; u0 < nbytes; u0 += unit_bytes, u++) {
+        uint8_t iv[16], t[16], x[16], y[16];
+        uint64_t i = first_unit + u;
+        for (int b = 0; b < 16; b++)
+            iv[b] = b < 8 ? (uint8_t)(i >> (8 * b)) : 0;
+        ref_encrypt_block(w2, Nr, iv, t);
+        size_t end = u0 + unit_bytes < nbytes ? u0 + unit_bytes : nbytes;
+        for (size_t off = u0; off < end; off += 16) {
+            for (int b = 0; b < 16; b++)
+                x[b] = in[off + b] ^ t[b];
+            if (dir == 0)
+                ref_encrypt_block(w1, Nr, x, y);
+            else
+                ref_decrypt_block(w1, Nr, x, y);
+            for (int b = 0; b < 16; b++)
+                out[off + b] = y[b] ^ t[b];
+            ref_xts_mul_alpha(t);
+        }
+    }
+    return 0;
+}

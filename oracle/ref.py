@@ -63,6 +63,10 @@ class Oracle:
                                 ctypes.c_size_t]
         lib.ref_cbc.restype = ctypes.c_int
         lib.ref_cbc.argtypes = [ctypes.c_int, _u8p, ctypes.c_int, _u8p, _u8p, _u8p, ctypes.c_size_t]
+        lib.ref_xts_mul_alpha.argtypes = [_u8p]
+        lib.ref_xts.restype = ctypes.c_int
+        lib.ref_xts.argtypes = [ctypes.c_int, _u8p, _u8p, ctypes.c_int, ctypes.c_size_t, ctypes.c_uint64,
+                                _u8p, _u8p, ctypes.c_size_t]
         lib.ref_par_run.restype = ctypes.c_int
         lib.ref_par_run.argtypes = [ctypes.c_int, _u8p, ctypes.c_int, _u8p, _u8p, _u8p,
                                     ctypes.c_size_t, ctypes.c_int,
@@ -156,6 +160,19 @@ class Oracle:
 
     def cbc_decrypt(self, rk, nr, iv, data):
         return self.cbc(True, rk, nr, iv, data)
+
+    def xts_mul_alpha(self, t):
+        b = _as_u8(t).copy()
+        self.lib.ref_xts_mul_alpha(_ptr(b))
+        return b
+
+    def xts(self, decrypt, rk1, rk2, nr, unit_bytes, first_unit, data):
+        d = _as_u8(data)
+        out = np.empty_like(d)
+        if self.lib.ref_xts(1 if decrypt else 0, _ptr(_as_u8(rk1)), _ptr(_as_u8(rk2)), nr, unit_bytes,
+                            first_unit, _ptr(d), _ptr(out), d.size):
+            raise ValueError("XTS lengths must be multiples of 16")
+        return out
 
     def par_run(self, op, rk, nr, data, nthreads, ctr0=None, out=None):
         """The paper's pthreads method; returns (output, seconds)."""

@@ -279,8 +279,70 @@ def pin_cbc(o, nkeys=4, blocks=64):
     return fails
 
 
+# --- an independent GF(2^128) for XTS: Python integers ---------------------
+XTS_POLY = (1 << 128) | 0x87          # x^128 + x^7 + x^2 + x + 1
+
+
+def gf128_mulx_int(t):
+    t <<= 1
+    return t ^ XTS_POLY if t >> 128 else t
+
+
+def gf128_mul_int(a, b):
+    """Carry-less product reduced by the XTS polynomial (bit k = x^k)."""
+    p = 0
+    for k in range(128):
+        if (b >> k) & 1:
+            p ^= a << k
+    for k in range(254, 127, -1):
+        if (p >> k) & 1:
+            p ^= XTS_POLY << (k - 128)
+    return p
+
+
+def pin_xts(o):
+    """XTS rebuilt block by block from pinned pieces: T_j from the ECB
+    encryption (pinned against openssl) of the little-endian unit number and
+    an independent GF(2^128) (Python integers: x^j by repeated doubling, and
+    by a general carry-less product with x^j), each block through ECB.  No
+    external XTS implementation is available here, so the conventions (byte
+    order of the tweak, placement of alpha) are the standard's as read."""
+    fails = []
+    for k in range(200):
+        t = int.from_bytes(seedgen.bytes_np(seedgen.stream_seed(81, seedgen.TAG_DATA, k), 16).tobytes(), "little")
+        want = gf128_mulx_int(t).to_bytes(16, "little")
+        got = bytes(o.xts_mul_alpha(np.frombuffer(t.to_bytes(16, "little"), np.uint8)))
+        if got != want:
+            fails.append("alpha multiplication")
+            break
+    for bits in (128, 256):
+        k1, k2 = seedgen.key(82, bits, bits), seedgen.key(82, bits + 1, bits)
+        w1, nr = o.expand_key(k1)
+        w2, _ = o.expand_key(k2)
+        for unit, nblocks, first in ((512, 80, 7), (4096, 300, 1 << 40), (16, 5, 0)):
+            pt = seedgen.data_np(82, unit + bits, 16 * nblocks)
+            ct = o.xts(False, w1, w2, nr, unit, first, pt)
+            want = np.empty_like(pt)
+            for j in range(nblocks):
+                u, jj = divmod(16 * j, unit)
+                iv = np.frombuffer((first + u).to_bytes(16, "little"), np.uint8)
+                t0 = int.from_bytes(o.encrypt_block(w2, nr, iv).tobytes(), "little")
+                e = jj // 16
+                # x^e: a general product for e < 128, repeated doubling beyond
+                tj = gf128_mul_int(t0, 1 << e) if e < 128 else t0
+                for _ in range(e if e >= 128 else 0):
+                    tj = gf128_mulx_int(tj)
+                tb = np.frombuffer(tj.to_bytes(16, "little"), np.uint8)
+                want[16 * j:16 * j + 16] = o.encrypt_block(w1, nr, pt[16 * j:16 * j + 16] ^ tb) ^ tb
+            if not np.array_equal(ct, want):
+                fails.append("XTS-%d unit %d" % (bits, unit))
+            if not np.array_equal(o.xts(True, w1, w2, nr, unit, first, ct), pt):
+                fails.append("XTS-%d decrypt(encrypt(x)) != x" % bits)
+    return fails
+
+
 ALL_PINS = (pin_gf, pin_sbox, pin_mix_columns, pin_shift_rows, pin_key_expansion,
-            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking, pin_cbc)
+            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking, pin_cbc, pin_xts)
 
 
 def run_all(o, fast=False):

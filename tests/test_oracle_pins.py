@@ -76,3 +76,23 @@ def test_bad_arguments(o):
 
 def test_cbc(o):
     assert pins.pin_cbc(o) == []
+
+
+def test_xts(o):
+    assert pins.pin_xts(o) == []
+
+
+def test_gf128_reference_is_a_field_multiplication():
+    # the test-side GF(2^128) itself: commutative, distributive, x * x^127 = x^128
+    import random
+    rnd = random.Random(5)
+    for _ in range(20):
+        a, b, c = (rnd.getrandbits(128) for _ in range(3))
+        assert pins.gf128_mul_int(a, b) == pins.gf128_mul_int(b, a)
+        assert pins.gf128_mul_int(a, b ^ c) == pins.gf128_mul_int(a, b) ^ pins.gf128_mul_int(a, c)
+    assert pins.gf128_mul_int(2, 1 << 127) == 0x87
+    t = rnd.getrandbits(128)
+    x = t
+    for _ in range(37):
+        x = pins.gf128_mulx_int(x)
+    assert x == pins.gf128_mul_int(t, 1 << 37)

@@ -19,6 +19,7 @@ PLANTS = {
     "REF_PLANT_LASTKEY": "final AddRoundKey dropped",
     "REF_PLANT_CTR_LE": "CTR counter stored little-endian",
     "REF_PLANT_CBC_PLAIN": "CBC chains the previous plaintext instead of the ciphertext",
+    "REF_PLANT_XTS_NOREDUCE": "XTS tweak doubling without the reduction",
 }
 
 
