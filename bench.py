@@ -314,6 +314,17 @@ def main():
                 sec[name] = {"GB/s": round(n / k / 1e9, 1)}
         finally:
             A.aes_set_launch(None)
+        # XTS over 512-byte and 4 KiB data units (tweak key: the next seeded key)
+        for bits, key in ((128, key128), (256, key256)):
+            rk1, nr = A.aes_expand_key(key)
+            rk2, _ = A.aes_expand_key(seedgen.key(2, 1, bits))
+            for unit in (512, 4096):
+                for dec in (False, True):
+                    fn = A.aes_xts_decrypt if dec else A.aes_xts_encrypt
+                    w, k = timed_launches(torch, stream,
+                                          lambda: fn(x, y, n, rk1, rk2, nr, unit, 0, stream=stream), 10, 2)
+                    sec["xts%d_%s_unit%d" % (bits, "dec" if dec else "enc", unit)] = {
+                        "GB/s": round(n / k / 1e9, 1)}
         w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, 2)
         sec["copy_kernel"] = {"GB/s (read+write)": round(2 * n / k / 1e9, 1)}
         out["secondary"] = sec

@@ -108,6 +108,38 @@ int aes_decrypt(const void *in, void *out, size_t nbytes,
                 const uint8_t *roundkeys, int Nr, int mode,
                 const uint8_t *ctr0, void *stream);
 
+/*
+ * XTS-AES (IEEE 1619; NIST SP 800-38E), the storage mode after the paper's
+ * (its motivating use is encrypting stored files).  The buffer is a run of
+ * data units ("sectors") of unit_bytes each; unit u has the tweak value
+ * i = first_unit + u (mod 2^64), taken as a 16-byte little-endian number.
+ * Block j of a unit (j counted from 0 within the unit) is
+ *     C_j = Cipher_K1(P_j ^ T_j) ^ T_j,  T_j = Cipher_K2(i) * alpha^j,
+ * the product in GF(2^128) modulo x^128 + x^7 + x^2 + x + 1 with the
+ * standard's little-endian bit order (alpha = x).  Decryption uses
+ * InvCipher_K1 with the same T_j.
+ *   in, out          device pointers, 16-byte aligned; in == out allowed,
+ *                    any other overlap is AES_E_OVERLAP.
+ *   nbytes           a multiple of 16 (no ciphertext stealing); the last
+ *                    unit may be shorter than unit_bytes.  0 enqueues
+ *                    nothing.
+ *   roundkeys1/2     host pointers to the ENCRYPTION schedules of the data
+ *                    key K1 and the tweak key K2 (aes_expand_key output),
+ *                    both with Nr rounds (the standard names AES-128 and
+ *                    AES-256; Nr = 12 is accepted and computed the same way).
+ *   unit_bytes       a power of two from 16 to 4096.
+ *   first_unit       tweak value of the buffer's first unit.
+ *   stream           hipStream_t or NULL.
+ * Errors: AES_E_NULL, AES_E_NR, AES_E_LENGTH (nbytes), AES_E_ARG
+ * (unit_bytes), AES_E_ALIGN, AES_E_OVERLAP, AES_E_DEVICE.
+ */
+int aes_xts_encrypt(const void *in, void *out, size_t nbytes,
+                    const uint8_t *roundkeys1, const uint8_t *roundkeys2, int Nr,
+                    size_t unit_bytes, uint64_t first_unit, void *stream);
+int aes_xts_decrypt(const void *in, void *out, size_t nbytes,
+                    const uint8_t *roundkeys1, const uint8_t *roundkeys2, int Nr,
+                    size_t unit_bytes, uint64_t first_unit, void *stream);
+
 /* Message for the last non-zero status returned on this thread. */
 const char *aes_last_error(void);
 

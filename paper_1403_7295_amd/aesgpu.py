@@ -43,6 +43,12 @@ _SIGNATURES = {
     "aes_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "aes_xts_encrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_size_t, ctypes.c_uint64, ctypes.c_void_p]),
+    "aes_xts_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_size_t, ctypes.c_uint64, ctypes.c_void_p]),
     "aes_last_error": (ctypes.c_char_p, []),
     "aes_set_launch": (ctypes.c_int, [ctypes.c_void_p]),
     "aes_get_launch": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -217,6 +223,28 @@ def aes_encrypt(inp, out, nbytes, roundkeys, Nr, mode, ctr0=None, stream=None):
 def aes_decrypt(inp, out, nbytes, roundkeys, Nr, mode, ctr0=None, stream=None):
     """Enqueue decryption of nbytes of device buffer `inp` into `out`."""
     return _crypt(lib.aes_decrypt, inp, out, nbytes, roundkeys, Nr, mode, ctr0, stream)
+
+
+def _xts(fn, inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, first_unit, stream):
+    rk1, rk2 = _host_bytes(roundkeys1), _host_bytes(roundkeys2)
+    if nbytes is None:
+        nbytes = inp.numel() * inp.element_size()
+    _check(fn(_dptr(inp), _dptr(out), nbytes, _hptr(rk1), _hptr(rk2), Nr, unit_bytes, first_unit,
+              _stream_handle(stream, inp)))
+    return out
+
+
+def aes_xts_encrypt(inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, first_unit=0, stream=None):
+    """Enqueue XTS encryption of nbytes (data units of unit_bytes; tweak
+    values first_unit, first_unit + 1, ...)."""
+    return _xts(lib.aes_xts_encrypt, inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes,
+                first_unit, stream)
+
+
+def aes_xts_decrypt(inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, first_unit=0, stream=None):
+    """Enqueue XTS decryption; the arguments of aes_xts_encrypt."""
+    return _xts(lib.aes_xts_decrypt, inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes,
+                first_unit, stream)
 
 
 def aes_last_error():

@@ -3,6 +3,7 @@
 // the key schedule.  No call here allocates device memory.
 #include "aesgpu.h"
 
+#include <algorithm>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -53,6 +54,8 @@ void init_device(int dev) {
     e = upload_tables(host_tables());
     if (e == hipSuccess)
         e = upload_tables_batch(host_tables());
+    if (e == hipSuccess)
+        e = upload_tables_xts(host_tables());
     if (e != hipSuccess) {
         d.error = std::string("table upload: ") + hipGetErrorString(e);
         return;
@@ -228,6 +231,56 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
     return AES_OK;
 }
 
+int xts_crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *rk1, const uint8_t *rk2,
+              int Nr, size_t unit_bytes, uint64_t first_unit, void *stream) {
+    if (Nr != 10 && Nr != 12 && Nr != 14)
+        return fail(AES_E_NR, "Nr must be 10, 12 or 14");
+    if (!rk1 || !rk2)
+        return fail(AES_E_NULL, "roundkeys1 and roundkeys2 must not be NULL");
+    if (unit_bytes < 16 || unit_bytes > 4096 || (unit_bytes & (unit_bytes - 1)) != 0)
+        return fail(AES_E_ARG, "unit_bytes must be a power of two from 16 to 4096");
+    if (nbytes % 16 != 0)
+        return fail(AES_E_LENGTH, "XTS length must be a multiple of 16 bytes (no ciphertext stealing)");
+    if (nbytes == 0)
+        return AES_OK;
+    int st = check_buffers(in, out, nbytes);
+    if (st != AES_OK)
+        return st;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+
+    XtsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.in = static_cast<const uint8_t *>(in);
+    a.out = static_cast<uint8_t *>(out);
+    a.nbytes = nbytes;
+    a.first_unit = first_unit;
+    uint32_t shift = 0;
+    while ((uint64_t(16) << shift) < unit_bytes)
+        shift++;
+    a.unit_shift = shift;
+    uint32_t w[60];
+    const int nwords = 4 * (Nr + 1);
+    for (int i = 0; i < nwords; i++)
+        std::memcpy(&w[i], rk1 + 4 * i, 4);
+    if (decrypt)
+        decryption_schedule(w, Nr, a.rk1);
+    else
+        std::memcpy(a.rk1, w, 4 * nwords);
+    for (int i = 0; i < nwords; i++)
+        std::memcpy(&a.rk2[i], rk2 + 4 * i, 4);
+    // one 1024-thread workgroup per CU, fewer if the buffer has fewer
+    // groups of 64 units than the grid has waves
+    const uint64_t nunits = ((nbytes >> 4) + (uint64_t(1) << shift) - 1) >> shift;
+    const uint64_t groups = (nunits + 63) / 64;
+    const int grid = int(std::min<uint64_t>(uint64_t(d->cus), (groups + 15) / 16));
+    hipError_t e = launch_xts(Nr, decrypt ? DIR_DEC : DIR_ENC, grid, a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
 constexpr int kDefaultTileBlocks = 8192;  // 128 KiB of data per tile
 
 // Tile capacity and workspace bytes for a batch shape; 0 bytes if too big.
@@ -321,6 +374,16 @@ int aes_encrypt(const void *in, void *out, size_t nbytes, const uint8_t *roundke
 int aes_decrypt(const void *in, void *out, size_t nbytes, const uint8_t *roundkeys, int Nr, int mode,
                 const uint8_t *ctr0, void *stream) {
     return crypt(1, in, out, nbytes, roundkeys, Nr, mode, ctr0, stream);
+}
+
+int aes_xts_encrypt(const void *in, void *out, size_t nbytes, const uint8_t *roundkeys1,
+                    const uint8_t *roundkeys2, int Nr, size_t unit_bytes, uint64_t first_unit, void *stream) {
+    return xts_crypt(0, in, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, first_unit, stream);
+}
+
+int aes_xts_decrypt(const void *in, void *out, size_t nbytes, const uint8_t *roundkeys1,
+                    const uint8_t *roundkeys2, int Nr, size_t unit_bytes, uint64_t first_unit, void *stream) {
+    return xts_crypt(1, in, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, first_unit, stream);
 }
 
 const char *aes_last_error(void) { return g_error.c_str(); }

@@ -61,6 +61,19 @@ hipError_t launch_cbc_encrypt(int nr, const CipherArgs &a, hipStream_t stream);
 constexpr int LAYOUT_BITSLICED = 2;
 hipError_t launch_bitslice(int nr, int mode, int grid, const CipherArgs &a, hipStream_t stream);
 
+// ---- XTS (xts.hip) ------------------------------------------------------------
+struct XtsArgs {
+    const uint8_t *in;
+    uint8_t *out;
+    uint64_t nbytes;       // a multiple of 16
+    uint64_t first_unit;   // tweak value of the first data unit
+    uint32_t unit_shift;   // log2 of the blocks per data unit, 0..8
+    uint32_t rk1[60];      // data key, in the order the rounds use it (direction's schedule)
+    uint32_t rk2[60];      // tweak key, encryption schedule
+};
+hipError_t upload_tables_xts(const HostTables &t);
+hipError_t launch_xts(int nr, int dir, int grid, const XtsArgs &a, hipStream_t stream);
+
 // ---- batches (batch_kernels.hip) -------------------------------------------
 // Workspace = header | key schedules (max_msgs slots) | tiles[3][capacity].
 struct BatchHeader {

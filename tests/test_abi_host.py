@@ -92,6 +92,28 @@ def test_argument_checks(A, fn):
     call(None, None, 0, rk, nr, "ctr", ctr0=bytes(16), stream=0)
 
 
+@pytest.mark.parametrize("fn", ["aes_xts_encrypt", "aes_xts_decrypt"])
+def test_xts_argument_checks(A, fn):
+    rk, nr = A.aes_expand_key(np.zeros(32, np.uint8))
+    call = getattr(A, fn)
+
+    def code(*args, **kw):
+        with pytest.raises(A.AESError) as e:
+            call(*args, stream=0, **kw)
+        return e.value.code
+
+    assert code(IN, OUT, 512, rk, rk, 11, 512) == A.AES_E_NR
+    assert code(IN, OUT, 512, None, rk, nr, 512) == A.AES_E_NULL
+    assert code(IN, OUT, 512, rk, None, nr, 512) == A.AES_E_NULL
+    for unit in (0, 8, 48, 520, 8192):
+        assert code(IN, OUT, 512, rk, rk, nr, unit) == A.AES_E_ARG
+    assert code(IN, OUT, 520, rk, rk, nr, 512) == A.AES_E_LENGTH     # no ciphertext stealing
+    assert code(None, OUT, 512, rk, rk, nr, 512) == A.AES_E_NULL
+    assert code(IN + 8, OUT, 512, rk, rk, nr, 512) == A.AES_E_ALIGN
+    assert code(IN, IN + 16, 512, rk, rk, nr, 512) == A.AES_E_OVERLAP
+    call(None, None, 0, rk, rk, nr, 4096, stream=0)                 # empty: a no-op
+
+
 def test_launch_config_validation(A):
     for bad in ({"layout": 3}, {"blocks_per_thread": 3}, {"wg_size": 100}, {"grid": -1}):
         with pytest.raises(A.AESError) as e:
