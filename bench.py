@@ -325,6 +325,12 @@ def main():
                                           lambda: fn(x, y, n, rk1, rk2, nr, unit, 0, stream=stream), 10, 2)
                     sec["xts%d_%s_unit%d" % (bits, "dec" if dec else "enc", unit)] = {
                         "GB/s": round(n / k / 1e9, 1)}
+        # one GPU's share of the 1 GiB job if it were split over eight GPUs
+        rk, nr = A.aes_expand_key(key128)
+        share = n // 8
+        w, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, share, rk, nr, A.AES_MODE_ECB,
+                                                                    stream=stream), 40, 5)
+        sec["aes128_ecb_enc_eighth_share"] = {"bytes": share, "GB/s": round(share / k / 1e9, 1)}
         w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, 2)
         sec["copy_kernel"] = {"GB/s (read+write)": round(2 * n / k / 1e9, 1)}
         out["secondary"] = sec

@@ -1,6 +1,6 @@
 /*
  * Oracle: a plain, slow, byte-oriented CPU implementation of AES (FIPS-197)
- * in ECB and CTR mode.
+ * in ECB and CTR mode, and in the modes after the paper's: CBC, XTS and GCM.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
  * load this file.  Its users are the tests, the package's smoke check and the
@@ -23,7 +23,9 @@
  *   - Modes: the paper encrypts independent chunks and concatenates them
  *     (Section IV), which is ECB; CTR follows NIST SP 800-38A section 6.5
  *     with a 96-bit nonce and a 32-bit big-endian block counter that wraps
- *     modulo 2^32 without carrying into the nonce.
+ *     modulo 2^32 without carrying into the nonce.  CBC is SP 800-38A
+ *     section 6.2, XTS is IEEE 1619 (SP 800-38E) without ciphertext
+ *     stealing, GCM is SP 800-38D sections 6 and 7.
  *
  * Style: every step is a separate function on a 4x4 byte state s[r][c]
  * (row r, column c), exactly as the standard draws it.  No T-tables, no word
@@ -510,4 +512,151 @@ int ref_xts(int dir, const uint8_t *w1, const uint8_t *w2, int Nr, size_t unit_b
         }
     }
     return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* GCM (NIST SP 800-38D): CTR encryption plus the GHASH authenticator.    */
+/* ---------------------------------------------------------------------- */
+
+/* Product of two blocks in GF(2^128) (SP 800-38D section 6.3, the
+ * bit-serial method).  The standard's bit order: bit 0 of a block is the
+ * most significant bit of byte 0 and is the coefficient of x^0.  For each
+ * bit x_i of X (i = 0..127), Z gains V when x_i is set, then V is
+ * multiplied by x: shifted one bit towards the end of the block, and if the
+ * bit that fell off (the coefficient of x^127) was set, R = 11100001 || 0^120
+ * is added. */
+void ref_gcm_mul(const uint8_t X[16], const uint8_t Y[16], uint8_t Z[16])
+{
+    uint8_t V[16], acc[16];
+    memset(acc, 0, 16);
+    memcpy(V, Y, 16);
+    for (int i = 0; i < 128; i++) {
+        if ((X[i / 8] >> (7 - i % 8)) & 1)
+            for (int b = 0; b < 16; b++)
+                acc[b] ^= V[b];
+        int lsb = V[15] & 1;
+        for (int b = 15; b > 0; b--)
+            V[b] = (uint8_t)((V[b] >> 1) | (V[b - 1] << 7));
+        V[0] >>= 1;
+        if (lsb)
+#ifdef REF_PLANT_GCM_R
+            V[15] ^= 0x87;            /* planted: XTS's constant at the wrong end */
+#else
+            V[0] ^= 0xe1;
+#endif
+    }
+    memcpy(Z, acc, 16);
+}
+
+/* GHASH (SP 800-38D section 6.4) continued over nblocks 16-byte blocks:
+ * Y = (Y XOR X_i) * H for each block in turn.  Y is the running value (all
+ * zero at the start of a GHASH). */
+void ref_ghash(const uint8_t H[16], const uint8_t *X, size_t nblocks, uint8_t Y[16])
+{
+    for (size_t i = 0; i < nblocks; i++) {
+        uint8_t t[16];
+        for (int b = 0; b < 16; b++)
+            t[b] = Y[b] ^ X[16 * i + b];
+        ref_gcm_mul(t, H, Y);
+    }
+}
+
+/* GHASH over a byte string padded with zeros to a whole number of blocks. */
+static void ghash_padded(const uint8_t H[16], const uint8_t *X, size_t n, uint8_t Y[16])
+{
+    ref_ghash(H, X, n / 16, Y);
+    if (n % 16) {
+        uint8_t last[16];
+        memset(last, 0, 16);
+        memcpy(last, X + n - n % 16, n % 16);
+        ref_ghash(H, last, 1, Y);
+    }
+}
+
+static void put_be64(uint8_t *p, uint64_t v)
+{
+    for (int b = 0; b < 8; b++)
+        p[b] = (uint8_t)(v >> (56 - 8 * b));
+}
+
+/* The pre-counter block J0 (SP 800-38D section 7.1, step 2): for a 96-bit
+ * IV, IV || 0^31 || 1; otherwise GHASH_H(IV || 0^(s+64) || [len(IV)]_64),
+ * the IV padded with zeros to whole blocks and followed by a block holding
+ * its length in bits. */
+void ref_gcm_j0(const uint8_t H[16], const uint8_t *iv, size_t iv_bytes, uint8_t J0[16])
+{
+    if (iv_bytes == 12) {
+        memcpy(J0, iv, 12);
+        J0[12] = 0; J0[13] = 0; J0[14] = 0; J0[15] = 1;
+        return;
+    }
+    uint8_t lenblk[16];
+    memset(J0, 0, 16);
+    ghash_padded(H, iv, iv_bytes, J0);
+    memset(lenblk, 0, 16);
+    put_be64(lenblk + 8, 8 * (uint64_t)iv_bytes);
+    ref_ghash(H, lenblk, 1, J0);
+}
+
+/* The GCM tag before truncation: S = GHASH_H(A || 0^v || C || 0^u ||
+ * [len(A)]_64 || [len(C)]_64) and T = Cipher(J0) XOR S (SP 800-38D section
+ * 7.1, steps 5 and 6; lengths in bits). */
+static void gcm_tag(const uint8_t *w, int Nr, const uint8_t H[16], const uint8_t J0[16],
+                    const uint8_t *aad, size_t aad_bytes, const uint8_t *c, size_t nbytes, uint8_t T[16])
+{
+    uint8_t S[16], lenblk[16], E[16];
+    memset(S, 0, 16);
+    ghash_padded(H, aad, aad_bytes, S);
+    ghash_padded(H, c, nbytes, S);
+#ifdef REF_PLANT_GCM_LEN
+    put_be64(lenblk, (uint64_t)aad_bytes);          /* planted: lengths in bytes */
+    put_be64(lenblk + 8, (uint64_t)nbytes);
+#else
+    put_be64(lenblk, 8 * (uint64_t)aad_bytes);
+    put_be64(lenblk + 8, 8 * (uint64_t)nbytes);
+#endif
+    ref_ghash(H, lenblk, 1, S);
+    ref_encrypt_block(w, Nr, J0, E);
+    for (int b = 0; b < 16; b++)
+        T[b] = E[b] ^ S[b];
+}
+
+/* Authenticated encryption (SP 800-38D section 7.1): H = Cipher(0^128), J0
+ * from the IV, C = GCTR(inc32(J0), P) -- CTR starting one past J0 with the
+ * 32-bit increment -- and the full 16-byte tag (callers truncate).  Returns
+ * -1 for an empty IV. */
+int ref_gcm_encrypt(const uint8_t *w, int Nr, const uint8_t *iv, size_t iv_bytes, const uint8_t *aad,
+                    size_t aad_bytes, const uint8_t *in, uint8_t *out, size_t nbytes, uint8_t tag[16])
+{
+    if (iv_bytes == 0)
+        return -1;
+    uint8_t zero[16], H[16], J0[16];
+    memset(zero, 0, 16);
+    ref_encrypt_block(w, Nr, zero, H);
+    ref_gcm_j0(H, iv, iv_bytes, J0);
+    ref_ctr(w, Nr, J0, 1, in, out, nbytes);
+    gcm_tag(w, Nr, H, J0, aad, aad_bytes, out, nbytes, tag);
+    return 0;
+}
+
+/* Authenticated decryption (SP 800-38D section 7.2): the tag is recomputed
+ * over the ciphertext and compared with the first tag_bytes bytes of `tag`.
+ * The plaintext is written either way; the return value says whether it may
+ * be released: 0 = authentic, 1 = FAIL, -1 = bad arguments. */
+int ref_gcm_decrypt(const uint8_t *w, int Nr, const uint8_t *iv, size_t iv_bytes, const uint8_t *aad,
+                    size_t aad_bytes, const uint8_t *in, uint8_t *out, size_t nbytes, const uint8_t *tag,
+                    size_t tag_bytes)
+{
+    if (iv_bytes == 0 || tag_bytes == 0 || tag_bytes > 16)
+        return -1;
+    uint8_t zero[16], H[16], J0[16], T[16];
+    memset(zero, 0, 16);
+    ref_encrypt_block(w, Nr, zero, H);
+    ref_gcm_j0(H, iv, iv_bytes, J0);
+    gcm_tag(w, Nr, H, J0, aad, aad_bytes, in, nbytes, T);
+    ref_ctr(w, Nr, J0, 1, in, out, nbytes);
+    int diff = 0;
+    for (size_t b = 0; b < tag_bytes; b++)
+        diff |= T[b] ^ tag[b];
+    return diff ? 1 : 0;
 }

@@ -67,6 +67,15 @@ class Oracle:
         lib.ref_xts.restype = ctypes.c_int
         lib.ref_xts.argtypes = [ctypes.c_int, _u8p, _u8p, ctypes.c_int, ctypes.c_size_t, ctypes.c_uint64,
                                 _u8p, _u8p, ctypes.c_size_t]
+        lib.ref_gcm_mul.argtypes = [_u8p, _u8p, _u8p]
+        lib.ref_ghash.argtypes = [_u8p, _u8p, ctypes.c_size_t, _u8p]
+        lib.ref_gcm_j0.argtypes = [_u8p, _u8p, ctypes.c_size_t, _u8p]
+        lib.ref_gcm_encrypt.restype = ctypes.c_int
+        lib.ref_gcm_encrypt.argtypes = [_u8p, ctypes.c_int, _u8p, ctypes.c_size_t, _u8p, ctypes.c_size_t,
+                                        _u8p, _u8p, ctypes.c_size_t, _u8p]
+        lib.ref_gcm_decrypt.restype = ctypes.c_int
+        lib.ref_gcm_decrypt.argtypes = [_u8p, ctypes.c_int, _u8p, ctypes.c_size_t, _u8p, ctypes.c_size_t,
+                                        _u8p, _u8p, ctypes.c_size_t, _u8p, ctypes.c_size_t]
         lib.ref_par_run.restype = ctypes.c_int
         lib.ref_par_run.argtypes = [ctypes.c_int, _u8p, ctypes.c_int, _u8p, _u8p, _u8p,
                                     ctypes.c_size_t, ctypes.c_int,
@@ -173,6 +182,47 @@ class Oracle:
                             first_unit, _ptr(d), _ptr(out), d.size):
             raise ValueError("XTS lengths must be multiples of 16")
         return out
+
+    def gcm_mul(self, x, y):
+        """Product in GF(2^128), the GCM bit order."""
+        out = np.zeros(16, np.uint8)
+        self.lib.ref_gcm_mul(_ptr(_as_u8(x)), _ptr(_as_u8(y)), _ptr(out))
+        return out
+
+    def ghash(self, h, data, y=None):
+        """GHASH_H over whole blocks of `data`, continuing from `y` (zero)."""
+        d = _as_u8(data)
+        assert d.size % 16 == 0
+        out = np.zeros(16, np.uint8) if y is None else _as_u8(y).copy()
+        self.lib.ref_ghash(_ptr(_as_u8(h)), _ptr(d) if d.size else None, d.size // 16, _ptr(out))
+        return out
+
+    def gcm_j0(self, h, iv):
+        v = _as_u8(iv)
+        out = np.zeros(16, np.uint8)
+        self.lib.ref_gcm_j0(_ptr(_as_u8(h)), _ptr(v), v.size, _ptr(out))
+        return out
+
+    def gcm_encrypt(self, rk, nr, iv, aad, data):
+        """Returns (ciphertext, 16-byte tag)."""
+        v, a, d = _as_u8(iv), _as_u8(aad), _as_u8(data)
+        out, tag = np.empty_like(d), np.zeros(16, np.uint8)
+        if self.lib.ref_gcm_encrypt(_ptr(_as_u8(rk)), nr, _ptr(v), v.size, _ptr(a) if a.size else None,
+                                    a.size, _ptr(d) if d.size else None, _ptr(out) if d.size else None,
+                                    d.size, _ptr(tag)):
+            raise ValueError("GCM needs a non-empty IV")
+        return out, tag
+
+    def gcm_decrypt(self, rk, nr, iv, aad, data, tag):
+        """Returns (plaintext, authentic?) for the given (possibly truncated) tag."""
+        v, a, d, t = _as_u8(iv), _as_u8(aad), _as_u8(data), _as_u8(tag)
+        out = np.empty_like(d)
+        rc = self.lib.ref_gcm_decrypt(_ptr(_as_u8(rk)), nr, _ptr(v), v.size, _ptr(a) if a.size else None,
+                                      a.size, _ptr(d) if d.size else None, _ptr(out) if d.size else None,
+                                      d.size, _ptr(t), t.size)
+        if rc < 0:
+            raise ValueError("GCM needs a non-empty IV and a tag of 1..16 bytes")
+        return out, rc == 0
 
     def par_run(self, op, rk, nr, data, nthreads, ctr0=None, out=None):
         """The paper's pthreads method; returns (output, seconds)."""

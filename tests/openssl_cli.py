@@ -34,3 +34,15 @@ def enc(mode, key, data, iv=None, decrypt=False):
     r = subprocess.run(cmd, input=bytes(np.asarray(data, dtype=np.uint8)),
                        capture_output=True, check=True)
     return np.frombuffer(r.stdout, dtype=np.uint8).copy()
+
+
+def gmac(key, iv, data):
+    """``openssl mac -cipher AES-<bits>-GCM ... GMAC``: the GCM tag of an
+    empty plaintext with `data` as the additional authenticated data."""
+    key = bytes(np.asarray(key, dtype=np.uint8))
+    iv = bytes(np.asarray(iv, dtype=np.uint8))
+    cmd = [OPENSSL, "mac", "-cipher", "AES-%d-GCM" % (8 * len(key)), "-macopt", "hexkey:" + key.hex(),
+           "-macopt", "hexiv:" + iv.hex(), "GMAC"]
+    data = bytes(data) if isinstance(data, (bytes, bytearray)) else bytes(np.asarray(data, dtype=np.uint8))
+    r = subprocess.run(cmd, input=data, capture_output=True, check=True)
+    return np.frombuffer(bytes.fromhex(r.stdout.decode().strip()), dtype=np.uint8).copy()

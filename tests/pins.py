@@ -341,8 +341,104 @@ def pin_xts(o):
     return fails
 
 
+def gcm_to_int(b):
+    """A block in GCM's bit order (bit 0 = most significant bit of byte 0 =
+    coefficient of x^0) as an integer whose bit i is the coefficient of x^i:
+    the bits of every byte reversed, bytes little-endian."""
+    return int.from_bytes(bytes(int("{:08b}".format(x)[::-1], 2) for x in bytes(b)), "little")
+
+
+def int_to_gcm(v):
+    return np.frombuffer(bytes(int("{:08b}".format(x)[::-1], 2) for x in v.to_bytes(16, "little")), np.uint8)
+
+
+def gcm_mul_int(a, b):
+    # GCM reduces by the same x^128 + x^7 + x^2 + x + 1 as XTS; only the bit order differs
+    return int_to_gcm(gf128_mul_int(gcm_to_int(a), gcm_to_int(b)))
+
+
+def _be64(v):
+    return v.to_bytes(8, "big")
+
+
+def pin_gcm(o, nkeys=2):
+    """GCM from pieces pinned elsewhere:
+    - the GF(2^128) product against an independent carry-less product;
+    - tags of empty plaintexts against the openssl executable's GMAC (which
+      is GCM with the message as additional data), for IVs of 12 and of
+      other lengths (the GHASH-derived pre-counter block);
+    - the ciphertext against openssl CTR started one past the pre-counter
+      block J0, where Cipher(J0) is read off openssl's GMAC of an empty
+      message and J0 = InvCipher of it (openssl ECB);
+    - tags with a plaintext through GHASH's linearity: with additional data
+      of whole blocks, tag(A, C) = GMAC(A || C padded) XOR (L1 XOR L2) * H,
+      L1, L2 the two length blocks and H = Cipher(0) (openssl ECB);
+    - decryption accepts the tag, a truncated tag, and rejects any change."""
+    fails = []
+    for k in range(300):
+        a = seedgen.bytes_np(seedgen.stream_seed(91, seedgen.TAG_DATA, 2 * k), 16)
+        b = seedgen.bytes_np(seedgen.stream_seed(91, seedgen.TAG_DATA, 2 * k + 1), 16)
+        if k == 0:
+            b = np.frombuffer(bytes([0x80]) + bytes(15), np.uint8)      # the element 1
+        if not np.array_equal(o.gcm_mul(a, b), gcm_mul_int(a, b)):
+            fails.append("GF(2^128) product")
+            break
+    if not openssl_cli.available():
+        return fails + ["openssl executable not available"]
+    for bits in (128, 256):
+        for kk in range(nkeys):
+            key = seedgen.key(92, 10 * bits + kk, bits)
+            w, nr = o.expand_key(key)
+            H = openssl_cli.enc("ecb", key, np.zeros(16, np.uint8))
+            for ivlen, alen in ((12, 0), (12, 16), (12, 45), (1, 7), (17, 64), (60, 1000)):
+                iv = seedgen.bytes_np(seedgen.stream_seed(93, seedgen.TAG_NONCE, 100 * ivlen + kk), ivlen)
+                aad = seedgen.bytes_np(seedgen.stream_seed(93, seedgen.TAG_DATA, alen + kk), alen)
+                _, tag = o.gcm_encrypt(w, nr, iv, aad, b"")
+                if not np.array_equal(tag, openssl_cli.gmac(key, iv, aad)):
+                    fails.append("GCM-%d tag of empty plaintext, IV %d B, AAD %d B" % (bits, ivlen, alen))
+            for ivlen in (12, 13):
+                iv = seedgen.bytes_np(seedgen.stream_seed(94, seedgen.TAG_NONCE, 100 * ivlen + kk), ivlen)
+                ek_j0 = openssl_cli.gmac(key, iv, b"")
+                j0 = openssl_cli.enc("ecb", key, ek_j0, decrypt=True)
+                for plen, alen in ((16 * 37, 32), (1000, 0), (5, 16)):
+                    pt = seedgen.data_np(95, plen + ivlen + kk, plen)
+                    aad = seedgen.data_np(96, alen + kk, alen)
+                    ct, tag = o.gcm_encrypt(w, nr, iv, aad, pt)
+                    c0 = int.from_bytes(j0[12:].tobytes(), "big")
+                    if c0 + 1 + (plen + 15) // 16 < (1 << 32):      # openssl CTR carries past 32 bits
+                        icb = np.concatenate([j0[:12], np.frombuffer(((c0 + 1) & 0xFFFFFFFF).to_bytes(4, "big"),
+                                                                     np.uint8)])
+                        if not np.array_equal(ct, openssl_cli.enc("ctr", key, pt, iv=icb)):
+                            fails.append("GCM-%d ciphertext, IV %d B" % (bits, ivlen))
+                    cpad = np.concatenate([ct, np.zeros((-plen) % 16, np.uint8)])
+                    g = openssl_cli.gmac(key, iv, np.concatenate([aad, cpad]))
+                    l1 = np.frombuffer(_be64(8 * alen) + _be64(8 * plen), np.uint8)
+                    l2 = np.frombuffer(_be64(8 * (alen + cpad.size)) + _be64(0), np.uint8)
+                    if not np.array_equal(tag, g ^ gcm_mul_int(l1 ^ l2, H)):
+                        fails.append("GCM-%d tag, IV %d B, %d B plaintext" % (bits, ivlen, plen))
+                    back, ok = o.gcm_decrypt(w, nr, iv, aad, ct, tag)
+                    if not ok or not np.array_equal(back, pt):
+                        fails.append("GCM-%d decrypt" % bits)
+                    if not o.gcm_decrypt(w, nr, iv, aad, ct, tag[:12])[1]:
+                        fails.append("GCM-%d truncated tag rejected" % bits)
+                    bad = ct.copy()
+                    bad[-1] ^= 1
+                    if o.gcm_decrypt(w, nr, iv, aad, bad, tag)[1]:
+                        fails.append("GCM-%d changed ciphertext accepted" % bits)
+                    badtag = tag.copy()
+                    badtag[3] ^= 0x40
+                    if o.gcm_decrypt(w, nr, iv, aad, ct, badtag)[1]:
+                        fails.append("GCM-%d changed tag accepted" % bits)
+                    if alen:
+                        bada = aad.copy()
+                        bada[0] ^= 0x80
+                        if o.gcm_decrypt(w, nr, iv, bada, ct, tag)[1]:
+                            fails.append("GCM-%d changed additional data accepted" % bits)
+    return fails
+
+
 ALL_PINS = (pin_gf, pin_sbox, pin_mix_columns, pin_shift_rows, pin_key_expansion,
-            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking, pin_cbc, pin_xts)
+            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking, pin_cbc, pin_xts, pin_gcm)
 
 
 def run_all(o, fast=False):

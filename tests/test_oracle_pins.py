@@ -82,6 +82,10 @@ def test_xts(o):
     assert pins.pin_xts(o) == []
 
 
+def test_gcm(o):
+    assert pins.pin_gcm(o) == []
+
+
 def test_gf128_reference_is_a_field_multiplication():
     # the test-side GF(2^128) itself: commutative, distributive, x * x^127 = x^128
     import random
