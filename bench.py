@@ -325,6 +325,21 @@ def main():
                                           lambda: fn(x, y, n, rk1, rk2, nr, unit, 0, stream=stream), 10, 2)
                     sec["xts%d_%s_unit%d" % (bits, "dec" if dec else "enc", unit)] = {
                         "GB/s": round(n / k / 1e9, 1)}
+        # GCM (CTR with the GHASH tag fused), 16 bytes of additional data
+        gws = torch.empty(A.aes_gcm_workspace_size(), dtype=torch.uint8, device=dev)
+        gtag = torch.empty(16, dtype=torch.uint8, device=dev)
+        gok = torch.empty(1, dtype=torch.int32, device=dev)
+        gaad = torch.zeros(16, dtype=torch.uint8, device=dev)
+        giv = seedgen.nonce(2, 3)[:12]   # the standard 96-bit IV
+        for bits, key in ((128, key128), (256, key256)):
+            rk, nr = A.aes_expand_key(key)
+            w, k = timed_launches(torch, stream, lambda: A.aes_gcm_encrypt(
+                x, y, n, gaad, 16, rk, nr, giv, gtag, gws, stream=stream), 10, 2)
+            sec["aes%d_gcm_enc" % bits] = {"GB/s": round(n / k / 1e9, 1)}
+            w, k = timed_launches(torch, stream, lambda: A.aes_gcm_decrypt(
+                y, x, n, gaad, 16, rk, nr, giv, gtag, 16, gok, gws, stream=stream), 10, 2)
+            sec["aes%d_gcm_dec" % bits] = {"GB/s": round(n / k / 1e9, 1)}
+        # the decryptions above wrote the plaintext back into x
         # one GPU's share of the 1 GiB job if it were split over eight GPUs
         rk, nr = A.aes_expand_key(key128)
         share = n // 8

@@ -140,6 +140,50 @@ int aes_xts_decrypt(const void *in, void *out, size_t nbytes,
                     const uint8_t *roundkeys1, const uint8_t *roundkeys2, int Nr,
                     size_t unit_bytes, uint64_t first_unit, void *stream);
 
+/*
+ * AES-GCM (NIST SP 800-38D), authenticated encryption after the paper's
+ * modes: CTR encryption with the counter starting one past the pre-counter
+ * block J0, and the tag Cipher_K(J0) XOR GHASH_H(A || C || lengths) with
+ * H = Cipher_K(0^128) (sections 6.3 - 6.5, 7.1, 7.2).  One pass over the
+ * data: each ciphertext block is hashed in the kernel that produces it.
+ *   in, out          device pointers, 16-byte aligned, nbytes of them (any
+ *                    length up to 2^36 - 32 bytes; 0 is GMAC, a tag over
+ *                    the additional data alone).  in == out allowed.
+ *   aad, aad_bytes   additional authenticated data: device pointer, 16-byte
+ *                    aligned (NULL only when aad_bytes == 0), up to 2^36
+ *                    bytes; must not overlap out.
+ *   roundkeys, Nr    host pointer to the encryption schedule
+ *                    (aes_expand_key output); 10, 12 or 14.
+ *   iv, iv_bytes     host pointer to the IV, 1 .. 256 bytes (12 is the
+ *                    standard's recommended length; others go through
+ *                    GHASH to form J0).
+ *   workspace        device memory of at least aes_gcm_workspace_size()
+ *                    bytes, 256-byte aligned, private to the call until the
+ *                    stream has run it (calls in flight at once need their
+ *                    own).
+ *   stream           hipStream_t or NULL.
+ * Encryption writes the full 16-byte tag to device memory at `tag` (callers
+ * that use a shorter tag keep its leading bytes).  Decryption recomputes the
+ * tag over `in` and compares its first tag_bytes (4, 8 or 12 .. 16) with the
+ * device buffer `tag`, writing 1 (authentic) or 0 to the device int `*ok`.
+ * The plaintext is written in either case: a caller must not release it
+ * unless *ok is 1.
+ * Errors: AES_E_NULL, AES_E_NR, AES_E_LENGTH, AES_E_ALIGN, AES_E_OVERLAP,
+ * AES_E_ARG (iv_bytes, tag_bytes), AES_E_DEVICE.
+ */
+int aes_gcm_workspace_size(size_t *bytes);
+int aes_gcm_encrypt(const void *in, void *out, size_t nbytes,
+                    const void *aad, size_t aad_bytes,
+                    const uint8_t *roundkeys, int Nr,
+                    const uint8_t *iv, size_t iv_bytes, void *tag,
+                    void *workspace, size_t workspace_bytes, void *stream);
+int aes_gcm_decrypt(const void *in, void *out, size_t nbytes,
+                    const void *aad, size_t aad_bytes,
+                    const uint8_t *roundkeys, int Nr,
+                    const uint8_t *iv, size_t iv_bytes,
+                    const void *tag, size_t tag_bytes, int *ok,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
 /* Message for the last non-zero status returned on this thread. */
 const char *aes_last_error(void);
 

@@ -49,6 +49,15 @@ _SIGNATURES = {
     "aes_xts_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_size_t, ctypes.c_uint64, ctypes.c_void_p]),
+    "aes_gcm_workspace_size": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t)]),
+    "aes_gcm_encrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "aes_gcm_decrypt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "aes_last_error": (ctypes.c_char_p, []),
     "aes_set_launch": (ctypes.c_int, [ctypes.c_void_p]),
     "aes_get_launch": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -245,6 +254,36 @@ def aes_xts_decrypt(inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, fi
     """Enqueue XTS decryption; the arguments of aes_xts_encrypt."""
     return _xts(lib.aes_xts_decrypt, inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes,
                 first_unit, stream)
+
+
+def aes_gcm_workspace_size():
+    n = ctypes.c_size_t(0)
+    _check(lib.aes_gcm_workspace_size(ctypes.byref(n)))
+    return n.value
+
+
+def aes_gcm_encrypt(inp, out, nbytes, aad, aad_bytes, roundkeys, Nr, iv, tag, workspace,
+                    workspace_bytes=None, stream=None):
+    """Enqueue GCM encryption; the 16-byte tag goes to device buffer `tag`."""
+    rk, v = _host_bytes(roundkeys), _host_bytes(iv)
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    _check(lib.aes_gcm_encrypt(_dptr(inp), _dptr(out), nbytes, _dptr(aad), aad_bytes, _hptr(rk), Nr,
+                               _hptr(v), v.size, _dptr(tag), _dptr(workspace), workspace_bytes,
+                               _stream_handle(stream, tag)))
+    return out
+
+
+def aes_gcm_decrypt(inp, out, nbytes, aad, aad_bytes, roundkeys, Nr, iv, tag, tag_bytes, ok, workspace,
+                    workspace_bytes=None, stream=None):
+    """Enqueue GCM decryption; device int32 `ok` receives 1 if the tag matches."""
+    rk, v = _host_bytes(roundkeys), _host_bytes(iv)
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size()
+    _check(lib.aes_gcm_decrypt(_dptr(inp), _dptr(out), nbytes, _dptr(aad), aad_bytes, _hptr(rk), Nr,
+                               _hptr(v), v.size, _dptr(tag), tag_bytes, _dptr(ok), _dptr(workspace),
+                               workspace_bytes, _stream_handle(stream, tag)))
+    return out
 
 
 def aes_last_error():

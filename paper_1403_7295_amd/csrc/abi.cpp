@@ -56,6 +56,8 @@ void init_device(int dev) {
         e = upload_tables_batch(host_tables());
     if (e == hipSuccess)
         e = upload_tables_xts(host_tables());
+    if (e == hipSuccess)
+        e = upload_tables_gcm(host_tables());
     if (e != hipSuccess) {
         d.error = std::string("table upload: ") + hipGetErrorString(e);
         return;
@@ -281,6 +283,75 @@ int xts_crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8
     return AES_OK;
 }
 
+int gcm_crypt(int decrypt, const void *in, void *out, size_t nbytes, const void *aad, size_t aad_bytes,
+              const uint8_t *roundkeys, int Nr, const uint8_t *iv, size_t iv_bytes, void *tag, const void *tag_in,
+              size_t tag_bytes, int *ok, void *workspace, size_t workspace_bytes, void *stream) {
+    if (Nr != 10 && Nr != 12 && Nr != 14)
+        return fail(AES_E_NR, "Nr must be 10, 12 or 14");
+    if (!roundkeys || !iv || !workspace)
+        return fail(AES_E_NULL, "roundkeys, iv and workspace must not be NULL");
+    if (decrypt ? (!tag_in || !ok) : !tag)
+        return fail(AES_E_NULL, decrypt ? "tag and ok must not be NULL" : "tag must not be NULL");
+    if (iv_bytes < 1 || iv_bytes > 256)
+        return fail(AES_E_ARG, "iv_bytes must be 1 .. 256");
+    if (decrypt && !(tag_bytes == 4 || tag_bytes == 8 || (tag_bytes >= 12 && tag_bytes <= 16)))
+        return fail(AES_E_ARG, "tag_bytes must be 4, 8 or 12 .. 16");
+    if (nbytes > (uint64_t(1) << 36) - 32)
+        return fail(AES_E_LENGTH, "GCM plaintext is limited to 2^36 - 32 bytes");
+    if (aad_bytes > (uint64_t(1) << 36))
+        return fail(AES_E_LENGTH, "additional data is limited to 2^36 bytes");
+    if (aad_bytes && !aad)
+        return fail(AES_E_NULL, "aad must not be NULL when aad_bytes > 0");
+    if (reinterpret_cast<uintptr_t>(aad) & 15u)
+        return fail(AES_E_ALIGN, "aad must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+        return fail(AES_E_ALIGN, "workspace must be 256-byte aligned");
+    if (workspace_bytes < kGcmWorkspaceBytes)
+        return fail(AES_E_LENGTH, "workspace smaller than aes_gcm_workspace_size reports");
+    int st;
+    if (nbytes) {
+        st = check_buffers(in, out, nbytes);
+        if (st != AES_OK)
+            return st;
+        const uintptr_t o = reinterpret_cast<uintptr_t>(out), ad = reinterpret_cast<uintptr_t>(aad);
+        if (aad_bytes && ad < o + nbytes && o < ad + aad_bytes)
+            return fail(AES_E_OVERLAP, "aad must not overlap out");
+    }
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+
+    GcmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.in = static_cast<const uint8_t *>(in);
+    a.out = static_cast<uint8_t *>(out);
+    a.nbytes = nbytes;
+    a.aad = static_cast<const uint8_t *>(aad);
+    a.aad_bytes = aad_bytes;
+    a.ws = static_cast<GcmWork *>(workspace);
+    a.tag_out = static_cast<uint8_t *>(tag);
+    a.tag_in = static_cast<const uint8_t *>(tag_in);
+    a.ok = ok;
+    a.tag_bytes = uint32_t(tag_bytes);
+    a.iv_bytes = uint32_t(iv_bytes);
+    a.decrypt = uint32_t(decrypt);
+    for (int i = 0; i < 4 * (Nr + 1); i++)
+        std::memcpy(&a.rk[i], roundkeys + 4 * i, 4);
+    std::memcpy(a.iv, iv, iv_bytes);
+    // one chunk of 256 hash positions per wave, 16 waves per workgroup; the
+    // workgroup count is a power of two (the folding factors are H^(2^t))
+    const uint64_t positions = (nbytes + 15) / 16 + (aad_bytes + 15) / 16 + 1;
+    const uint64_t wgs = (positions + 4095) / 4096;
+    uint32_t lg = 0;
+    while ((uint64_t(1) << lg) < wgs && (2 << lg) <= std::min(d->cus, kGcmMaxGrid))
+        lg++;
+    a.grid_log2 = lg;
+    hipError_t e = launch_gcm(Nr, a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
 constexpr int kDefaultTileBlocks = 8192;  // 128 KiB of data per tile
 
 // Tile capacity and workspace bytes for a batch shape; 0 bytes if too big.
@@ -384,6 +455,27 @@ int aes_xts_encrypt(const void *in, void *out, size_t nbytes, const uint8_t *rou
 int aes_xts_decrypt(const void *in, void *out, size_t nbytes, const uint8_t *roundkeys1,
                     const uint8_t *roundkeys2, int Nr, size_t unit_bytes, uint64_t first_unit, void *stream) {
     return xts_crypt(1, in, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, first_unit, stream);
+}
+
+int aes_gcm_workspace_size(size_t *bytes) {
+    if (!bytes)
+        return fail(AES_E_NULL, "bytes must not be NULL");
+    *bytes = kGcmWorkspaceBytes;
+    return AES_OK;
+}
+
+int aes_gcm_encrypt(const void *in, void *out, size_t nbytes, const void *aad, size_t aad_bytes,
+                    const uint8_t *roundkeys, int Nr, const uint8_t *iv, size_t iv_bytes, void *tag,
+                    void *workspace, size_t workspace_bytes, void *stream) {
+    return gcm_crypt(0, in, out, nbytes, aad, aad_bytes, roundkeys, Nr, iv, iv_bytes, tag, nullptr, 16, nullptr,
+                     workspace, workspace_bytes, stream);
+}
+
+int aes_gcm_decrypt(const void *in, void *out, size_t nbytes, const void *aad, size_t aad_bytes,
+                    const uint8_t *roundkeys, int Nr, const uint8_t *iv, size_t iv_bytes, const void *tag,
+                    size_t tag_bytes, int *ok, void *workspace, size_t workspace_bytes, void *stream) {
+    return gcm_crypt(1, in, out, nbytes, aad, aad_bytes, roundkeys, Nr, iv, iv_bytes, nullptr, tag, tag_bytes, ok,
+                     workspace, workspace_bytes, stream);
 }
 
 const char *aes_last_error(void) { return g_error.c_str(); }

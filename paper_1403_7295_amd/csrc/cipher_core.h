@@ -194,6 +194,34 @@ __device__ __forceinline__ void rounds(uint32_t (&s)[BPT][4], const uint32_t *ld
     }
 }
 
+// One AES encryption with the round table read from the base table in
+// global memory (through the vector L1), for the few blocks a kernel
+// encrypts outside its LDS tables: XTS tweaks while the LDS holds the
+// inverse tables, GCM's hash key and pre-counter block.
+template <int NR>
+__device__ __forceinline__ void encrypt_global(const uint32_t *rk, uint32_t (&s)[4]) {
+    const uint32_t *te0 = g_base;
+    auto T = [&](int t, uint32_t w, int k) { return rotl(te0[(w >> (8 * k)) & 255u], 8 * t); };
+    uint32_t a0 = s[0] ^ rk[0], a1 = s[1] ^ rk[1], a2 = s[2] ^ rk[2], a3 = s[3] ^ rk[3];
+#pragma unroll
+    for (int r = 1; r < NR; r++) {
+        const uint32_t b0 = T(0, a0, 0) ^ T(1, a1, 1) ^ T(2, a2, 2) ^ T(3, a3, 3) ^ rk[4 * r];
+        const uint32_t b1 = T(0, a1, 0) ^ T(1, a2, 1) ^ T(2, a3, 2) ^ T(3, a0, 3) ^ rk[4 * r + 1];
+        const uint32_t b2 = T(0, a2, 0) ^ T(1, a3, 1) ^ T(2, a0, 2) ^ T(3, a1, 3) ^ rk[4 * r + 2];
+        const uint32_t b3 = T(0, a3, 0) ^ T(1, a0, 1) ^ T(2, a1, 2) ^ T(3, a2, 3) ^ rk[4 * r + 3];
+        a0 = b0;
+        a1 = b1;
+        a2 = b2;
+        a3 = b3;
+    }
+    // last round: S[x] is byte 1 of te0[x]
+    auto S = [&](uint32_t w, int k) { return (te0[(w >> (8 * k)) & 255u] >> 8) & 255u; };
+    s[0] = (S(a0, 0) | (S(a1, 1) << 8) | (S(a2, 2) << 16) | (S(a3, 3) << 24)) ^ rk[4 * NR];
+    s[1] = (S(a1, 0) | (S(a2, 1) << 8) | (S(a3, 2) << 16) | (S(a0, 3) << 24)) ^ rk[4 * NR + 1];
+    s[2] = (S(a2, 0) | (S(a3, 1) << 8) | (S(a0, 2) << 16) | (S(a1, 3) << 24)) ^ rk[4 * NR + 2];
+    s[3] = (S(a3, 0) | (S(a0, 1) << 8) | (S(a1, 2) << 16) | (S(a2, 3) << 24)) ^ rk[4 * NR + 3];
+}
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32x4 vec4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {

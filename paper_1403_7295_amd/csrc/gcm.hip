@@ -1,0 +1,455 @@
+// AES-GCM (NIST SP 800-38D) for gfx950: CTR encryption fused with the GHASH
+// authenticator in one pass over the data.
+//
+// Definitions (SP 800-38D sections 6 and 7).  H = Cipher_K(0^128).  The
+// pre-counter block J0 is IV || 0^31 || 1 for a 96-bit IV and otherwise
+// GHASH_H of the zero-padded IV followed by its bit length.  Ciphertext
+// block j is P_j XOR Cipher_K(J0 + 1 + j), the count in the last 32 bits.
+// The tag is Cipher_K(J0) XOR S, where S is GHASH_H over the sequence
+// X_1 .. X_m = A (zero-padded) || C (zero-padded) || [len(A)]_64 [len(C)]_64,
+// i.e. S = sum_i X_i * H^(m - i + 1) in GF(2^128).
+//
+// Evaluation order.  Number the sequence from its end, r = m - i, so that
+// S = H * sum_r X_r * H^r: r = 0 is the length block, r = 1 .. nC the
+// ciphertext blocks (block j at r = nC - j), then the additional data.
+// Positions are cut into chunks of 256 (64 lanes x 4 slots); wave w of NW
+// takes chunks w, w + NW, w + 2 NW, ... from the last to the first, so every
+// (lane, slot) stream is a Horner evaluation with the same multiplier
+// G = H^(256 NW):  W <- W * G + X.  At the end a stream at offset s in its
+// wave's first chunk needs the factor H^(s + 256 w); the streams are folded
+// with factors H^64 (slots), H^1 .. H^32 (lanes, a tree), H^256 .. H^2048
+// (the 16 waves of a workgroup) and H^(4096 b) (workgroups, in the last
+// kernel).  Every factor is a power H^(2^t), computed once by the first
+// kernel.
+//
+// Multiplication by a fixed element M uses 4-bit tables in LDS: for each of
+// the 32 nibble positions of a block, the 16 products (nibble value at that
+// position) * M, 16 bytes each (8 KiB per multiplier).  A product is 32
+// 16-byte LDS reads XORed together.  A table of 256 bytes covers every LDS
+// bank once, so the 64 lanes of a read never conflict (equal values are
+// broadcast).  The bulk kernel keeps the AES encryption tables (128 KiB) and
+// G's table; after its loop the AES tables' space holds the folding tables.
+#include <hip/hip_runtime.h>
+
+#include "cipher_core.h"
+#include "gf128.h"
+#include "internal.h"
+
+namespace aesgpu {
+namespace {
+
+// LDS of the bulk kernel: G's tables at 0, the AES encryption tables at
+// kAesBase (128 KiB), scratch for building G's tables after them.  After the
+// loop: eleven folding tables from 0, their scratch, the wave partials.
+constexpr uint32_t kTabBytes = 8192;   // one multiplier's nibble tables
+constexpr uint32_t kVecBytes = 2048;   // M * x^e for e < 128, while building them
+constexpr uint32_t kGTab = 0;
+constexpr uint32_t kAesBase = 0x2000;
+constexpr uint32_t kGVec = kAesBase + 0x20000;
+constexpr uint32_t kFoldTabs = 11;
+constexpr uint32_t kFoldVec = kFoldTabs * kTabBytes;
+constexpr uint32_t kWavePartials = kFoldVec + kFoldTabs * kVecBytes;
+
+__device__ __forceinline__ u32x4 lds_load16(const uint32_t *lds, uint32_t off) {
+    return *reinterpret_cast<const u32x4 *>(reinterpret_cast<const char *>(lds) + off);
+}
+
+__device__ __forceinline__ void lds_store16(uint32_t *lds, uint32_t off, u32x4 v) {
+    *reinterpret_cast<u32x4 *>(reinterpret_cast<char *>(lds) + off) = v;
+}
+
+// y = x * M for the multiplier whose tables start at byte offset `tab`.
+// Position p = 8c + m is bits 4m .. 4m+3 of word c (byte 4c + m/2 of the
+// block); entry (p, v) sits at tab + 256 p + 16 v, so below 64 KiB the
+// position's offset rides in the read's immediate field and the address
+// register is just 16 v.
+__device__ __forceinline__ void mul_tab(const uint32_t *lds, uint32_t tab, const uint32_t (&x)[4],
+                                        uint32_t (&y)[4]) {
+    uint32_t acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        uint32_t xc = x[c];
+        // an empty step the compiler cannot see through: this word's eight
+        // addresses and reads are formed here rather than all 32 up front,
+        // which would need 128 more registers
+        asm volatile("" : "+v"(xc) :: "memory");
+        const uint32_t x4 = xc << 4;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const uint32_t vlo = (x4 >> (8 * b)) & 0xF0u;   // low nibble of byte b, times 16
+            const uint32_t vhi = (xc >> (8 * b)) & 0xF0u;   // high nibble of byte b, times 16
+            const u32x4 t0 = lds_load16(lds, vlo + tab + uint32_t(8 * c + 2 * b) * 256u);
+            const u32x4 t1 = lds_load16(lds, vhi + tab + uint32_t(8 * c + 2 * b + 1) * 256u);
+            acc[0] = xor3(acc[0], t0.x, t1.x);
+            acc[1] = xor3(acc[1], t0.y, t1.y);
+            acc[2] = xor3(acc[2], t0.z, t1.z);
+            acc[3] = xor3(acc[3], t0.w, t1.w);
+        }
+    }
+    // and the product is complete here: no XOR of it is deferred past this
+    // point (which would keep all 32 reads alive)
+    asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]));
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+        y[c] = acc[c];
+}
+
+// Builds the tables of the multipliers powers[pick(k)], k < count, at byte
+// offsets dst + k * kTabBytes, using count * kVecBytes of scratch at `vec`.
+// Every thread of the workgroup takes part; starts and ends with a barrier
+// (the tables may overwrite LDS that other waves were reading).
+template <typename Pick>
+__device__ __forceinline__ void build_tables(uint32_t *lds, uint32_t dst, uint32_t vec, const GcmWork *ws, int count,
+                             Pick pick) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < uint32_t(count) * 128u; i += blockDim.x) {
+        const uint32_t k = i >> 7, e = i & 127u;
+        const uint32_t *m = ws->powers[pick(int(k))];
+        const uint32_t w[4] = {m[0], m[1], m[2], m[3]};
+        uint64_t lo, hi;
+        to_poly(w, lo, hi);
+        mulx_pow(lo, hi, e);
+        uint32_t r[4];
+        from_poly(lo, hi, r);
+        lds_store16(lds, vec + (k * 128u + e) * 16u, vec4(r[0], r[1], r[2], r[3]));
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < uint32_t(count) * 512u; i += blockDim.x) {
+        const uint32_t k = i >> 9, p = (i >> 4) & 31u, v = i & 15u;
+        const uint32_t byte = 4u * (p >> 3) + ((p & 7u) >> 1), half = p & 1u;
+        u32x4 acc = vec4(0, 0, 0, 0);
+#pragma unroll
+        for (uint32_t t = 0; t < 4; t++) {
+            if ((v >> t) & 1u) {
+                // bit 4*half + t of the byte is the coefficient of x^(8*byte + 7 - 4*half - t)
+                const uint32_t e = 8u * byte + 7u - 4u * half - t;
+                acc ^= lds_load16(lds, vec + (k * 128u + e) * 16u);
+            }
+        }
+        lds_store16(lds, dst + k * kTabBytes + p * 256u + v * 16u, acc);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask) {
+    const int lo = __shfl_xor(int(uint32_t(v)), mask, 64);
+    const int hi = __shfl_xor(int(uint32_t(v >> 32)), mask, 64);
+    return uint64_t(uint32_t(lo)) | (uint64_t(uint32_t(hi)) << 32);
+}
+
+// x * y in the arithmetic form, x and y the same in every lane of the wave:
+// lane l adds x_(2l) y x^(2l) and x_(2l+1) y x^(2l+1), then the wave XORs
+// its 64 partial sums.
+__device__ void mul_wave(uint64_t xlo, uint64_t xhi, uint64_t ylo, uint64_t yhi, uint64_t &rlo,
+                         uint64_t &rhi) {
+    const uint32_t e = 2u * (threadIdx.x & 63u);
+    uint64_t vlo = ylo, vhi = yhi;
+    mulx_pow(vlo, vhi, e);
+    const uint64_t bits = e < 64 ? xlo >> e : xhi >> (e - 64);
+    uint64_t alo = (bits & 1) ? vlo : 0, ahi = (bits & 1) ? vhi : 0;
+    mulx_small(vlo, vhi, 1);
+    if (bits & 2) {
+        alo ^= vlo;
+        ahi ^= vhi;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        alo ^= shfl_xor64(alo, off);
+        ahi ^= shfl_xor64(ahi, off);
+    }
+    rlo = alo;
+    rhi = ahi;
+}
+
+// One wave: H, J0, Cipher_K(J0) and the powers H^(2^t).
+template <int NR>
+__global__ __launch_bounds__(64) void gcm_setup_kernel(const GcmArgs a) {
+    uint32_t h[4] = {0, 0, 0, 0};
+    encrypt_global<NR>(a.rk, h);
+    uint64_t hlo, hhi;
+    to_poly(h, hlo, hhi);
+    uint32_t j0[4];
+    if (a.iv_bytes == 12) {
+        for (int c = 0; c < 3; c++)
+            j0[c] = uint32_t(a.iv[4 * c]) | (uint32_t(a.iv[4 * c + 1]) << 8) |
+                    (uint32_t(a.iv[4 * c + 2]) << 16) | (uint32_t(a.iv[4 * c + 3]) << 24);
+        j0[3] = 0x01000000u;   // 0^31 || 1, big-endian
+    } else {
+        // GHASH_H(IV || 0^(s+64) || [len(IV)]_64)
+        uint64_t ylo = 0, yhi = 0;
+        const uint32_t nblk = (a.iv_bytes + 15u) / 16u;
+        for (uint32_t b = 0; b <= nblk; b++) {
+            uint32_t x[4] = {0, 0, 0, 0};
+            if (b < nblk) {
+                for (uint32_t i = 0; i < 16; i++)
+                    if (16u * b + i < a.iv_bytes)
+                        x[i >> 2] |= uint32_t(a.iv[16u * b + i]) << (8 * (i & 3));
+            } else {
+                const uint64_t bits = 8ull * a.iv_bytes;
+                x[2] = __builtin_bswap32(uint32_t(bits >> 32));
+                x[3] = __builtin_bswap32(uint32_t(bits));
+            }
+            uint64_t xlo, xhi;
+            to_poly(x, xlo, xhi);
+            mul_wave(ylo ^ xlo, yhi ^ xhi, hlo, hhi, ylo, yhi);
+        }
+        from_poly(ylo, yhi, j0);
+    }
+    uint32_t ej0[4] = {j0[0], j0[1], j0[2], j0[3]};
+    encrypt_global<NR>(a.rk, ej0);
+    const bool writer = (threadIdx.x & 63u) == 0;
+    uint64_t plo = hlo, phi = hhi;
+    for (int t = 0; t < kGcmPowers; t++) {
+        if (writer) {
+            uint32_t w[4];
+            from_poly(plo, phi, w);
+            for (int c = 0; c < 4; c++)
+                a.ws->powers[t][c] = w[c];
+        }
+        mul_wave(plo, phi, plo, phi, plo, phi);
+    }
+    if (writer)
+        for (int c = 0; c < 4; c++) {
+            a.ws->j0[c] = j0[c];
+            a.ws->ej0[c] = ej0[c];
+        }
+}
+
+template <int NR, bool DEC, int BPT>
+__global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
+    static_assert(BPT == 4, "a chunk is 64 lanes x 4 slots = 256 positions");
+    __shared__ uint32_t lds[40960];   // 160 KiB
+    uint32_t *aes = lds + kAesBase / 4;
+    stage_tables<LAYOUT_T4X32, DIR_ENC>(aes);
+    // G = H^(256 * 16 * gridDim.x), gridDim.x = 2^grid_log2
+    const int gpow = 12 + int(a.grid_log2);
+    build_tables(lds, kGTab, kGVec, a.ws, 1, [gpow](int) { return gpow; });
+
+    const uint32_t lane = threadIdx.x & 63u;
+    const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
+    const uint64_t nC = (a.nbytes + 15) >> 4, nA = (a.aad_bytes + 15) >> 4;
+    const uint64_t nchunks = (nC + nA + 1 + 255) >> 8;
+    const uint64_t cwhole = a.nbytes >> 4, awhole = a.aad_bytes >> 4;
+    const uint32_t ctail = uint32_t(a.nbytes & 15u), atail = uint32_t(a.aad_bytes & 15u);
+    const uint64_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const uint64_t nwaves = uint64_t(gridDim.x) * (blockDim.x >> 6);
+    // counter blocks: J0's first 12 bytes, then the 32-bit count of J0 plus 1 + j
+    const uint32_t n0 = a.ws->j0[0] ^ a.rk[0], n1 = a.ws->j0[1] ^ a.rk[1], n2 = a.ws->j0[2] ^ a.rk[2];
+    const uint32_t c1 = __builtin_bswap32(a.ws->j0[3]) + 1u;
+    // [len(A)]_64 || [len(C)]_64 in bits, big-endian
+    const uint64_t abits = 8 * a.aad_bytes, cbits = 8 * a.nbytes;
+    const uint32_t len[4] = {__builtin_bswap32(uint32_t(abits >> 32)), __builtin_bswap32(uint32_t(abits)),
+                             __builtin_bswap32(uint32_t(cbits >> 32)), __builtin_bswap32(uint32_t(cbits))};
+    // bytes of a partial last ciphertext block that enter GHASH
+    uint32_t tmask[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const int keep = int(ctail) - 4 * c;
+        tmask[c] = keep >= 4 ? ~0u : keep <= 0 ? 0u : (1u << (8 * keep)) - 1u;
+    }
+
+    uint32_t W[BPT][4];
+#pragma unroll
+    for (int i = 0; i < BPT; i++)
+        W[i][0] = W[i][1] = W[i][2] = W[i][3] = 0;
+    // A chunk of 256 positions that are all whole ciphertext blocks: every
+    // chunk but the one holding the length block and a partial block, and
+    // those holding additional data.
+    auto fast_chunk = [&](uint64_t q) __attribute__((always_inline)) {
+        uint32_t s[BPT][4], x[BPT][4];
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            // position r = 256q + 64i + lane is block j = nC - r; the slot's
+            // 64 blocks end at block nC - 256q - 64i
+            const uint64_t top = nC - 256 * q - 64u * uint32_t(i) - 63;
+            const u32x4 v = load16(a.in + 16 * top + 16u * (63u - lane));
+            x[i][0] = v.x;
+            x[i][1] = v.y;
+            x[i][2] = v.z;
+            x[i][3] = v.w;
+            const uint32_t cnt = c1 + uint32_t(top) + (63u - lane);
+            s[i][0] = n0;
+            s[i][1] = n1;
+            s[i][2] = n2;
+            s[i][3] = __builtin_bswap32(cnt) ^ a.rk[3];
+        }
+        rounds<NR, DIR_ENC, LAYOUT_T4X32, BPT>(s, aes, lc, a.rk, 1);
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            const uint64_t top = nC - 256 * q - 64u * uint32_t(i) - 63;
+            const uint32_t o[4] = {x[i][0] ^ s[i][0], x[i][1] ^ s[i][1], x[i][2] ^ s[i][2], x[i][3] ^ s[i][3]};
+            store16(a.out + 16 * top + 16u * (63u - lane), vec4(o[0], o[1], o[2], o[3]));
+            uint32_t g[4];
+            mul_tab(lds, kGTab, W[i], g);
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                W[i][c] = g[c] ^ (DEC ? x[i][c] : o[c]);
+        }
+    };
+    // Any other chunk, one slot of 64 positions at a time: the length block,
+    // ciphertext blocks (whole or the partial last one), additional data, or
+    // nothing past the start of the sequence.
+    auto slow_chunk = [&](uint64_t q) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            const uint64_t r = 256 * q + 64u * uint32_t(i) + lane;
+            const bool is_c = r >= 1 && r <= nC;
+            const uint64_t j = nC - r;
+            u32x4 v = vec4(0, 0, 0, 0);
+            if (r == 0) {
+                v = vec4(len[0], len[1], len[2], len[3]);
+            } else if (is_c) {
+                v = j < cwhole ? load16(a.in + 16 * j) : load_tail(a.in + 16 * j, ctail);
+            } else if (r <= nC + nA) {
+                const uint64_t k = nC + nA - r;
+                v = k < awhole ? load16(a.aad + 16 * k) : load_tail(a.aad + 16 * k, atail);
+            }
+            uint32_t x[4] = {v.x, v.y, v.z, v.w};
+            uint32_t s[1][4] = {{n0, n1, n2, __builtin_bswap32(c1 + uint32_t(j)) ^ a.rk[3]}};
+            rounds<NR, DIR_ENC, LAYOUT_T4X32, 1>(s, aes, lc, a.rk, 1);
+            if (is_c) {
+                const uint32_t o[4] = {x[0] ^ s[0][0], x[1] ^ s[0][1], x[2] ^ s[0][2], x[3] ^ s[0][3]};
+                const bool whole = j < cwhole;
+                if (whole)
+                    store16(a.out + 16 * j, vec4(o[0], o[1], o[2], o[3]));
+                else
+                    store_tail(a.out + 16 * j, vec4(o[0], o[1], o[2], o[3]), ctail);
+                if (!DEC)
+#pragma unroll
+                    for (int c = 0; c < 4; c++)
+                        x[c] = whole ? o[c] : o[c] & tmask[c];
+            }
+            uint32_t g[4];
+            mul_tab(lds, kGTab, W[i], g);
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                W[i][c] = g[c] ^ x[c];
+            asm volatile("" ::: "memory");   // one slot's work at a time
+        }
+    };
+    if (wave < nchunks) {
+        uint64_t q = wave + nwaves * ((nchunks - 1 - wave) / nwaves);
+        for (;;) {
+            if (q >= 1 && 256 * q + 255 <= nC)
+                fast_chunk(q);
+            else
+                slow_chunk(q);
+            if (q < nwaves)
+                break;
+            q -= nwaves;
+        }
+    }
+
+    // fold: tables 0..6 hold H^1 .. H^64, tables 7..10 hold H^256 .. H^2048
+    build_tables(lds, 0, kFoldVec, a.ws, int(kFoldTabs), [](int k) { return k < 7 ? k : k + 1; });
+    uint32_t u[4] = {W[BPT - 1][0], W[BPT - 1][1], W[BPT - 1][2], W[BPT - 1][3]};
+#pragma unroll
+    for (int i = BPT - 2; i >= 0; i--) {
+        mul_tab(lds, 6 * kTabBytes, u, u);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            u[c] ^= W[i][c];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        uint32_t v[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            v[c] = uint32_t(__shfl_down(int(u[c]), 1u << k, 64));
+        mul_tab(lds, uint32_t(k) * kTabBytes, v, v);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            u[c] ^= v[c];
+    }
+    const uint32_t wv = threadIdx.x >> 6;
+    if (lane == 0)
+        lds_store16(lds, kWavePartials + 16u * wv, vec4(u[0], u[1], u[2], u[3]));
+    __syncthreads();
+    if (wv == 0) {
+        const u32x4 p = lane < 16 ? lds_load16(lds, kWavePartials + 16u * lane) : vec4(0, 0, 0, 0);
+        uint32_t y[4] = {p.x, p.y, p.z, p.w};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            uint32_t v[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                v[c] = uint32_t(__shfl_down(int(y[c]), 1u << k, 64));
+            mul_tab(lds, uint32_t(7 + k) * kTabBytes, v, v);
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                y[c] ^= v[c];
+        }
+        if (lane == 0)
+            for (int c = 0; c < 4; c++)
+                a.ws->partials[blockIdx.x][c] = y[c];
+    }
+}
+
+// One workgroup of 256: folds the workgroups' partial sums with the factors
+// H^(4096 b), multiplies by H and forms (or checks) the tag.
+__global__ __launch_bounds__(256) void gcm_final_kernel(const GcmArgs a) {
+    constexpr uint32_t kTabs = 9, kParts = kTabs * kTabBytes + kTabs * kVecBytes;
+    __shared__ uint32_t lds[(kParts + 256 * 16) / 4];
+    // tables 0..7 hold H^4096 .. H^(4096 * 128), table 8 holds H
+    build_tables(lds, 0, kTabs * kTabBytes, a.ws, int(kTabs), [](int k) { return k < 8 ? 12 + k : 0; });
+    const uint32_t t = threadIdx.x, grid = 1u << a.grid_log2;
+    u32x4 p = vec4(0, 0, 0, 0);
+    if (t < grid)
+        p = vec4(a.ws->partials[t][0], a.ws->partials[t][1], a.ws->partials[t][2], a.ws->partials[t][3]);
+    lds_store16(lds, kParts + 16u * t, p);
+    __syncthreads();
+    for (uint32_t k = 0, d = 1; d < grid; k++, d <<= 1) {
+        if ((t & (2 * d - 1)) == 0 && t + d < grid) {
+            const u32x4 o = lds_load16(lds, kParts + 16u * (t + d));
+            uint32_t v[4] = {o.x, o.y, o.z, o.w};
+            mul_tab(lds, k * kTabBytes, v, v);
+            const u32x4 m = lds_load16(lds, kParts + 16u * t);
+            lds_store16(lds, kParts + 16u * t, vec4(m.x ^ v[0], m.y ^ v[1], m.z ^ v[2], m.w ^ v[3]));
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const u32x4 o = lds_load16(lds, kParts);
+        uint32_t sum[4] = {o.x, o.y, o.z, o.w};
+        mul_tab(lds, 8 * kTabBytes, sum, sum);
+        uint8_t tag[16];
+        for (int b = 0; b < 16; b++)
+            tag[b] = uint8_t((sum[b >> 2] ^ a.ws->ej0[b >> 2]) >> (8 * (b & 3)));
+        if (a.decrypt) {
+            uint32_t diff = 0;
+            for (uint32_t b = 0; b < a.tag_bytes; b++)
+                diff |= uint32_t(tag[b] ^ a.tag_in[b]);
+            *a.ok = diff == 0 ? 1 : 0;
+        } else {
+            for (int b = 0; b < 16; b++)
+                a.tag_out[b] = tag[b];
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t upload_tables_gcm(const HostTables &t) { return upload_base_tables(t); }
+
+hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream) {
+    void (*setup)(const GcmArgs) = nr == 10 ? gcm_setup_kernel<10> : nr == 12 ? gcm_setup_kernel<12>
+                                                                              : gcm_setup_kernel<14>;
+    void (*bulk)(const GcmArgs);
+    if (a.decrypt)
+        bulk = nr == 10 ? gcm_kernel<10, true, 4> : nr == 12 ? gcm_kernel<12, true, 4> : gcm_kernel<14, true, 4>;
+    else
+        bulk = nr == 10 ? gcm_kernel<10, false, 4> : nr == 12 ? gcm_kernel<12, false, 4>
+                                                              : gcm_kernel<14, false, 4>;
+    hipLaunchKernelGGL(setup, dim3(1), dim3(64), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(bulk, dim3(1u << a.grid_log2), dim3(1024), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(gcm_final_kernel, dim3(1), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace aesgpu

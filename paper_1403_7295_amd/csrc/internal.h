@@ -74,6 +74,41 @@ struct XtsArgs {
 hipError_t upload_tables_xts(const HostTables &t);
 hipError_t launch_xts(int nr, int dir, int grid, const XtsArgs &a, hipStream_t stream);
 
+// ---- GCM (gcm.hip) --------------------------------------------------------------
+constexpr int kGcmPowers = 32;
+constexpr int kGcmMaxGrid = 256;
+// The caller's device workspace for one GCM call.  Blocks are stored as four
+// little-endian words (bytes in memory order).
+struct GcmWork {
+    uint32_t powers[kGcmPowers][4];     // H^(2^t)
+    uint32_t j0[4];                     // pre-counter block
+    uint32_t ej0[4];                    // Cipher_K(J0)
+    uint32_t pad[56];
+    uint32_t partials[kGcmMaxGrid][4];  // one hash partial per workgroup
+};
+static_assert(sizeof(GcmWork) <= 8192, "GCM workspace");
+constexpr size_t kGcmWorkspaceBytes = 8192;
+
+struct GcmArgs {
+    const uint8_t *in;
+    uint8_t *out;
+    uint64_t nbytes;
+    const uint8_t *aad;
+    uint64_t aad_bytes;
+    GcmWork *ws;
+    uint8_t *tag_out;        // encryption: the 16-byte tag
+    const uint8_t *tag_in;   // decryption: the expected tag (tag_bytes bytes)
+    int *ok;                 // decryption: 1 if authentic, else 0
+    uint32_t tag_bytes;
+    uint32_t iv_bytes;       // 1 .. 256
+    uint32_t grid_log2;      // the bulk kernel runs 2^grid_log2 workgroups of 1024
+    uint32_t decrypt;
+    uint32_t rk[60];         // encryption schedule
+    uint8_t iv[256];
+};
+hipError_t upload_tables_gcm(const HostTables &t);
+hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream);
+
 // ---- batches (batch_kernels.hip) -------------------------------------------
 // Workspace = header | key schedules (max_msgs slots) | tiles[3][capacity].
 struct BatchHeader {

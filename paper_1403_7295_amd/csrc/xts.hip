@@ -16,54 +16,11 @@
 #include <hip/hip_runtime.h>
 
 #include "cipher_core.h"
+#include "gf128.h"
 #include "internal.h"
 
 namespace aesgpu {
 namespace {
-
-// T * x^b for 0 <= b < 64 on a 128-bit little-endian value (lo = bits 0..63).
-__device__ __forceinline__ void mulx_small(uint64_t &lo, uint64_t &hi, uint32_t b) {
-    const uint32_t bb = b & 63u;
-    const uint64_t o = bb ? hi >> (64 - bb) : 0;            // the bits that leave the top
-    hi = bb ? (hi << bb) | (lo >> (64 - bb)) : hi;
-    lo = lo << bb;
-    // o * x^128 = o * (x^7 + x^2 + x + 1); o has at most 63 bits
-    lo ^= o ^ (o << 1) ^ (o << 2) ^ (o << 7);
-    hi ^= (o >> 63) ^ (o >> 62) ^ (o >> 57);
-}
-
-// T * x^64.
-__device__ __forceinline__ void mulx64(uint64_t &lo, uint64_t &hi) {
-    const uint64_t o = hi;
-    hi = lo ^ (o >> 63) ^ (o >> 62) ^ (o >> 57);
-    lo = o ^ (o << 1) ^ (o << 2) ^ (o << 7);
-}
-
-// One AES encryption with the round table read from global memory (the
-// tweak key; used once per lane per group of 64 units).
-template <int NR>
-__device__ __forceinline__ void encrypt_global(const uint32_t *rk, uint32_t (&s)[4]) {
-    const uint32_t *te0 = g_base;
-    auto T = [&](int t, uint32_t w, int k) { return rotl(te0[(w >> (8 * k)) & 255u], 8 * t); };
-    uint32_t a0 = s[0] ^ rk[0], a1 = s[1] ^ rk[1], a2 = s[2] ^ rk[2], a3 = s[3] ^ rk[3];
-#pragma unroll
-    for (int r = 1; r < NR; r++) {
-        const uint32_t b0 = T(0, a0, 0) ^ T(1, a1, 1) ^ T(2, a2, 2) ^ T(3, a3, 3) ^ rk[4 * r];
-        const uint32_t b1 = T(0, a1, 0) ^ T(1, a2, 1) ^ T(2, a3, 2) ^ T(3, a0, 3) ^ rk[4 * r + 1];
-        const uint32_t b2 = T(0, a2, 0) ^ T(1, a3, 1) ^ T(2, a0, 2) ^ T(3, a1, 3) ^ rk[4 * r + 2];
-        const uint32_t b3 = T(0, a3, 0) ^ T(1, a0, 1) ^ T(2, a1, 2) ^ T(3, a2, 3) ^ rk[4 * r + 3];
-        a0 = b0;
-        a1 = b1;
-        a2 = b2;
-        a3 = b3;
-    }
-    // last round: S[x] is byte 1 of te0[x]
-    auto S = [&](uint32_t w, int k) { return (te0[(w >> (8 * k)) & 255u] >> 8) & 255u; };
-    s[0] = (S(a0, 0) | (S(a1, 1) << 8) | (S(a2, 2) << 16) | (S(a3, 3) << 24)) ^ rk[4 * NR];
-    s[1] = (S(a1, 0) | (S(a2, 1) << 8) | (S(a3, 2) << 16) | (S(a0, 3) << 24)) ^ rk[4 * NR + 1];
-    s[2] = (S(a2, 0) | (S(a3, 1) << 8) | (S(a0, 2) << 16) | (S(a1, 3) << 24)) ^ rk[4 * NR + 2];
-    s[3] = (S(a3, 0) | (S(a0, 1) << 8) | (S(a1, 2) << 16) | (S(a2, 3) << 24)) ^ rk[4 * NR + 3];
-}
 
 template <int NR, int DIR, int BPT>
 __global__ __launch_bounds__(1024) void xts_kernel(const XtsArgs a) {
@@ -121,9 +78,7 @@ __global__ __launch_bounds__(1024) void xts_kernel(const XtsArgs a) {
                     w3 = __builtin_amdgcn_ds_bpermute(int(src << 2), int(tw[3]));
                 }
                 uint64_t lo = uint64_t(w0) | (uint64_t(w1) << 32), hi = uint64_t(w2) | (uint64_t(w3) << 32);
-                mulx_small(lo, hi, j);
-                for (uint32_t q = j >> 6; q > 0; q--)
-                    mulx64(lo, hi);
+                mulx_pow(lo, hi, j);
                 tlo[i] = lo;
                 thi[i] = hi;
                 u32x4 x = vec4(0, 0, 0, 0);

@@ -114,6 +114,46 @@ def test_xts_argument_checks(A, fn):
     call(None, None, 0, rk, rk, nr, 4096, stream=0)                 # empty: a no-op
 
 
+def test_gcm_argument_checks(A):
+    rk, nr = A.aes_expand_key(np.zeros(16, np.uint8))
+    WS, TAG, OK, AAD = 0x40000, 0x50000, 0x60000, 0x70000
+    wsb = A.aes_gcm_workspace_size()
+    assert wsb >= 4096
+
+    def enc(*args, **kw):
+        f = dict(inp=IN, out=OUT, nbytes=64, aad=AAD, aad_bytes=16, roundkeys=rk, Nr=nr, iv=bytes(12),
+                 tag=TAG, workspace=WS, workspace_bytes=wsb, stream=0)
+        f.update(kw)
+        with pytest.raises(A.AESError) as e:
+            A.aes_gcm_encrypt(**f)
+        return e.value.code
+
+    def dec(**kw):
+        f = dict(inp=IN, out=OUT, nbytes=64, aad=AAD, aad_bytes=16, roundkeys=rk, Nr=nr, iv=bytes(12),
+                 tag=TAG, tag_bytes=16, ok=OK, workspace=WS, workspace_bytes=wsb, stream=0)
+        f.update(kw)
+        with pytest.raises(A.AESError) as e:
+            A.aes_gcm_decrypt(**f)
+        return e.value.code
+
+    assert enc(Nr=11) == A.AES_E_NR
+    assert enc(tag=None) == A.AES_E_NULL
+    assert enc(workspace=None) == A.AES_E_NULL
+    assert enc(iv=b"") == A.AES_E_NULL or enc(iv=b"") == A.AES_E_ARG
+    assert enc(iv=bytes(257)) == A.AES_E_ARG
+    assert enc(aad=None) == A.AES_E_NULL
+    assert enc(aad=AAD + 8) == A.AES_E_ALIGN
+    assert enc(workspace=WS + 16) == A.AES_E_ALIGN
+    assert enc(workspace_bytes=wsb - 1) == A.AES_E_LENGTH
+    assert enc(nbytes=(1 << 36)) == A.AES_E_LENGTH
+    assert enc(inp=IN + 4) == A.AES_E_ALIGN
+    assert enc(out=IN + 16) == A.AES_E_OVERLAP
+    assert enc(aad=OUT + 16, aad_bytes=16) == A.AES_E_OVERLAP
+    assert dec(ok=None) == A.AES_E_NULL
+    for tb in (0, 3, 5, 9, 11, 17):
+        assert dec(tag_bytes=tb) == A.AES_E_ARG
+
+
 def test_launch_config_validation(A):
     for bad in ({"layout": 3}, {"blocks_per_thread": 3}, {"wg_size": 100}, {"grid": -1}):
         with pytest.raises(A.AESError) as e:
