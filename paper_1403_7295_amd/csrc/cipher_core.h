@@ -397,11 +397,25 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
                 o = vec4(s[i][0], s[i][1], s[i][2], s[i][3]);
             } else if (MODE == MODE_CBC) {
                 // CBC decryption: P_j = InvCipher(C_j) ^ C_{j-1}, C_{-1} = IV.
-                // The previous block was just loaded by the neighbouring
-                // lane, so this load is served from cache.
-                u32x4 p = vec4(ctr[0], ctr[1], ctr[2], ctr[3]);
-                if (base + jj > 0 && jj < nwhole)
-                    p = load16((inb - 16) + 16u * jj);
+                // C_{j-1} is the neighbouring lane's input, moved one lane up
+                // by a DPP wave shift (a VALU op: no second read of the data,
+                // no LDS); lane 0 takes lane 63 of the previous slot, or for
+                // the first slot the block before the step (the IV before
+                // block 0), one wave-uniform load.
+                u32x4 f;
+                if (i == 0) {
+                    f = vec4(ctr[0], ctr[1], ctr[2], ctr[3]);
+                    if (base > 0)
+                        f = load16(inb - 16);
+                } else {
+                    f = vec4(__builtin_amdgcn_readlane(x[i - 1].x, 63), __builtin_amdgcn_readlane(x[i - 1].y, 63),
+                             __builtin_amdgcn_readlane(x[i - 1].z, 63), __builtin_amdgcn_readlane(x[i - 1].w, 63));
+                }
+                constexpr int kWaveShr1 = 0x138;   // lane l reads lane l - 1; lane 0 keeps `old`
+                const u32x4 p = vec4(__builtin_amdgcn_update_dpp(f.x, x[i].x, kWaveShr1, 0xf, 0xf, false),
+                                     __builtin_amdgcn_update_dpp(f.y, x[i].y, kWaveShr1, 0xf, 0xf, false),
+                                     __builtin_amdgcn_update_dpp(f.z, x[i].z, kWaveShr1, 0xf, 0xf, false),
+                                     __builtin_amdgcn_update_dpp(f.w, x[i].w, kWaveShr1, 0xf, 0xf, false));
                 o = vec4(s[i][0] ^ p.x, s[i][1] ^ p.y, s[i][2] ^ p.z, s[i][3] ^ p.w);
             } else
                 o = vec4(s[i][0] ^ x[i].x, s[i][1] ^ x[i].y, s[i][2] ^ x[i].z, s[i][3] ^ x[i].w);
