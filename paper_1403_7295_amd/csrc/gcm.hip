@@ -161,11 +161,41 @@ __device__ void mul_wave(uint64_t xlo, uint64_t xhi, uint64_t ylo, uint64_t yhi,
     rhi = ahi;
 }
 
-// One wave: H, J0, Cipher_K(J0) and the powers H^(2^t).
+// One AES encryption by every lane of a wave (all with the same input),
+// the row-0 round table in LDS (the other rows are its rotations).
+template <int NR>
+__device__ __forceinline__ void encrypt_one(const uint32_t *t0, const uint32_t *rk, uint32_t (&s)[4]) {
+    auto T = [&](int t, uint32_t w, int k) { return rotl(t0[(w >> (8 * k)) & 255u], 8 * t); };
+    uint32_t a0 = s[0] ^ rk[0], a1 = s[1] ^ rk[1], a2 = s[2] ^ rk[2], a3 = s[3] ^ rk[3];
+#pragma unroll
+    for (int r = 1; r < NR; r++) {
+        const uint32_t b0 = T(0, a0, 0) ^ T(1, a1, 1) ^ T(2, a2, 2) ^ T(3, a3, 3) ^ rk[4 * r];
+        const uint32_t b1 = T(0, a1, 0) ^ T(1, a2, 1) ^ T(2, a3, 2) ^ T(3, a0, 3) ^ rk[4 * r + 1];
+        const uint32_t b2 = T(0, a2, 0) ^ T(1, a3, 1) ^ T(2, a0, 2) ^ T(3, a1, 3) ^ rk[4 * r + 2];
+        const uint32_t b3 = T(0, a3, 0) ^ T(1, a0, 1) ^ T(2, a1, 2) ^ T(3, a2, 3) ^ rk[4 * r + 3];
+        a0 = b0;
+        a1 = b1;
+        a2 = b2;
+        a3 = b3;
+    }
+    // last round: S[x] is byte 1 of T0[x]
+    auto S = [&](uint32_t w, int k) { return (t0[(w >> (8 * k)) & 255u] >> 8) & 255u; };
+    s[0] = (S(a0, 0) | (S(a1, 1) << 8) | (S(a2, 2) << 16) | (S(a3, 3) << 24)) ^ rk[4 * NR];
+    s[1] = (S(a1, 0) | (S(a2, 1) << 8) | (S(a3, 2) << 16) | (S(a0, 3) << 24)) ^ rk[4 * NR + 1];
+    s[2] = (S(a2, 0) | (S(a3, 1) << 8) | (S(a0, 2) << 16) | (S(a1, 3) << 24)) ^ rk[4 * NR + 2];
+    s[3] = (S(a3, 0) | (S(a0, 1) << 8) | (S(a1, 2) << 16) | (S(a2, 3) << 24)) ^ rk[4 * NR + 3];
+}
+
+// One wave: H, J0, Cipher_K(J0) and the powers H^(2^t) that this launch's
+// folding needs (t <= 12 + grid_log2).
 template <int NR>
 __global__ __launch_bounds__(64) void gcm_setup_kernel(const GcmArgs a) {
+    __shared__ uint32_t t0[256];
+    for (uint32_t i = threadIdx.x; i < 256; i += 64)
+        t0[i] = g_base[i];
+    __syncthreads();
     uint32_t h[4] = {0, 0, 0, 0};
-    encrypt_global<NR>(a.rk, h);
+    encrypt_one<NR>(t0, a.rk, h);
     uint64_t hlo, hhi;
     to_poly(h, hlo, hhi);
     uint32_t j0[4];
@@ -196,17 +226,18 @@ __global__ __launch_bounds__(64) void gcm_setup_kernel(const GcmArgs a) {
         from_poly(ylo, yhi, j0);
     }
     uint32_t ej0[4] = {j0[0], j0[1], j0[2], j0[3]};
-    encrypt_global<NR>(a.rk, ej0);
-    const bool writer = (threadIdx.x & 63u) == 0;
+    encrypt_one<NR>(t0, a.rk, ej0);
+    const bool writer = threadIdx.x == 0;
     uint64_t plo = hlo, phi = hhi;
-    for (int t = 0; t < kGcmPowers; t++) {
+    const int tmax = 12 + int(a.grid_log2);
+    for (int t = 0; t <= tmax; t++) {
         if (writer) {
             uint32_t w[4];
             from_poly(plo, phi, w);
             for (int c = 0; c < 4; c++)
                 a.ws->powers[t][c] = w[c];
         }
-        mul_wave(plo, phi, plo, phi, plo, phi);
+        gf_square(plo, phi);
     }
     if (writer)
         for (int c = 0; c < 4; c++) {
@@ -255,6 +286,17 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
     // A chunk of 256 positions that are all whole ciphertext blocks: every
     // chunk but the one holding the length block and a partial block, and
     // those holding additional data.
+    // Round 1 of a counter block: columns 0..2 are J0's first twelve bytes
+    // after AddRoundKey, the same for every block, so 12 of its 16 lookups
+    // are summed once here; a block adds the four on column 3.
+    const uint32_t pre0 = tl<LAYOUT_T4X32, 0, 0>(aes, lc, n0) ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, n1) ^
+                          tl<LAYOUT_T4X32, 2, 2>(aes, lc, n2) ^ a.rk[4];
+    const uint32_t pre1 = tl<LAYOUT_T4X32, 0, 0>(aes, lc, n1) ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, n2) ^
+                          tl<LAYOUT_T4X32, 3, 3>(aes, lc, n0) ^ a.rk[5];
+    const uint32_t pre2 = tl<LAYOUT_T4X32, 0, 0>(aes, lc, n2) ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, n0) ^
+                          tl<LAYOUT_T4X32, 3, 3>(aes, lc, n1) ^ a.rk[6];
+    const uint32_t pre3 = tl<LAYOUT_T4X32, 1, 1>(aes, lc, n0) ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, n1) ^
+                          tl<LAYOUT_T4X32, 3, 3>(aes, lc, n2) ^ a.rk[7];
     auto fast_chunk = [&](uint64_t q) __attribute__((always_inline)) {
         uint32_t s[BPT][4], x[BPT][4];
 #pragma unroll
@@ -267,13 +309,37 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
             x[i][1] = v.y;
             x[i][2] = v.z;
             x[i][3] = v.w;
-            const uint32_t cnt = c1 + uint32_t(top) + (63u - lane);
-            s[i][0] = n0;
-            s[i][1] = n1;
-            s[i][2] = n2;
-            s[i][3] = __builtin_bswap32(cnt) ^ a.rk[3];
+            // rounds 1 and 2 (the counters of the slot are cs .. cs + 63)
+            const uint32_t cs = c1 + uint32_t(top);
+            const uint32_t v3 = __builtin_bswap32(cs + (63u - lane)) ^ a.rk[3];
+            const uint32_t t0 = pre0 ^ tl<LAYOUT_T4X32, 3, 3>(aes, lc, v3);
+            if ((cs & 255u) + 64u <= 256u) {
+                // the slot's counters share their top 24 bits: after round 1
+                // columns 1..3 are the same for all 64 blocks, and so are 12
+                // of round 2's lookups (15 lookups per slot, not per block)
+                const uint32_t g3 = __builtin_bswap32(cs) ^ a.rk[3];
+                const uint32_t t1 = pre1 ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, g3);
+                const uint32_t t2 = pre2 ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, g3);
+                const uint32_t t3 = pre3 ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, g3);
+                s[i][0] = xor3(tl<LAYOUT_T4X32, 1, 1>(aes, lc, t1), tl<LAYOUT_T4X32, 2, 2>(aes, lc, t2),
+                               tl<LAYOUT_T4X32, 3, 3>(aes, lc, t3)) ^ a.rk[8] ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, t0);
+                s[i][1] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t1), tl<LAYOUT_T4X32, 1, 1>(aes, lc, t2),
+                               tl<LAYOUT_T4X32, 2, 2>(aes, lc, t3)) ^ a.rk[9] ^ tl<LAYOUT_T4X32, 3, 3>(aes, lc, t0);
+                s[i][2] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t2), tl<LAYOUT_T4X32, 1, 1>(aes, lc, t3),
+                               tl<LAYOUT_T4X32, 3, 3>(aes, lc, t1)) ^ a.rk[10] ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, t0);
+                s[i][3] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t3), tl<LAYOUT_T4X32, 2, 2>(aes, lc, t1),
+                               tl<LAYOUT_T4X32, 3, 3>(aes, lc, t2)) ^ a.rk[11] ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, t0);
+            } else {
+                const uint32_t t1 = pre1 ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, v3);
+                const uint32_t t2 = pre2 ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, v3);
+                const uint32_t t3 = pre3 ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, v3);
+                s[i][0] = round_col<LAYOUT_T4X32>(aes, lc, t0, t1, t2, t3, a.rk[8]);
+                s[i][1] = round_col<LAYOUT_T4X32>(aes, lc, t1, t2, t3, t0, a.rk[9]);
+                s[i][2] = round_col<LAYOUT_T4X32>(aes, lc, t2, t3, t0, t1, a.rk[10]);
+                s[i][3] = round_col<LAYOUT_T4X32>(aes, lc, t3, t0, t1, t2, a.rk[11]);
+            }
         }
-        rounds<NR, DIR_ENC, LAYOUT_T4X32, BPT>(s, aes, lc, a.rk, 1);
+        rounds<NR, DIR_ENC, LAYOUT_T4X32, BPT>(s, aes, lc, a.rk, 3);
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
             const uint64_t top = nC - 256 * q - 64u * uint32_t(i) - 63;
@@ -385,18 +451,21 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
     }
 }
 
-// One workgroup of 256: folds the workgroups' partial sums with the factors
+// One workgroup: folds the workgroups' partial sums with the factors
 // H^(4096 b), multiplies by H and forms (or checks) the tag.
-__global__ __launch_bounds__(256) void gcm_final_kernel(const GcmArgs a) {
-    constexpr uint32_t kTabs = 9, kParts = kTabs * kTabBytes + kTabs * kVecBytes;
-    __shared__ uint32_t lds[(kParts + 256 * 16) / 4];
-    // tables 0..7 hold H^4096 .. H^(4096 * 128), table 8 holds H
-    build_tables(lds, 0, kTabs * kTabBytes, a.ws, int(kTabs), [](int k) { return k < 8 ? 12 + k : 0; });
+__global__ __launch_bounds__(1024) void gcm_final_kernel(const GcmArgs a) {
+    constexpr uint32_t kMaxTabs = 9, kParts = kMaxTabs * kTabBytes + kMaxTabs * kVecBytes;
+    __shared__ uint32_t lds[(kParts + kGcmMaxGrid * 16) / 4];
+    // tables 0 .. lg-1 hold H^4096 .. H^(4096 * 2^(lg-1)), table lg holds H
+    const int lg = int(a.grid_log2);
+    build_tables(lds, 0, uint32_t(lg + 1) * kTabBytes, a.ws, lg + 1, [lg](int k) { return k < lg ? 12 + k : 0; });
     const uint32_t t = threadIdx.x, grid = 1u << a.grid_log2;
-    u32x4 p = vec4(0, 0, 0, 0);
-    if (t < grid)
-        p = vec4(a.ws->partials[t][0], a.ws->partials[t][1], a.ws->partials[t][2], a.ws->partials[t][3]);
-    lds_store16(lds, kParts + 16u * t, p);
+    if (t < kGcmMaxGrid) {
+        u32x4 p = vec4(0, 0, 0, 0);
+        if (t < grid)
+            p = vec4(a.ws->partials[t][0], a.ws->partials[t][1], a.ws->partials[t][2], a.ws->partials[t][3]);
+        lds_store16(lds, kParts + 16u * t, p);
+    }
     __syncthreads();
     for (uint32_t k = 0, d = 1; d < grid; k++, d <<= 1) {
         if ((t & (2 * d - 1)) == 0 && t + d < grid) {
@@ -411,7 +480,7 @@ __global__ __launch_bounds__(256) void gcm_final_kernel(const GcmArgs a) {
     if (t == 0) {
         const u32x4 o = lds_load16(lds, kParts);
         uint32_t sum[4] = {o.x, o.y, o.z, o.w};
-        mul_tab(lds, 8 * kTabBytes, sum, sum);
+        mul_tab(lds, uint32_t(lg) * kTabBytes, sum, sum);
         uint8_t tag[16];
         for (int b = 0; b < 16; b++)
             tag[b] = uint8_t((sum[b >> 2] ^ a.ws->ej0[b >> 2]) >> (8 * (b & 3)));
@@ -448,7 +517,7 @@ hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream) {
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(gcm_final_kernel, dim3(1), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(gcm_final_kernel, dim3(1), dim3(1024), 0, stream, a);
     return hipGetLastError();
 }
 

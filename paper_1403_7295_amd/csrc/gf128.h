@@ -41,6 +41,29 @@ __device__ __forceinline__ void mulx_pow(uint64_t &lo, uint64_t &hi, uint32_t e)
         mulx64(lo, hi);
 }
 
+// v * v.  Squaring is linear over GF(2): coefficient i moves to 2i (the bits
+// spread out with zeros between them), and the upper 128 bits of the
+// 255-bit result fold back through x^128 = x^7 + x^2 + x + 1.
+__device__ __forceinline__ uint64_t spread32(uint32_t w) {
+    uint64_t x = w;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+__device__ __forceinline__ void gf_square(uint64_t &lo, uint64_t &hi) {
+    const uint64_t w0 = spread32(uint32_t(lo)), w1 = spread32(uint32_t(lo >> 32));
+    const uint64_t a0 = spread32(uint32_t(hi)), a1 = spread32(uint32_t(hi >> 32));
+    // (a1:a0) * (x^7 + x^2 + x + 1): its bits above x^127 (at most 7 of
+    // them, o) fold back once more
+    const uint64_t o = (a1 >> 63) ^ (a1 >> 62) ^ (a1 >> 57);
+    lo = w0 ^ a0 ^ (a0 << 1) ^ (a0 << 2) ^ (a0 << 7) ^ o ^ (o << 1) ^ (o << 2) ^ (o << 7);
+    hi = w1 ^ a1 ^ ((a1 << 1) | (a0 >> 63)) ^ ((a1 << 2) | (a0 >> 62)) ^ ((a1 << 7) | (a0 >> 57));
+}
+
 // A GCM block given as four little-endian words (bytes 0..15 in memory
 // order) to the arithmetic form, and back: the bits of each byte reversed.
 __device__ __forceinline__ uint32_t rev_bits_in_bytes(uint32_t w) {
