@@ -1,6 +1,7 @@
 /*
  * aesgpu: AES (FIPS-197) encryption and decryption of large device-resident
- * buffers on AMD Instinct MI355X (gfx950), in ECB and CTR mode.
+ * buffers on AMD Instinct MI355X (gfx950), in ECB and CTR mode, and in the
+ * modes after the paper's: CBC, XTS and GCM.
  *
  * The operation is the one the paper (Barnes, Fernando, Mettananda, Ragel,
  * "Improving the Throughput of the AES Algorithm with Multicore Processors")
@@ -53,8 +54,10 @@ typedef enum {
 /* ECB and CTR: every block independent.  CBC (SP 800-38A section 6.2, one of
  * the modes after the paper's): decryption is block-parallel (each block
  * needs the previous ciphertext block); encryption is serial by definition
- * and runs on one lane per message. */
-typedef enum { AES_MODE_ECB = 0, AES_MODE_CTR = 1, AES_MODE_CBC = 2 } aes_mode;
+ * and runs on one lane per message.  XTS (IEEE 1619) is a mode of batch
+ * descriptors only; single buffers use aes_xts_encrypt / aes_xts_decrypt
+ * (aes_encrypt with AES_MODE_XTS is AES_E_MODE). */
+typedef enum { AES_MODE_ECB = 0, AES_MODE_CTR = 1, AES_MODE_CBC = 2, AES_MODE_XTS = 3 } aes_mode;
 
 /*
  * Key Expansion (FIPS-197 section 5.2; the paper's first step,
@@ -82,7 +85,7 @@ int aes_expand_key(const uint8_t *key, int keybits, uint8_t *roundkeys, int *Nr)
  *   roundkeys  host pointer to the 16*(Nr+1)-byte ENCRYPTION schedule as
  *              written by aes_expand_key.
  *   Nr         10, 12 or 14.
- *   mode       AES_MODE_ECB or AES_MODE_CTR.
+ *   mode       AES_MODE_ECB, AES_MODE_CTR or AES_MODE_CBC.
  *   ctr0       CTR: host pointer to the 16-byte initial counter block; block
  *              j uses bytes 0..11 of ctr0 followed by (c0 + j) mod 2^32 in
  *              big-endian order, c0 being the big-endian value of
@@ -262,7 +265,11 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
  * blocks; CTR messages may end in a partial block.  ctr0 is the initial
  * counter block (CTR) or the IV (CBC) exactly as for aes_encrypt.  A CBC
  * decryption whose input and output share bytes is rejected; a CBC
- * encryption runs serially on one lane.
+ * encryption runs serially on one lane.  XTS messages (whole blocks, as
+ * aes_xts_encrypt) use key_idx for the data key and ctr0 for the rest, all
+ * little-endian: bytes 0..7 the tweak value of the message's first data
+ * unit, 8..11 the key slot of the tweak key (same key size), 12..15 the
+ * data-unit size in bytes (a power of two, 16 .. 4096).
  */
 typedef struct {
     uint64_t in_off;
@@ -270,7 +277,7 @@ typedef struct {
     uint64_t nbytes;
     uint32_t key_idx;
     uint8_t keybits_code;  /* 0 = 128, 1 = 192, 2 = 256 */
-    uint8_t mode;          /* AES_MODE_ECB or AES_MODE_CTR */
+    uint8_t mode;          /* AES_MODE_ECB, _CTR, _CBC or _XTS */
     uint8_t decrypt;       /* 0 = encrypt, 1 = decrypt */
     uint8_t reserved;
     uint8_t ctr0[16];

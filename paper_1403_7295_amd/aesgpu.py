@@ -30,8 +30,9 @@ AES_E_ARG = 9
 AES_MODE_ECB = 0
 AES_MODE_CTR = 1
 AES_MODE_CBC = 2
+AES_MODE_XTS = 3      # batch descriptors only
 
-MODES = {"ecb": AES_MODE_ECB, "ctr": AES_MODE_CTR, "cbc": AES_MODE_CBC}
+MODES = {"ecb": AES_MODE_ECB, "ctr": AES_MODE_CTR, "cbc": AES_MODE_CBC, "xts": AES_MODE_XTS}
 
 # every function the header declares, with its ctypes signature
 _SIGNATURES = {
@@ -402,6 +403,13 @@ def make_descs(nbytes, in_off=None, out_off=None, key_idx=None, keybits=128, mod
     if ctr0 is not None:
         d["ctr0"] = np.broadcast_to(np.asarray(ctr0, dtype=np.uint8), (n, 16))
     return d
+
+
+def xts_ctr0(first_unit, key2_idx, unit_bytes):
+    """The ctr0 field of an XTS batch descriptor: tweak value of the first data
+    unit, key slot of the tweak key, data-unit size (little-endian)."""
+    return np.frombuffer(int(first_unit).to_bytes(8, "little") + int(key2_idx).to_bytes(4, "little") +
+                         int(unit_bytes).to_bytes(4, "little"), dtype=np.uint8).copy()
 
 
 class Batch:

@@ -3,12 +3,15 @@
 //
 //   keyexp_kernel   one lane per message: Key Expansion on the device
 //                   (FIPS-197 section 5.2), plus the equivalent-inverse
-//                   schedule (section 5.3.5) for ECB decryption.
+//                   schedule (section 5.3.5) for decryption and the tweak
+//                   key's schedule for XTS.
 //   plan_kernel     one workgroup: checks every descriptor, cuts each message
 //                   into tiles of at most T blocks (a tile never spans two
-//                   messages), and lays the tiles out in two lists: forward
-//                   (ECB encryption and CTR, which use the encryption tables)
-//                   and inverse (ECB decryption, which uses the inverse ones).
+//                   messages; an XTS tile is whole groups of 64 data units),
+//                   and lays the tiles out in three lists: forward (ECB
+//                   encryption, CTR, XTS encryption: the encryption tables),
+//                   inverse (ECB, CBC and XTS decryption: the inverse ones)
+//                   and serial (CBC encryption, one message per tile).
 //                   It also zeroes the two tile counters, so the sequence can
 //                   be replayed from a graph without any memset.
 //   batch_kernel    persistent, one per list: every wave takes the next tile
@@ -24,6 +27,7 @@
 #include "aesgpu.h"
 #include "cipher_core.h"
 #include "internal.h"
+#include "xts_core.h"
 
 namespace aesgpu {
 namespace {
@@ -32,12 +36,33 @@ constexpr int kPlanThreads = 1024;
 
 __device__ __forceinline__ int desc_nr(const aes_msg_desc &d) { return 10 + 2 * int(d.keybits_code); }
 
+__device__ __forceinline__ uint32_t le32(const uint8_t *p) {
+    return uint32_t(p[0]) | (uint32_t(p[1]) << 8) | (uint32_t(p[2]) << 16) | (uint32_t(p[3]) << 24);
+}
+
+// XTS messages carry in ctr0: bytes 0..7 the tweak value of the first data
+// unit, 8..11 the slot of the tweak key, 12..15 the data-unit size in bytes
+// (all little-endian).
+__device__ __forceinline__ uint64_t xts_first_unit(const aes_msg_desc &d) {
+    return uint64_t(le32(d.ctr0)) | (uint64_t(le32(d.ctr0 + 4)) << 32);
+}
+__device__ __forceinline__ uint32_t xts_key2(const aes_msg_desc &d) { return le32(d.ctr0 + 8); }
+__device__ __forceinline__ uint32_t xts_unit_bytes(const aes_msg_desc &d) { return le32(d.ctr0 + 12); }
+__device__ __forceinline__ uint32_t xts_unit_shift(const aes_msg_desc &d) {
+    return 31u - __builtin_clz(xts_unit_bytes(d) >> 4);   // log2 of the blocks per unit
+}
+
 // Same test as the host applies to a single-buffer call, plus bounds.
 __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKArgs &a) {
-    if (d.keybits_code > 2 || d.mode > AES_MODE_CBC || d.decrypt > 1)
+    if (d.keybits_code > 2 || d.mode > AES_MODE_XTS || d.decrypt > 1)
         return false;
-    if ((d.mode == AES_MODE_ECB || d.mode == AES_MODE_CBC) && (d.nbytes & 15u))
+    if ((d.mode == AES_MODE_ECB || d.mode == AES_MODE_CBC || d.mode == AES_MODE_XTS) && (d.nbytes & 15u))
         return false;
+    if (d.mode == AES_MODE_XTS) {
+        const uint32_t u = xts_unit_bytes(d);
+        if (u < 16 || u > 4096 || (u & (u - 1)) != 0 || xts_key2(d) >= uint32_t(a.nkeys))
+            return false;
+    }
     // CBC decryption reads block j-1 of the input after other waves may have
     // written their outputs: input and output must not share bytes
     if (d.mode == AES_MODE_CBC && d.decrypt && a.in_base == a.out_base && d.nbytes &&
@@ -57,12 +82,21 @@ __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKAr
     return true;
 }
 
-// Forward list (encryption tables): ECB encrypt, CTR.  Inverse list
-// (decryption tables): ECB and CBC decrypt.  Serial list: CBC encrypt.
+// Forward list (encryption tables): ECB encrypt, CTR, XTS encrypt.  Inverse
+// list (decryption tables): ECB, CBC and XTS decrypt.  Serial list: CBC
+// encrypt.
 __device__ __forceinline__ int desc_class(const aes_msg_desc &d) {
     if (d.mode == AES_MODE_CBC)
         return d.decrypt ? 1 : 2;
-    return (d.mode == AES_MODE_ECB && d.decrypt) ? 1 : 0;
+    return ((d.mode == AES_MODE_ECB || d.mode == AES_MODE_XTS) && d.decrypt) ? 1 : 0;
+}
+
+// Blocks per XTS tile: whole groups of 64 data units (the unit of the tweak
+// work), as many as fit in the tile size, at least one.
+__device__ __forceinline__ uint64_t xts_tile_blocks(const aes_msg_desc &d, uint32_t tile_blocks) {
+    const uint64_t group = uint64_t(64) << xts_unit_shift(d);
+    const uint64_t g = tile_blocks / group;
+    return (g ? g : 1) * group;
 }
 
 __device__ __forceinline__ uint32_t batch_count(const BatchKArgs &a) {
@@ -87,17 +121,8 @@ __device__ __forceinline__ uint32_t inv_mix_column(uint32_t w) {
            rotl(g_base[256 + sbox(w >> 16)], 16) ^ rotl(g_base[256 + sbox(w >> 24)], 24);
 }
 
-__global__ __launch_bounds__(256) void keyexp_kernel(const BatchKArgs a) {
-    const uint32_t n = batch_count(a);
-    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n)
-        return;
-    const aes_msg_desc d = a.desc[m];
-    if (!desc_valid(d, a))
-        return;
-    const int nk = 4 + 2 * int(d.keybits_code), nr = nk + 6;
-    uint32_t *w = a.keytab + size_t(m) * kKeySlotWords;
-    const uint8_t *key = a.keys + size_t(d.key_idx) * 32;
+// Key Expansion (FIPS-197 section 5.2) of the key at `key` into w[0 .. 4Nr+3].
+__device__ void expand_key_words(const uint8_t *key, int nk, int nr, uint32_t *w) {
     uint32_t prev = 0;
     for (int i = 0; i < nk; i++) {
         prev = uint32_t(key[4 * i]) | (uint32_t(key[4 * i + 1]) << 8) | (uint32_t(key[4 * i + 2]) << 16) |
@@ -116,6 +141,19 @@ __global__ __launch_bounds__(256) void keyexp_kernel(const BatchKArgs a) {
         prev = w[i - nk] ^ t;
         w[i] = prev;
     }
+}
+
+__global__ __launch_bounds__(256) void keyexp_kernel(const BatchKArgs a) {
+    const uint32_t n = batch_count(a);
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n)
+        return;
+    const aes_msg_desc d = a.desc[m];
+    if (!desc_valid(d, a))
+        return;
+    const int nk = 4 + 2 * int(d.keybits_code), nr = nk + 6;
+    uint32_t *w = a.keytab + size_t(m) * kKeySlotWords;
+    expand_key_words(a.keys + size_t(d.key_idx) * 32, nk, nr, w);
     if (desc_class(d) == 1) {
         uint32_t *dk = w + kKeySlotWords / 2;
         for (int c = 0; c < 4; c++) {
@@ -126,13 +164,18 @@ __global__ __launch_bounds__(256) void keyexp_kernel(const BatchKArgs a) {
             for (int c = 0; c < 4; c++)
                 dk[4 * r + c] = inv_mix_column(w[4 * (nr - r) + c]);
     }
+    // XTS: the tweak key's encryption schedule in the half of the slot the
+    // data key's direction leaves free
+    if (d.mode == AES_MODE_XTS)
+        expand_key_words(a.keys + size_t(xts_key2(d)) * 32, nk, nr, w + (d.decrypt ? 0 : kKeySlotWords / 2));
 }
 
 __device__ __forceinline__ uint64_t tiles_of(const aes_msg_desc &d, uint32_t tile_blocks) {
     const uint64_t nblk = (d.nbytes + 15) >> 4;
     if (desc_class(d) == 2)
         return nblk ? 1 : 0;
-    return (nblk + tile_blocks - 1) / tile_blocks;
+    const uint64_t step = d.mode == AES_MODE_XTS ? xts_tile_blocks(d, tile_blocks) : tile_blocks;
+    return (nblk + step - 1) / step;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) {
@@ -182,7 +225,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
             continue;
         const uint64_t nblk = (d.nbytes + 15) >> 4;
         BatchTile *list = a.tiles + size_t(k) * a.tile_capacity;
-        const uint64_t step = k == 2 ? nblk : a.tile_blocks;   // a serial message is one tile
+        // a serial message is one tile; XTS tiles are whole groups of units
+        const uint64_t step = k == 2 ? nblk : d.mode == AES_MODE_XTS ? xts_tile_blocks(d, a.tile_blocks)
+                                                                     : uint64_t(a.tile_blocks);
         for (uint64_t first = 0; first < nblk; first += step) {
             BatchTile t;
             t.msg = m;
@@ -234,6 +279,27 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const LaneConsts &
     uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
     process_blocks<NR, MODE, DIR, LAYOUT_T4X32, BPT>(lds, lc, rk, ctr, in, out, d.nbytes, t.first,
                                                      t.first + t.count, 64u * BPT);
+}
+
+// An XTS tile: whole groups of 64 data units starting at a unit boundary.
+template <int NR, int DIR, int BPT>
+__device__ __forceinline__ void run_xts_tile(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
+                                             const aes_msg_desc &d, const BatchTile &t) {
+    const uint32_t *slot = a.keytab + size_t(t.msg) * kKeySlotWords;
+    const uint32_t *rkp = slot + (DIR == DIR_DEC ? kKeySlotWords / 2 : 0);
+    uint32_t rk[4 * (NR + 1)];
+#pragma unroll
+    for (int i = 0; i < 4 * (NR + 1); i++)
+        rk[i] = __builtin_amdgcn_readfirstlane(rkp[i]);
+    const uint32_t *rk2 = slot + (DIR == DIR_DEC ? 0 : kKeySlotWords / 2);   // read once per group
+    const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
+    uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
+    const uint32_t ushift = xts_unit_shift(d);
+    const uint64_t group = uint64_t(64) << ushift, end = t.first + t.count;
+    const uint64_t first_unit = xts_first_unit(d);
+    for (uint64_t gb0 = t.first; gb0 < end; gb0 += group)
+        xts_group<NR, DIR, BPT>(lds, lc, rk, rk2, in, out, gb0, min(end, gb0 + group),
+                                first_unit + (gb0 >> ushift), ushift);
 }
 
 // The serial list (CBC encryption): every wave takes 64 messages at a time,
@@ -309,7 +375,12 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchKArgs a) {
         const BatchTile tile = list[t];
         const aes_msg_desc d = a.desc[tile.msg];
         const int nr = desc_nr(d);
-        if (CLASS == 1 && d.mode == AES_MODE_CBC) {
+        if (d.mode == AES_MODE_XTS) {
+            constexpr int XDIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
+            if (nr == 10) run_xts_tile<10, XDIR, BPT>(lds, lc, a, d, tile);
+            else if (nr == 12) run_xts_tile<12, XDIR, BPT>(lds, lc, a, d, tile);
+            else run_xts_tile<14, XDIR, BPT>(lds, lc, a, d, tile);
+        } else if (CLASS == 1 && d.mode == AES_MODE_CBC) {
             if (nr == 10) run_tile<10, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
             else if (nr == 12) run_tile<12, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
             else run_tile<14, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);

@@ -26,11 +26,12 @@ def O():
     return ref.default()
 
 
-def mixed_messages(A, n, seed, max_len=1 << 16, min_len=0, mode=None, decrypt=None, modes=3):
-    """n messages of every kind: ECB encrypt/decrypt, CTR and CBC
-    encrypt/decrypt, 128/192/256-bit keys, lengths log-uniform in
-    [1, max_len] (ECB and CBC rounded up to whole blocks), a few empty ones
-    (unless min_len > 0), counters that wrap."""
+def mixed_messages(A, n, seed, max_len=1 << 16, min_len=0, mode=None, decrypt=None, modes=4):
+    """n messages of every kind: ECB encrypt/decrypt, CTR, CBC and XTS
+    encrypt/decrypt (the first `modes` modes), 128/192/256-bit keys, lengths
+    log-uniform in [1, max_len] (all but CTR rounded up to whole blocks), a
+    few empty ones (unless min_len > 0), counters that wrap, XTS data units of
+    16 B .. 4 KiB with the tweak key in another message's key slot."""
     rng = np.random.default_rng(seed)
     lens = np.maximum(seedgen.log_uniform_lengths(rng, n, 1, max_len), min_len)
     mode = rng.integers(0, modes, n) if mode is None else np.full(n, mode)
@@ -41,11 +42,15 @@ def mixed_messages(A, n, seed, max_len=1 << 16, min_len=0, mode=None, decrypt=No
         lens[rng.choice(n, 3, replace=False)] = 0
     keys = np.zeros((n, 32), np.uint8)
     ctr0 = np.zeros((n, 16), np.uint8)
+    units = rng.choice([16, 32, 512, 4096], n)
     for m in range(n):
         keys[m, :keybits[m] // 8] = seedgen.key(seed, m, int(keybits[m]))
         ctr0[m] = seedgen.nonce(seed, m)
         if m % 7 == 0:
             ctr0[m, 12:16] = [0xFF, 0xFF, 0xFF, 0xF8]   # wraps inside the message
+        if mode[m] == 3:
+            first = int(rng.integers(0, 1 << 62)) if m % 3 else (1 << 64) - 5   # and one that wraps
+            ctr0[m] = A.xts_ctr0(first, (m + 1) % n, int(units[m]))
     descs = A.make_descs(lens, keybits=keybits, mode=mode, decrypt=decrypt, ctr0=ctr0)
     return descs, keys
 
@@ -59,9 +64,19 @@ def buffers(descs, seed):
     return x, xd, yd
 
 
-def oracle_message(O, d, key, x):
+def xts_fields(d):
+    c = bytes(d["ctr0"])
+    return (int.from_bytes(c[0:8], "little"), int.from_bytes(c[8:12], "little"),
+            int.from_bytes(c[12:16], "little"))
+
+
+def oracle_message(O, d, keys, x):
     bits = 128 + 64 * int(d["keybits_code"])
-    rk, nr = O.expand_key(key[:bits // 8])
+    rk, nr = O.expand_key(keys[int(d["key_idx"])][:bits // 8])
+    if d["mode"] == 3:
+        first, key2, unit = xts_fields(d)
+        rk2, _ = O.expand_key(keys[key2][:bits // 8])
+        return O.xts(bool(d["decrypt"]), rk, rk2, nr, unit, first, x)
     if d["mode"] == 0:
         return O.ecb_decrypt(rk, nr, x) if d["decrypt"] else O.ecb_encrypt(rk, nr, x)
     if d["mode"] == 2:
@@ -73,7 +88,7 @@ def check_against_oracle(O, descs, keys, x, y):
     for m, d in enumerate(descs):
         n = int(d["nbytes"])
         i, o = int(d["in_off"]), int(d["out_off"])
-        want = oracle_message(O, d, keys[int(d["key_idx"])], x[i:i + n])
+        want = oracle_message(O, d, keys, x[i:i + n])
         if not np.array_equal(y[o:o + n], want):
             raise AssertionError("message %d (%s) differs" % (m, d))
 
@@ -142,15 +157,19 @@ def test_invalid_descriptors_are_skipped(A, O):
     bad["key_idx"][3] = len(keys)                  # no such key
     x, xd, yd = buffers(descs, 46)
     bad["nbytes"][4] = xd.numel() + 16             # outside the buffers
+    for m, (unit, key2, nbytes) in zip((5, 6, 7), ((24, 0, 64), (512, len(keys), 64), (512, 0, 40))):
+        bad["mode"][m] = 3                         # XTS: unit not a power of two, no such
+        bad["ctr0"][m] = A.xts_ctr0(0, key2, unit)  # tweak key, not whole blocks
+        bad["nbytes"][m] = nbytes
     b = A.Batch(bad, keys, xd, yd)
     b.run()
     tiles, rejected = b.query()
-    assert rejected == 5
+    assert rejected == 8
     y = yd.cpu().numpy()
-    for m in range(5):
+    for m in range(8):
         o, n = int(descs["out_off"][m]), int(descs["nbytes"][m])
         assert (y[o:o + n] == SENTINEL).all(), "rejected message %d was written" % m
-    check_against_oracle(O, descs[5:], keys, x, y)
+    check_against_oracle(O, descs[8:], keys, x, y)
 
 
 def test_tile_overflow_is_reported(A):
@@ -218,3 +237,39 @@ def test_many_serial_cbc_messages(A, O):
     tiles, rejected = b.query()
     assert rejected == 0
     check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
+
+
+@pytest.mark.parametrize("decrypt", [0, 1])
+def test_xts_sector_batch_equals_plain(A, O, decrypt):
+    """A storage-like batch: 3,000 requests of 1 .. 64 data units of 512 B or
+    4 KiB, each with its own key pair and starting sector, against one
+    aes_xts_* call per request, and sampled requests against the oracle."""
+    rng = np.random.default_rng(48 + decrypt)
+    n = 3000
+    unit = rng.choice([512, 4096], n)
+    lens = unit * rng.integers(1, 65, n)
+    keybits = rng.choice([128, 256], n)
+    first = rng.integers(0, 1 << 40, n)
+    keys = np.zeros((2 * n, 32), np.uint8)
+    ctr0 = np.zeros((n, 16), np.uint8)
+    for m in range(n):
+        keys[2 * m, :keybits[m] // 8] = seedgen.key(48, 2 * m, int(keybits[m]))
+        keys[2 * m + 1, :keybits[m] // 8] = seedgen.key(48, 2 * m + 1, int(keybits[m]))
+        ctr0[m] = A.xts_ctr0(int(first[m]), 2 * m + 1, int(unit[m]))
+    descs = A.make_descs(lens, key_idx=2 * np.arange(n), keybits=keybits, mode="xts", decrypt=decrypt,
+                         ctr0=ctr0)
+    x, xd, yd = buffers(descs, 48)
+    b = A.Batch(descs, keys, xd, yd)
+    b.run()
+    assert b.query()[1] == 0
+    zd = torch.full_like(yd, SENTINEL)
+    fn = A.aes_xts_decrypt if decrypt else A.aes_xts_encrypt
+    for m in range(n):
+        o, ln, bits = int(descs["in_off"][m]), int(lens[m]), int(keybits[m])
+        rk1, nr = A.aes_expand_key(keys[2 * m][:bits // 8])
+        rk2, _ = A.aes_expand_key(keys[2 * m + 1][:bits // 8])
+        fn(xd[o:o + ln], zd[o:o + ln], ln, rk1, rk2, nr, int(unit[m]), int(first[m]))
+    torch.cuda.synchronize()
+    assert torch.equal(yd, zd)
+    y = yd.cpu().numpy()
+    check_against_oracle(O, descs[::97], keys, x, y)
