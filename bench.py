@@ -362,6 +362,11 @@ def main():
             w, k = timed_launches(torch, stream, lambda: A.aes_gcm_decrypt(
                 y, x, n, gaad, 16, rk, nr, giv, gtag, 16, gok, gws, stream=stream), 10, 2)
             sec["aes%d_gcm_dec" % bits] = {"GB/s": round(n / k / 1e9, 1)}
+        # GMAC: the tag of 1 GiB of additional data with no plaintext
+        rk, nr = A.aes_expand_key(key128)
+        w, k = timed_launches(torch, stream, lambda: A.aes_gcm_encrypt(
+            x, y, 0, x, n, rk, nr, giv, gtag, gws, stream=stream), 10, 2)
+        sec["aes128_gmac"] = {"GB/s": round(n / k / 1e9, 1)}
         # the decryptions above wrote the plaintext back into x
         # the 1 MiB case (AES-128 ECB): it stays in the caches between launches
         rk, nr = A.aes_expand_key(key128)

@@ -355,6 +355,23 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
     // Any other chunk, one slot of 64 positions at a time: the length block,
     // ciphertext blocks (whole or the partial last one), additional data, or
     // nothing past the start of the sequence.
+    // A chunk of 256 positions that are all whole blocks of additional data:
+    // only the hash (GMAC over long additional data runs here).
+    auto aad_chunk = [&](uint64_t q) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            // position r is additional-data block k = nC + nA - r; the slot's
+            // 64 blocks end at block nC + nA - 256q - 64i
+            const uint64_t top = nC + nA - 256 * q - 64u * uint32_t(i) - 63;
+            const u32x4 v = load16(a.aad + 16 * top + 16u * (63u - lane));
+            uint32_t g[4];
+            mul_tab(lds, kGTab, W[i], g);
+            W[i][0] = g[0] ^ v.x;
+            W[i][1] = g[1] ^ v.y;
+            W[i][2] = g[2] ^ v.z;
+            W[i][3] = g[3] ^ v.w;
+        }
+    };
     auto slow_chunk = [&](uint64_t q) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
@@ -398,6 +415,8 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
         for (;;) {
             if (q >= 1 && 256 * q + 255 <= nC)
                 fast_chunk(q);
+            else if (256 * q > nC && 256 * q + 255 <= nC + nA && nC + nA - 256 * q < awhole)
+                aad_chunk(q);
             else
                 slow_chunk(q);
             if (q < nwaves)

@@ -155,6 +155,21 @@ def test_gcm_16mib_whole(A, O, ws):
     assert_same(tag, want_tag, "16 MiB tag")
 
 
+@pytest.mark.parametrize("nbytes,aad_bytes", [(0, (1 << 24) + 5), ((1 << 20) + 3, (1 << 22) + 16)])
+def test_gcm_long_additional_data(A, O, ws, nbytes, aad_bytes):
+    # whole chunks of additional data take their own path (hash only): GMAC
+    # over 16 MiB, and a message whose additional data outweighs it
+    rk, nr = A.aes_expand_key(seedgen.key(58, 0, 256))
+    iv = seedgen.nonce(58, 0)[:12]
+    pt = seedgen.data_np(58, 1, nbytes)
+    aad = seedgen.data_np(58, 2, aad_bytes)
+    want_ct, want_tag = O.gcm_encrypt(rk, nr, iv, aad, pt)
+    ct, tag = gpu_encrypt(A, ws, rk, nr, iv, aad, pt)
+    assert_same(ct, want_ct, "long AAD ciphertext")
+    assert_same(tag, want_tag, "long AAD tag")
+    assert gpu_decrypt(A, ws, rk, nr, iv, aad, ct, tag)[1] == 1
+
+
 def h_power(O, h, e):
     """H^e by square and multiply with the oracle's product."""
     one = np.zeros(16, np.uint8)
