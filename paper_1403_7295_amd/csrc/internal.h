@@ -112,8 +112,9 @@ hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream);
 // ---- batches (batch_kernels.hip) -------------------------------------------
 // Workspace = header | key schedules (max_msgs slots) | tiles[3][capacity].
 struct BatchHeader {
-    uint32_t ntiles[3];   // forward list (ECB encrypt, CTR), inverse list (ECB and CBC
-                          // decrypt), serial list (CBC encrypt: one whole message each)
+    uint32_t ntiles[3];   // forward list (ECB encrypt, CTR, XTS encrypt), inverse list (ECB,
+                          // CBC and XTS decrypt), serial list (CBC encrypt: one whole
+                          // message each)
     uint32_t next[3];     // next tile to hand out, per list
     uint32_t rejected;    // messages whose descriptor failed the checks
     uint32_t overflow;    // 1 if the tiles did not fit the workspace
@@ -127,7 +128,9 @@ struct BatchTile {
     uint64_t first;   // first block of the tile within its message
 };
 
-constexpr int kKeySlotWords = 128;  // encryption schedule at 0, decryption schedule at 64
+// encryption schedule at 0, decryption schedule at 64; an XTS message keeps
+// its tweak key's encryption schedule in the half its direction leaves free
+constexpr int kKeySlotWords = 128;
 
 struct BatchKArgs {
     const aes_msg_desc *desc;
