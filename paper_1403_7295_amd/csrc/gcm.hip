@@ -299,6 +299,7 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
                           tl<LAYOUT_T4X32, 3, 3>(aes, lc, n2) ^ a.rk[7];
     auto fast_chunk = [&](uint64_t q) __attribute__((always_inline)) {
         uint32_t s[BPT][4], x[BPT][4];
+        // all four slots' loads first, ahead of the per-slot branches below
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
             // position r = 256q + 64i + lane is block j = nC - r; the slot's
@@ -309,6 +310,10 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
             x[i][1] = v.y;
             x[i][2] = v.z;
             x[i][3] = v.w;
+        }
+#pragma unroll
+        for (int i = 0; i < BPT; i++) {
+            const uint64_t top = nC - 256 * q - 64u * uint32_t(i) - 63;
             // rounds 1 and 2 (the counters of the slot are cs .. cs + 63)
             const uint32_t cs = c1 + uint32_t(top);
             const uint32_t v3 = __builtin_bswap32(cs + (63u - lane)) ^ a.rk[3];
