@@ -293,16 +293,20 @@ typedef struct {
  *   in_base/in_bytes, out_base/out_bytes   the buffers messages live in; a
  *                    message that does not fit inside them is rejected.
  *   workspace        256-byte aligned scratch of workspace_bytes, sized by
- *                    aes_batch_workspace_size for (max_msgs, max_total_blocks,
- *                    tile_blocks).  It holds the expanded key schedules, the
- *                    tile table and the counters.
- *   tile_blocks      16-byte blocks per unit of work (a tile never spans two
- *                    messages); 0 = library choice.
+ *                    aes_batch_workspace_size for max_msgs.  It holds the
+ *                    expanded key schedules, the work lists and the split.
+ *   tile_blocks      granularity of the split, 1 .. 1024: a wave's part of a
+ *                    message starts and ends on a multiple of this many
+ *                    16-byte blocks (XTS: of whole data units), or at the
+ *                    message's end; 0 = library choice (512).
  * The sequence is: on-device Key Expansion for every message (FIPS-197
- * section 5.2; the decryption schedule of section 5.3.5 where needed); a plan
- * that cuts messages into tiles (the paper's chunking, Section IV-A, applied
- * per message); then persistent kernels whose waves take tiles off a counter
- * until none is left.  A message with an invalid descriptor (bad key code or
+ * section 5.2; the decryption schedule of section 5.3.5 where needed) and a
+ * plan that puts the messages in three lists (encryption tables, inverse
+ * tables, serial CBC encryption) and splits each parallel list into equal
+ * shares of work, one per wave, by cost (blocks times rounds): the paper's
+ * chunking into one piece per processor, Section IV-A, across messages; then
+ * persistent kernels, one workgroup per compute unit, in which every wave
+ * runs its share.  A message with an invalid descriptor (bad key code or
  * mode, ECB length not a multiple of 16, misaligned offset, outside the
  * buffers, key_idx >= nkeys) is skipped and counted (aes_batch_query).
  */
@@ -319,23 +323,21 @@ typedef struct {
     void *workspace;
     size_t workspace_bytes;
     int max_msgs;
-    uint64_t max_total_blocks;
     int tile_blocks;
 } aes_batch;
 
-/* Workspace bytes for up to max_msgs messages holding up to
- * max_total_blocks 16-byte blocks (partial blocks count as whole) in tiles
- * of tile_blocks blocks (0 = library choice).  Host only. */
-int aes_batch_workspace_size(int max_msgs, uint64_t max_total_blocks, int tile_blocks,
-                             size_t *bytes);
+/* Workspace bytes for batches of up to max_msgs messages (any lengths).
+ * Host only. */
+int aes_batch_workspace_size(int max_msgs, size_t *bytes);
 
 /* Enqueue the whole batch on `stream`.  Errors are found on the host from
  * the aes_batch fields; descriptor contents are checked on the device. */
 int aes_batch_run(const aes_batch *b, void *stream);
 
-/* After the stream has run the batch: tiles processed and messages
- * rejected by the device-side checks.  Synchronous (waits for `stream`). */
-int aes_batch_query(const aes_batch *b, void *stream, uint64_t *tiles, uint64_t *rejected);
+/* After the stream has run the batch: messages planned (accepted into the
+ * lists) and messages rejected by the device-side checks.  Synchronous
+ * (waits for `stream`). */
+int aes_batch_query(const aes_batch *b, void *stream, uint64_t *planned, uint64_t *rejected);
 
 /* The same sequence captured once as a HIP graph for repeated launches on
  * any stream.  Descriptors, keys and (through d_nmsg) the message count may
@@ -423,7 +425,7 @@ int aes_serve_scratch_size(const aes_serve_cfg *cfg, size_t *bytes);
  * completed (their requests' latencies are taken then and their memory
  * returns to the budget); admit arrived requests in arrival order while the
  * budget has room; when a stream is free, launch everything admitted and not
- * yet launched as one batch (payload fill, Key Expansion, tile plan,
+ * yet launched as one batch (payload fill, Key Expansion, the plan,
  * persistent cipher kernels) on it.  Batches on different streams overlap on
  * the device.  results[i] describes reqs[i].  d_scratch (256-byte aligned)
  * holds aes_serve_scratch_size(cfg) bytes; the results stay in its arena at

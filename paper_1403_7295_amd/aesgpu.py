@@ -66,8 +66,7 @@ _SIGNATURES = {
     "aes_set_tuned": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "aes_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                 ctypes.c_void_p]),
-    "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
-                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "aes_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "aes_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_uint64),
@@ -110,8 +109,7 @@ class aes_batch(ctypes.Structure):
                 ("in_base", ctypes.c_void_p), ("in_bytes", ctypes.c_uint64),
                 ("out_base", ctypes.c_void_p), ("out_bytes", ctypes.c_uint64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("max_msgs", ctypes.c_int), ("max_total_blocks", ctypes.c_uint64),
-                ("tile_blocks", ctypes.c_int)]
+                ("max_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int)]
 
 
 # aes_request and aes_request_result, as numpy records
@@ -348,9 +346,9 @@ def decrypt(x, roundkeys, Nr, mode="ecb", ctr0=None, out=None, stream=None):
 
 
 # --- batches ----------------------------------------------------------------
-def aes_batch_workspace_size(max_msgs, max_total_blocks, tile_blocks=0):
+def aes_batch_workspace_size(max_msgs):
     n = ctypes.c_size_t(0)
-    _check(lib.aes_batch_workspace_size(max_msgs, max_total_blocks, tile_blocks, ctypes.byref(n)))
+    _check(lib.aes_batch_workspace_size(max_msgs, ctypes.byref(n)))
     return n.value
 
 
@@ -359,7 +357,7 @@ def aes_batch_run(batch, stream=None):
 
 
 def aes_batch_query(batch, stream=None):
-    """Waits for `stream`; returns (tiles processed, messages rejected)."""
+    """Waits for `stream`; returns (messages planned, messages rejected)."""
     t, r = ctypes.c_uint64(0), ctypes.c_uint64(0)
     _check(lib.aes_batch_query(ctypes.byref(batch), _stream_handle(stream), ctypes.byref(t),
                                ctypes.byref(r)))
@@ -422,20 +420,17 @@ class Batch:
     inp, out   device tensors the descriptors' offsets point into
     """
 
-    def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None,
-                 max_total_blocks=None, device=None):
+    def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None, device=None):
         import torch
         self.device = device or inp.device
         descs = np.ascontiguousarray(descs, dtype=MSG_DESC_DTYPE)
         keys = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
         self.max_msgs = max(1, int(max_msgs or len(descs)))
-        blocks = int(((descs["nbytes"].astype(np.uint64) + 15) // 16).sum()) if len(descs) else 0
-        self.max_total_blocks = int(max_total_blocks if max_total_blocks is not None else blocks)
         self.tile_blocks = int(tile_blocks or TUNED_TILE_BLOCKS)
         self.d_desc = torch.zeros(self.max_msgs * 48, dtype=torch.uint8, device=self.device)
         self.d_nmsg = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.d_keys = torch.from_numpy(keys.reshape(-1).copy()).to(self.device)
-        ws = aes_batch_workspace_size(self.max_msgs, self.max_total_blocks, self.tile_blocks)
+        ws = aes_batch_workspace_size(self.max_msgs)
         self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
@@ -445,7 +440,7 @@ class Batch:
                            in_base=inp.data_ptr(), in_bytes=inp.numel() * inp.element_size(),
                            out_base=out.data_ptr(), out_bytes=out.numel() * out.element_size(),
                            workspace=aligned, workspace_bytes=ws, max_msgs=self.max_msgs,
-                           max_total_blocks=self.max_total_blocks, tile_blocks=self.tile_blocks)
+                           tile_blocks=self.tile_blocks)
         self.graph = None
         self.set_descs(descs)
 

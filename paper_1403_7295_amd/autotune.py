@@ -5,8 +5,9 @@ size bucket it times every candidate launch configuration (table layout,
 blocks per thread -- i.e. blocks per wave step = 64 x blocks_per_thread --,
 workgroup size, or the bitsliced kernel) with HIP events on the current
 stream, keeps the fastest, and installs the result in the library with
-aes_set_tuned.  For batches it times the tile size (blocks per unit of
-work) on a ragged multi-message workload.  Results are saved as JSON keyed
+aes_set_tuned.  For batches it times the split granularity (the block
+multiple on which a wave's share of a message starts and ends) on a ragged
+multi-message workload.  Results are saved as JSON keyed
 by the GPU's architecture and compute-unit count; the binding installs the
 committed table for gfx950 when it is imported.
 
@@ -30,7 +31,7 @@ BITSLICED = dict(layout=2, blocks_per_thread=0, wg_size=0, grid=0)
 OPS = (("ecb_enc", "ecb", 0), ("ecb_dec", "ecb", 1), ("ctr", "ctr", 0))
 # size buckets: the size tuned at, and the smallest size the result applies to
 BUCKETS = ((1 << 16, 0), (1 << 20, 1 << 18), (1 << 24, 1 << 22), (1 << 30, 1 << 27))
-TILE_CANDIDATES = (1024, 2048, 4096, 8192, 16384, 32768)
+TILE_CANDIDATES = (128, 256, 512, 1024)
 
 
 def _time(torch, fn, reps, warm=2):
@@ -85,8 +86,8 @@ def tune_plain(A, torch, nrs=(10, 12, 14), buckets=BUCKETS, verbose=False):
 
 
 def tune_batch(A, torch, nmsg=2000, verbose=False):
-    """Best tile size for the ragged multi-message workload (a 2,000-message
-    slice of it)."""
+    """Best split granularity for the ragged multi-message workload (a
+    2,000-message slice of it)."""
     import seedgen
     lens, keybits, keys, _ = seedgen.ragged_batch(4, nmsg)
     descs = A.make_descs(lens, keybits=keybits, mode="ecb")
@@ -100,7 +101,7 @@ def tune_batch(A, torch, nmsg=2000, verbose=False):
         b.close()
         results.append(dict(tile_blocks=tile, seconds=t, GBps=total / t / 1e9))
         if verbose:
-            print("batch tile %6d: %.1f GB/s" % (tile, total / t / 1e9), flush=True)
+            print("batch split %6d: %.1f GB/s" % (tile, total / t / 1e9), flush=True)
     best = min(results, key=lambda r: r["seconds"])
     return best["tile_blocks"], results
 
@@ -132,11 +133,20 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--nr", type=int, nargs="*", default=[10, 12, 14])
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="re-tune only the batch split of the committed table; write it to --out "
+                         "(default: in place)")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
     from paper_1403_7295_amd import aesgpu as A
     t0 = time.time()
+    if args.batch_only:
+        table = load(DEFAULT_TABLE)
+        table["batch_tile_blocks"], table["batch_measurements"] = tune_batch(A, torch, verbose=True)
+        save(args.out or DEFAULT_TABLE, table)
+        print("batch_tile_blocks", table["batch_tile_blocks"])
+        return
     entries, log = tune_plain(A, torch, tuple(args.nr), verbose=True)
     table = {"device": device_key(torch), "entries": entries, "measurements": log}
     if not args.no_batch:

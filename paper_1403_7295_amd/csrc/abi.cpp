@@ -352,18 +352,16 @@ int gcm_crypt(int decrypt, const void *in, void *out, size_t nbytes, const void 
     return AES_OK;
 }
 
-constexpr int kDefaultTileBlocks = 8192;  // 128 KiB of data per tile
 
-// Tile capacity and workspace bytes for a batch shape; 0 bytes if too big.
-size_t batch_layout(int max_msgs, uint64_t max_total_blocks, int tile_blocks, uint64_t *capacity) {
-    const uint64_t t = uint64_t(tile_blocks);
-    const uint64_t cap = uint64_t(max_msgs) + (max_total_blocks + t - 1) / t;
-    if (capacity)
-        *capacity = cap;
-    if (cap >= (uint64_t(1) << 32))
-        return 0;
-    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(cap) * sizeof(BatchTile);
+
+// Workspace bytes for up to max_msgs messages: header, one key slot and one
+// list entry per message in each of the three lists.
+size_t batch_layout(int max_msgs) {
+    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(max_msgs) * sizeof(BatchItem);
 }
+
+// Cipher-kernel workgroups for a batch launch on this device.
+int batch_grid(const DeviceState &d) { return std::min(d.cus, kBatchMaxWaves / kBatchWavesPerGroup); }
 
 int batch_args(const aes_batch *b, BatchKArgs *a) {
     if (!b)
@@ -372,18 +370,13 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
         return fail(AES_E_NULL, "desc, keys, in_base, out_base and workspace must not be NULL");
     if (b->max_msgs < 1 || b->nmsg < 0 || b->nmsg > b->max_msgs || b->nkeys < 1)
         return fail(AES_E_ARG, "need 1 <= max_msgs, 0 <= nmsg <= max_msgs and nkeys >= 1");
-    if (b->tile_blocks < 0)
-        return fail(AES_E_ARG, "tile_blocks must be >= 0");
+    if (b->tile_blocks < 0 || b->tile_blocks > kMaxSplitBlocks)
+        return fail(AES_E_ARG, "tile_blocks must be 0 .. " + std::to_string(kMaxSplitBlocks));
     if ((reinterpret_cast<uintptr_t>(b->in_base) | reinterpret_cast<uintptr_t>(b->out_base)) & 15u)
         return fail(AES_E_ALIGN, "in_base and out_base must be 16-byte aligned");
     if (reinterpret_cast<uintptr_t>(b->workspace) & 255u)
         return fail(AES_E_ALIGN, "workspace must be 256-byte aligned");
-    const int tile = b->tile_blocks ? b->tile_blocks : kDefaultTileBlocks;
-    uint64_t cap = 0;
-    const size_t need = batch_layout(b->max_msgs, b->max_total_blocks, tile, &cap);
-    if (need == 0)
-        return fail(AES_E_LENGTH, "batch too large for one workspace");
-    if (b->workspace_bytes < need)
+    if (b->workspace_bytes < batch_layout(b->max_msgs))
         return fail(AES_E_LENGTH, "workspace smaller than aes_batch_workspace_size reports");
     char *ws = static_cast<char *>(b->workspace);
     a->desc = b->desc;
@@ -396,11 +389,11 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
     a->in_bytes = b->in_bytes;
     a->out_base = b->out_base;
     a->out_bytes = b->out_bytes;
+    const size_t items = sizeof(BatchHeader) + size_t(b->max_msgs) * kKeySlotWords * 4;
     a->header = reinterpret_cast<BatchHeader *>(ws);
     a->keytab = reinterpret_cast<uint32_t *>(ws + sizeof(BatchHeader));
-    a->tiles = reinterpret_cast<BatchTile *>(ws + sizeof(BatchHeader) + size_t(b->max_msgs) * kKeySlotWords * 4);
-    a->tile_capacity = cap;
-    a->tile_blocks = uint32_t(tile);
+    a->items = reinterpret_cast<BatchItem *>(ws + items);
+    a->split_blocks = uint32_t(b->tile_blocks ? b->tile_blocks : kDefaultSplitBlocks);
     return AES_OK;
 }
 
@@ -409,16 +402,16 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
 // Helpers the request loop (serve.cpp) shares with this file.
 namespace aesgpu {
 int serve_fail(int status, const std::string &msg) { return fail(status, msg); }
-int serve_device(int *cus) {
+int serve_device(int *cus, int *batch_grid_out) {
     int st;
     const DeviceState *d = current_device(&st);
-    if (d)
+    if (d) {
         *cus = d->cus;
+        *batch_grid_out = batch_grid(*d);
+    }
     return st;
 }
-size_t serve_batch_layout(int max_msgs, uint64_t max_total_blocks, int tile_blocks, uint64_t *cap) {
-    return batch_layout(max_msgs, max_total_blocks, tile_blocks, cap);
-}
+size_t serve_batch_layout(int max_msgs) { return batch_layout(max_msgs); }
 int serve_batch_args(const aes_batch *b, BatchKArgs *a) { return batch_args(b, a); }
 }  // namespace aesgpu
 
@@ -542,16 +535,12 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream) {
     return AES_OK;
 }
 
-int aes_batch_workspace_size(int max_msgs, uint64_t max_total_blocks, int tile_blocks, size_t *bytes) {
+int aes_batch_workspace_size(int max_msgs, size_t *bytes) {
     if (!bytes)
         return fail(AES_E_NULL, "bytes must not be NULL");
-    if (max_msgs < 1 || tile_blocks < 0)
-        return fail(AES_E_ARG, "need max_msgs >= 1 and tile_blocks >= 0");
-    const size_t n = batch_layout(max_msgs, max_total_blocks, tile_blocks ? tile_blocks : kDefaultTileBlocks,
-                                  nullptr);
-    if (n == 0)
-        return fail(AES_E_LENGTH, "batch too large for one workspace");
-    *bytes = n;
+    if (max_msgs < 1)
+        return fail(AES_E_ARG, "need max_msgs >= 1");
+    *bytes = batch_layout(max_msgs);
     return AES_OK;
 }
 
@@ -563,13 +552,13 @@ int aes_batch_run(const aes_batch *b, void *stream) {
     const DeviceState *d = current_device(&st);
     if (!d)
         return st;
-    hipError_t e = launch_batch(a, d->cus, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     return AES_OK;
 }
 
-int aes_batch_query(const aes_batch *b, void *stream, uint64_t *tiles, uint64_t *rejected) {
+int aes_batch_query(const aes_batch *b, void *stream, uint64_t *planned, uint64_t *rejected) {
     BatchKArgs a;
     int st = batch_args(b, &a);
     if (st != AES_OK)
@@ -580,13 +569,10 @@ int aes_batch_query(const aes_batch *b, void *stream, uint64_t *tiles, uint64_t 
         e = hipMemcpy(&h, a.header, sizeof(h), hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch query: ") + hipGetErrorString(e));
-    if (tiles)
-        *tiles = uint64_t(h.ntiles[0]) + h.ntiles[1] + h.ntiles[2];
+    if (planned)
+        *planned = uint64_t(h.ntiles[0]) + h.ntiles[1] + h.ntiles[2];
     if (rejected)
         *rejected = h.rejected;
-    if (h.overflow)
-        return fail(AES_E_LENGTH, "the batch's tiles did not fit the workspace; nothing was processed for "
-                                  "the list that overflowed");
     return AES_OK;
 }
 
@@ -607,7 +593,7 @@ int aes_batch_graph_create(const aes_batch *b, void **graph) {
     if (e == hipSuccess)
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_batch(a, d->cus, s);
+        hipError_t le = launch_batch(a, batch_grid(*d), s);
         e = hipStreamEndCapture(s, &g);
         if (le != hipSuccess)
             e = le;

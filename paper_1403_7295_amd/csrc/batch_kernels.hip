@@ -1,19 +1,19 @@
 // Batches of independent messages (each with its own key, length, mode and
 // direction) in one launch sequence:
 //
-//   keyexp_kernel   one lane per message: Key Expansion on the device
-//                   (FIPS-197 section 5.2), plus the equivalent-inverse
+//   prep_kernel     workgroup 0 plans: it checks every descriptor, cuts
+//                   each message into tiles of at most T blocks (a tile never
+//                   spans two messages; an XTS tile is whole groups of 64
+//                   data units), and lays the tiles out in three lists:
+//                   forward (ECB encryption, CTR, XTS encryption: the
+//                   encryption tables), inverse (ECB, CBC and XTS decryption:
+//                   the inverse ones) and serial (CBC encryption, one message
+//                   per tile).  It also zeroes the tile counters, so the
+//                   sequence can be replayed from a graph without any memset.
+//                   The other workgroups run Key Expansion (FIPS-197 section
+//                   5.2), one lane per message, plus the equivalent-inverse
 //                   schedule (section 5.3.5) for decryption and the tweak
 //                   key's schedule for XTS.
-//   plan_kernel     one workgroup: checks every descriptor, cuts each message
-//                   into tiles of at most T blocks (a tile never spans two
-//                   messages; an XTS tile is whole groups of 64 data units),
-//                   and lays the tiles out in three lists: forward (ECB
-//                   encryption, CTR, XTS encryption: the encryption tables),
-//                   inverse (ECB, CBC and XTS decryption: the inverse ones)
-//                   and serial (CBC encryption, one message per tile).
-//                   It also zeroes the two tile counters, so the sequence can
-//                   be replayed from a graph without any memset.
 //   batch_kernel    persistent, one per list: every wave takes the next tile
 //                   off its list's counter, reads that message's round keys
 //                   into scalar registers and runs the same block loop as the
@@ -32,7 +32,10 @@
 namespace aesgpu {
 namespace {
 
-constexpr int kPlanThreads = 1024;
+// Workgroup size of the prep kernel: four waves, so that its workgroups fit
+// beside a cipher kernel's 16 waves on a compute unit (the request loop runs
+// several batches at once).
+constexpr int kPlanThreads = 256;
 
 __device__ __forceinline__ int desc_nr(const aes_msg_desc &d) { return 10 + 2 * int(d.keybits_code); }
 
@@ -91,13 +94,21 @@ __device__ __forceinline__ int desc_class(const aes_msg_desc &d) {
     return ((d.mode == AES_MODE_ECB || d.mode == AES_MODE_XTS) && d.decrypt) ? 1 : 0;
 }
 
-// Blocks per XTS tile: whole groups of 64 data units (the unit of the tweak
-// work), as many as fit in the tile size, at least one.
-__device__ __forceinline__ uint64_t xts_tile_blocks(const aes_msg_desc &d, uint32_t tile_blocks) {
-    const uint64_t group = uint64_t(64) << xts_unit_shift(d);
-    const uint64_t g = tile_blocks / group;
-    return (g ? g : 1) * group;
+// Where a wave's share of a message may start or end: multiples of
+// split_blocks blocks; for XTS, of whole data units (the tweak work starts
+// at a unit), as many units as fit in split_blocks, at least one.
+__device__ __forceinline__ uint64_t split_step(const aes_msg_desc &d, uint32_t split_blocks) {
+    if (d.mode != AES_MODE_XTS)
+        return split_blocks;
+    const uint32_t ushift = xts_unit_shift(d);
+    const uint64_t units = split_blocks >> ushift;
+    return (units ? units : 1) << ushift;
 }
+
+// Work of one block in cost units, for splitting a list evenly: the rounds
+// (their table lookups dominate) plus a share for loads, stores and the
+// initial key addition.
+__device__ __forceinline__ uint64_t block_cost(const aes_msg_desc &d) { return uint64_t(desc_nr(d)) + 2; }
 
 __device__ __forceinline__ uint32_t batch_count(const BatchKArgs &a) {
     int n = a.d_nmsg ? *a.d_nmsg : a.nmsg;
@@ -108,298 +119,466 @@ __device__ __forceinline__ uint32_t batch_count(const BatchKArgs &a) {
     return uint32_t(n);
 }
 
-__device__ __forceinline__ uint32_t sbox(uint32_t x) { return (g_base[x & 255u] >> 8) & 255u; }
+// The S-box and the inverse round table, read from a copy of the base tables
+// in LDS: tab[0 .. 255] is the encryption round table for row 0, whose byte
+// 1 is S[x]; tab[256 .. 511] the decryption one.
+__device__ __forceinline__ uint32_t sbox(const uint32_t *tab, uint32_t x) { return (tab[x & 255u] >> 8) & 255u; }
 
-__device__ __forceinline__ uint32_t sub_word(uint32_t w) {
-    return sbox(w) | (sbox(w >> 8) << 8) | (sbox(w >> 16) << 16) | (sbox(w >> 24) << 24);
+__device__ __forceinline__ uint32_t sub_word(const uint32_t *tab, uint32_t w) {
+    return sbox(tab, w) | (sbox(tab, w >> 8) << 8) | (sbox(tab, w >> 16) << 16) | (sbox(tab, w >> 24) << 24);
 }
 
 // InvMixColumns of a column word, through the inverse round table:
 // td0[S[b]] is InvMixColumns of the column (b, 0, 0, 0).
-__device__ __forceinline__ uint32_t inv_mix_column(uint32_t w) {
-    return g_base[256 + sbox(w)] ^ rotl(g_base[256 + sbox(w >> 8)], 8) ^
-           rotl(g_base[256 + sbox(w >> 16)], 16) ^ rotl(g_base[256 + sbox(w >> 24)], 24);
+__device__ __forceinline__ uint32_t inv_mix_column(const uint32_t *tab, uint32_t w) {
+    return tab[256 + sbox(tab, w)] ^ rotl(tab[256 + sbox(tab, w >> 8)], 8) ^
+           rotl(tab[256 + sbox(tab, w >> 16)], 16) ^ rotl(tab[256 + sbox(tab, w >> 24)], 24);
 }
 
-// Key Expansion (FIPS-197 section 5.2) of the key at `key` into w[0 .. 4Nr+3].
-__device__ void expand_key_words(const uint8_t *key, int nk, int nr, uint32_t *w) {
-    uint32_t prev = 0;
-    for (int i = 0; i < nk; i++) {
-        prev = uint32_t(key[4 * i]) | (uint32_t(key[4 * i + 1]) << 8) | (uint32_t(key[4 * i + 2]) << 16) |
-               (uint32_t(key[4 * i + 3]) << 24);
-        w[i] = prev;
+// Key Expansion (FIPS-197 section 5.2) of the Nk-word key at `key`, fully
+// unrolled: each word w[i], i = 0 .. 4Nr+3, is handed to emit(i, w[i]) as
+// soon as it exists, so only the last Nk words stay live in registers.
+template <int NK, typename Emit>
+__device__ __forceinline__ void expand_key(const uint8_t *key, const uint32_t *tab, Emit emit) {
+    uint32_t w[4 * (NK + 7)];
+#pragma unroll
+    for (int i = 0; i < NK; i++) {
+        w[i] = le32(key + 4 * i);
+        emit(i, w[i]);
     }
     uint32_t rcon = 1;
-    for (int i = nk; i < 4 * (nr + 1); i++) {
-        uint32_t t = prev;
-        if (i % nk == 0) {
-            t = sub_word(rotl(t, 24)) ^ rcon;  // RotWord is a right rotation of a little-endian word
+#pragma unroll
+    for (int i = NK; i < 4 * (NK + 7); i++) {
+        uint32_t t = w[i - 1];
+        if (i % NK == 0) {
+            t = sub_word(tab, rotl(t, 24)) ^ rcon;  // RotWord is a right rotation of a little-endian word
             rcon = ((rcon << 1) ^ ((rcon & 0x80u) ? 0x1bu : 0u)) & 0xffu;
-        } else if (nk > 6 && i % nk == 4) {
-            t = sub_word(t);
+        } else if (NK > 6 && i % NK == 4) {
+            t = sub_word(tab, t);
         }
-        prev = w[i - nk] ^ t;
-        w[i] = prev;
+        w[i] = w[i - NK] ^ t;
+        emit(i, w[i]);
     }
 }
 
-__global__ __launch_bounds__(256) void keyexp_kernel(const BatchKArgs a) {
-    const uint32_t n = batch_count(a);
-    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n)
-        return;
-    const aes_msg_desc d = a.desc[m];
-    if (!desc_valid(d, a))
-        return;
-    const int nk = 4 + 2 * int(d.keybits_code), nr = nk + 6;
-    uint32_t *w = a.keytab + size_t(m) * kKeySlotWords;
-    expand_key_words(a.keys + size_t(d.key_idx) * 32, nk, nr, w);
-    if (desc_class(d) == 1) {
-        uint32_t *dk = w + kKeySlotWords / 2;
-        for (int c = 0; c < 4; c++) {
-            dk[c] = w[4 * nr + c];
-            dk[4 * nr + c] = w[c];
+// One message's key slot: the encryption schedule at 0; for the inverse
+// list the equivalent-inverse schedule (section 5.3.5) at kKeySlotWords / 2,
+// whose round r is InvMixColumns of encryption round Nr - r (rounds 0 and Nr
+// swapped, unmixed); for XTS the tweak key's encryption schedule in the half
+// the data key's direction leaves free.
+template <int NK>
+__device__ __forceinline__ void expand_message_keys(const BatchKArgs &a, const aes_msg_desc &d, uint32_t *slot,
+                                                    const uint32_t *tab) {
+    constexpr int NR = NK + 6;
+    const bool inverse = desc_class(d) == 1;
+    uint32_t *dk = slot + kKeySlotWords / 2;
+    expand_key<NK>(a.keys + size_t(d.key_idx) * 32, tab, [&](int i, uint32_t v) {
+        slot[i] = v;
+        if (inverse) {
+            if (i < 4)
+                dk[4 * NR + i] = v;
+            else if (i >= 4 * NR)
+                dk[i - 4 * NR] = v;
+            else
+                dk[4 * (NR - i / 4) + (i & 3)] = inv_mix_column(tab, v);
         }
-        for (int r = 1; r < nr; r++)
-            for (int c = 0; c < 4; c++)
-                dk[4 * r + c] = inv_mix_column(w[4 * (nr - r) + c]);
+    });
+    if (d.mode == AES_MODE_XTS) {
+        uint32_t *o = slot + (d.decrypt ? 0 : kKeySlotWords / 2);
+        expand_key<NK>(a.keys + size_t(xts_key2(d)) * 32, tab, [&](int i, uint32_t v) { o[i] = v; });
     }
-    // XTS: the tweak key's encryption schedule in the half of the slot the
-    // data key's direction leaves free
-    if (d.mode == AES_MODE_XTS)
-        expand_key_words(a.keys + size_t(xts_key2(d)) * 32, nk, nr, w + (d.decrypt ? 0 : kKeySlotWords / 2));
 }
 
-__device__ __forceinline__ uint64_t tiles_of(const aes_msg_desc &d, uint32_t tile_blocks) {
-    const uint64_t nblk = (d.nbytes + 15) >> 4;
-    if (desc_class(d) == 2)
-        return nblk ? 1 : 0;
-    const uint64_t step = d.mode == AES_MODE_XTS ? xts_tile_blocks(d, tile_blocks) : tile_blocks;
-    return (nblk + step - 1) / step;
+// Exclusive prefix sums over the workgroup's kPlanThreads threads of N
+// counters at once: scans within each wave by lane shifts, then the wave
+// totals through LDS.  total[] gets the workgroup sums.
+template <int N>
+__device__ __forceinline__ void block_exclusive_scan(uint64_t (&v)[N], uint64_t (*wsum)[kPlanThreads / 64],
+                                                     uint64_t (&total)[N]) {
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    uint64_t x[N];
+#pragma unroll
+    for (int k = 0; k < N; k++)
+        x[k] = v[k];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            const uint64_t y = __shfl_up(x[k], d, 64);
+            if (lane >= uint32_t(d))
+                x[k] += y;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < N; k++)
+            wsum[k][wave] = x[k];
+    }
+    __syncthreads();
+    // lane l of every group of NW lanes reads wave l's total; butterfly sums
+    // give the total of the waves before this one and of all of them
+    constexpr int NW = kPlanThreads / 64;
+    static_assert(NW >= 1 && NW <= 64 && (NW & (NW - 1)) == 0, "a power-of-two number of waves");
+    const uint32_t lw = lane & uint32_t(NW - 1);
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const uint64_t s = wsum[k][lw];
+        uint64_t before = lw < wave ? s : 0, sum = s;
+#pragma unroll
+        for (int o = 1; o < NW; o <<= 1) {
+            before += __shfl_xor(before, o, NW);
+            sum += __shfl_xor(sum, o, NW);
+        }
+        v[k] = before + x[k] - v[k];
+        total[k] = sum;
+    }
 }
 
-__global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) {
-    __shared__ uint64_t cnt[3][kPlanThreads];
-    __shared__ uint64_t base[3];
-    __shared__ uint32_t bad[kPlanThreads];
+constexpr int kPlanCounters = 6;   // items in lists 0, 1, 2; cost of lists 0, 1; rejected
+
+// floor(a b / c) without overflow (messages may overlap, so a list's cost is
+// not bounded by the memory size).
+__device__ __forceinline__ uint64_t mul_div_floor(uint64_t a, uint64_t b, uint64_t c) {
+    return uint64_t((unsigned __int128)a * b / c);
+}
+
+// The plan (one workgroup).  Every thread takes a contiguous range of
+// messages; a scan gives each thread its place in the three lists and, for
+// the forward and inverse lists, the cost units before its messages (each
+// item's start), from which every wave finds its shares.
+__device__ __forceinline__ void plan_lists(const BatchKArgs &a, uint64_t (*wsum)[kPlanThreads / 64]) {
     const uint32_t n = batch_count(a);
     const uint32_t tid = threadIdx.x;
     const uint32_t per = (n + kPlanThreads - 1) / kPlanThreads;
     const uint32_t m0 = min(n, tid * per), m1 = min(n, m0 + per);
-    uint64_t c[3] = {0, 0, 0};
-    uint32_t rejected = 0;
+    uint64_t c[kPlanCounters] = {0, 0, 0, 0, 0, 0};
     for (uint32_t m = m0; m < m1; m++) {
         const aes_msg_desc d = a.desc[m];
         if (!desc_valid(d, a)) {
-            rejected++;
+            c[5]++;
             continue;
         }
-        c[desc_class(d)] += tiles_of(d, a.tile_blocks);
+        // (selects, not indexed stores: keeps c[] in registers)
+        const int k = desc_class(d);
+        const uint64_t cost = ((d.nbytes + 15) >> 4) * block_cost(d);
+        c[0] += k == 0 ? 1 : 0;
+        c[1] += k == 1 ? 1 : 0;
+        c[2] += k == 2 ? 1 : 0;
+        c[3] += k == 0 ? cost : 0;
+        c[4] += k == 1 ? cost : 0;
     }
-    cnt[0][tid] = c[0];
-    cnt[1][tid] = c[1];
-    cnt[2][tid] = c[2];
-    bad[tid] = rejected;
-    __syncthreads();
-    if (tid < 3) {
-        // exclusive scan of one class's per-thread counts (1024 adds)
-        uint64_t run = 0;
-        for (int t = 0; t < kPlanThreads; t++) {
-            const uint64_t v = cnt[tid][t];
-            cnt[tid][t] = run;
-            run += v;
-        }
-        base[tid] = run;
-    }
-    __syncthreads();
-    bool fits[3];
-    for (int k = 0; k < 3; k++)
-        fits[k] = base[k] <= a.tile_capacity;
-    uint64_t off[3] = {cnt[0][tid], cnt[1][tid], cnt[2][tid]};
+    uint64_t total[kPlanCounters];
+    block_exclusive_scan<kPlanCounters>(c, wsum, total);
     for (uint32_t m = m0; m < m1; m++) {
         const aes_msg_desc d = a.desc[m];
         if (!desc_valid(d, a))
             continue;
         const int k = desc_class(d);
-        if (!fits[k])
-            continue;
         const uint64_t nblk = (d.nbytes + 15) >> 4;
-        BatchTile *list = a.tiles + size_t(k) * a.tile_capacity;
-        // a serial message is one tile; XTS tiles are whole groups of units
-        const uint64_t step = k == 2 ? nblk : d.mode == AES_MODE_XTS ? xts_tile_blocks(d, a.tile_blocks)
-                                                                     : uint64_t(a.tile_blocks);
-        for (uint64_t first = 0; first < nblk; first += step) {
-            BatchTile t;
-            t.msg = m;
-            t.count = uint32_t(min<uint64_t>(step, nblk - first));
-            t.first = first;
-            list[off[k]++] = t;
-        }
+        const uint64_t i = k == 0 ? c[0] : k == 1 ? c[1] : c[2];
+        BatchItem it;
+        it.msg = m;
+        it.count = k == 2 ? uint32_t(nblk) : 0u;   // desc_valid keeps a serial message below 2^32 blocks
+        it.start = k == 0 ? c[3] : k == 1 ? c[4] : 0;
+        a.items[size_t(k) * a.max_msgs + i] = it;
+        const uint64_t cost = nblk * block_cost(d);
+        c[3] += k == 0 ? cost : 0;
+        c[4] += k == 1 ? cost : 0;
+        c[0] += k == 0 ? 1 : 0;
+        c[1] += k == 1 ? 1 : 0;
+        c[2] += k == 2 ? 1 : 0;
     }
     if (tid == 0) {
-        uint32_t r = 0;
-        for (int t = 0; t < kPlanThreads; t++)
-            r += bad[t];
         BatchHeader *h = a.header;
         for (int k = 0; k < 3; k++) {
-            h->ntiles[k] = fits[k] ? uint32_t(base[k]) : 0u;
+            h->ntiles[k] = uint32_t(total[k]);
             h->next[k] = 0;
         }
-        h->rejected = r;
-        h->overflow = (fits[0] && fits[1] && fits[2]) ? 0u : 1u;
+        h->cost[0] = total[3];
+        h->cost[1] = total[4];
+        h->rejected = uint32_t(total[5]);
     }
 }
 
+// The launch before the cipher kernels: workgroup 0 plans the lists, every
+// other workgroup expands the keys of kPlanThreads messages, one per lane.
+__global__ __launch_bounds__(kPlanThreads) void prep_kernel(const BatchKArgs a) {
+    __shared__ uint32_t tab[512];
+    __shared__ uint64_t wsum[kPlanCounters][kPlanThreads / 64];
+    if (blockIdx.x == 0) {
+        plan_lists(a, wsum);
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < 512; i += kPlanThreads)
+        tab[i] = g_base[i];
+    __syncthreads();
+    const uint32_t n = batch_count(a);
+    const uint32_t m = (blockIdx.x - 1) * kPlanThreads + threadIdx.x;
+    if (m >= n)
+        return;
+    const aes_msg_desc d = a.desc[m];
+    if (!desc_valid(d, a))
+        return;
+    uint32_t *slot = a.keytab + size_t(m) * kKeySlotWords;
+    if (d.keybits_code == 0)
+        expand_message_keys<4>(a, d, slot, tab);
+    else if (d.keybits_code == 1)
+        expand_message_keys<6>(a, d, slot, tab);
+    else
+        expand_message_keys<8>(a, d, slot, tab);
+}
+
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    return uint64_t(uniform32(uint32_t(x))) | (uint64_t(uniform32(uint32_t(x >> 32))) << 32);
+}
+
+// Blocks [first, end) of message `msg` through the buffer kernels' block loop.
 template <int NR, int MODE, int DIR, int BPT>
-__device__ __forceinline__ void run_tile(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
-                                         const aes_msg_desc &d, const BatchTile &t) {
+__device__ __forceinline__ void run_range(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
+                                          const aes_msg_desc &d, uint32_t msg, uint64_t first, uint64_t end) {
     // The round keys are the same for the whole wave: read them once per
-    // tile and keep them in scalar registers.  (The compiler cannot use
+    // range and keep them in scalar registers.  (The compiler cannot use
     // scalar loads itself here: the kernel also stores to memory that it
     // cannot prove distinct from the key table.)
-    const uint32_t *rkp = a.keytab + size_t(t.msg) * kKeySlotWords + (DIR == DIR_DEC ? kKeySlotWords / 2 : 0);
+    const uint32_t *rkp = a.keytab + size_t(msg) * kKeySlotWords + (DIR == DIR_DEC ? kKeySlotWords / 2 : 0);
     uint32_t rk[4 * (NR + 1)];
 #pragma unroll
     for (int i = 0; i < 4 * (NR + 1); i++)
-        rk[i] = __builtin_amdgcn_readfirstlane(rkp[i]);
+        rk[i] = uniform32(rkp[i]);
     uint32_t ctr[4] = {0, 0, 0, 0};
     if (MODE == MODE_CBC) {
         for (int i = 0; i < 4; i++)
-            ctr[i] = uint32_t(d.ctr0[4 * i]) | (uint32_t(d.ctr0[4 * i + 1]) << 8) |
-                     (uint32_t(d.ctr0[4 * i + 2]) << 16) | (uint32_t(d.ctr0[4 * i + 3]) << 24);
+            ctr[i] = le32(d.ctr0 + 4 * i);
     }
     if (MODE == MODE_CTR) {
         for (int i = 0; i < 3; i++)
-            ctr[i] = uint32_t(d.ctr0[4 * i]) | (uint32_t(d.ctr0[4 * i + 1]) << 8) |
-                     (uint32_t(d.ctr0[4 * i + 2]) << 16) | (uint32_t(d.ctr0[4 * i + 3]) << 24);
+            ctr[i] = le32(d.ctr0 + 4 * i);
         ctr[3] = (uint32_t(d.ctr0[12]) << 24) | (uint32_t(d.ctr0[13]) << 16) | (uint32_t(d.ctr0[14]) << 8) |
                  uint32_t(d.ctr0[15]);
     }
     const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
     uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
-    process_blocks<NR, MODE, DIR, LAYOUT_T4X32, BPT>(lds, lc, rk, ctr, in, out, d.nbytes, t.first,
-                                                     t.first + t.count, 64u * BPT);
+    process_blocks<NR, MODE, DIR, LAYOUT_T4X32, BPT>(lds, lc, rk, ctr, in, out, d.nbytes, first, end, 64u * BPT);
 }
 
-// An XTS tile: whole groups of 64 data units starting at a unit boundary.
+// Blocks [first, end) of an XTS message, first at a unit boundary (the split
+// keeps both ends on unit multiples, or end at the message's end): groups of
+// up to 64 data units, one tweak per lane.
 template <int NR, int DIR, int BPT>
-__device__ __forceinline__ void run_xts_tile(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
-                                             const aes_msg_desc &d, const BatchTile &t) {
-    const uint32_t *slot = a.keytab + size_t(t.msg) * kKeySlotWords;
+__device__ __forceinline__ void run_xts_range(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
+                                              const aes_msg_desc &d, uint32_t msg, uint64_t first, uint64_t end) {
+    const uint32_t *slot = a.keytab + size_t(msg) * kKeySlotWords;
     const uint32_t *rkp = slot + (DIR == DIR_DEC ? kKeySlotWords / 2 : 0);
     uint32_t rk[4 * (NR + 1)];
 #pragma unroll
     for (int i = 0; i < 4 * (NR + 1); i++)
-        rk[i] = __builtin_amdgcn_readfirstlane(rkp[i]);
+        rk[i] = uniform32(rkp[i]);
     const uint32_t *rk2 = slot + (DIR == DIR_DEC ? 0 : kKeySlotWords / 2);   // read once per group
     const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
     uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
     const uint32_t ushift = xts_unit_shift(d);
-    const uint64_t group = uint64_t(64) << ushift, end = t.first + t.count;
+    const uint64_t group = uint64_t(64) << ushift;
     const uint64_t first_unit = xts_first_unit(d);
-    for (uint64_t gb0 = t.first; gb0 < end; gb0 += group)
+    for (uint64_t gb0 = first; gb0 < end; gb0 += group)
         xts_group<NR, DIR, BPT>(lds, lc, rk, rk2, in, out, gb0, min(end, gb0 + group),
                                 first_unit + (gb0 >> ushift), ushift);
 }
 
-// The serial list (CBC encryption): every wave takes 64 messages at a time,
-// one per lane, and each lane encrypts its message block after block with its
-// own round keys.  These run first, so the long serial chains start early and
-// the parallel tiles fill in around them.
-__device__ __forceinline__ void run_serial_tiles(const uint32_t *lds, const BatchKArgs &a) {
+// The serial list (CBC encryption): one message per lane, each lane
+// encrypting its message block after block with its own round keys.  Wave w
+// takes messages 64w .. 64w+63 first; only when there are more than 64 per
+// wave are the rest handed out 64 at a time from a counter.  These run
+// before the wave's parallel share, so the long serial chains start early.
+__device__ __forceinline__ void run_serial(const uint32_t *lds, const BatchKArgs &a, uint32_t n, uint32_t wave,
+                                           uint32_t nwaves) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t n = a.header->ntiles[2];
-    const BatchTile *list = a.tiles + size_t(2) * a.tile_capacity;
+    const BatchItem *list = a.items + size_t(2) * a.max_msgs;
     const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
-    for (;;) {
-        uint32_t t0 = 0;
-        if (lane == 0)
-            t0 = atomicAdd(&a.header->next[2], 64u);
-        t0 = __builtin_amdgcn_readfirstlane(t0);
-        if (t0 >= n)
+    const uint64_t statics = uint64_t(nwaves) * 64u;
+    uint64_t t0 = uint64_t(wave) * 64u;
+    while (t0 < n) {
+        const uint64_t t = t0 + lane;
+        if (t < n) {
+            const BatchItem item = list[t];
+            const aes_msg_desc d = a.desc[item.msg];
+            const uint32_t *rkp = a.keytab + size_t(item.msg) * kKeySlotWords;
+            uint32_t iv[4];
+            for (int i = 0; i < 4; i++)
+                iv[i] = le32(d.ctr0 + 4 * i);
+            const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
+            uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
+            const int nr = desc_nr(d);
+            uint32_t rk[60];
+            if (nr == 10) {
+#pragma unroll
+                for (int i = 0; i < 44; i++)
+                    rk[i] = rkp[i];
+                cbc_encrypt_serial<10, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, item.count);
+            } else if (nr == 12) {
+#pragma unroll
+                for (int i = 0; i < 52; i++)
+                    rk[i] = rkp[i];
+                cbc_encrypt_serial<12, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, item.count);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 60; i++)
+                    rk[i] = rkp[i];
+                cbc_encrypt_serial<14, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, item.count);
+            }
+        }
+        if (n <= statics)
             break;
-        const uint32_t t = t0 + lane;
-        if (t >= n)
-            continue;
-        const BatchTile tile = list[t];
-        const aes_msg_desc d = a.desc[tile.msg];
-        const uint32_t *rkp = a.keytab + size_t(tile.msg) * kKeySlotWords;
-        uint32_t iv[4];
-        for (int i = 0; i < 4; i++)
-            iv[i] = uint32_t(d.ctr0[4 * i]) | (uint32_t(d.ctr0[4 * i + 1]) << 8) |
-                    (uint32_t(d.ctr0[4 * i + 2]) << 16) | (uint32_t(d.ctr0[4 * i + 3]) << 24);
-        const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
-        uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
-        const int nr = desc_nr(d);
-        uint32_t rk[60];
-        if (nr == 10) {
-#pragma unroll
-            for (int i = 0; i < 44; i++)
-                rk[i] = rkp[i];
-            cbc_encrypt_serial<10, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, tile.count);
-        } else if (nr == 12) {
-#pragma unroll
-            for (int i = 0; i < 52; i++)
-                rk[i] = rkp[i];
-            cbc_encrypt_serial<12, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, tile.count);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 60; i++)
-                rk[i] = rkp[i];
-            cbc_encrypt_serial<14, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, tile.count);
+        uint64_t c = 0;
+        if (lane == 0)
+            c = atomicAdd(reinterpret_cast<unsigned long long *>(&a.header->next[2]), 64ull);
+        t0 = statics + uniform64(c);
+    }
+}
+
+// Block index of message item `start` (its first cost unit) at which a share
+// boundary x falls: the blocks whose cost units begin before x, rounded up to
+// the split step, within [0, nblk].  Both neighbours of a boundary evaluate
+// it the same way, so the shares partition every message exactly.
+__device__ __forceinline__ uint64_t split_point(uint64_t x, uint64_t start, uint64_t unit, uint64_t step,
+                                                uint64_t nblk) {
+    if (x <= start)
+        return 0;
+    uint64_t b = (x - start + unit - 1) / unit;
+    b = (b + step - 1) / step * step;
+    return b < nblk ? b : nblk;
+}
+
+// The item holding cost unit x: the last item whose start is <= x (items
+// are in order of start; the first starts at 0).  A 64-way search: each step
+// every lane tests one of 64 evenly spaced items and the ballot narrows the
+// range to the gap between two of them.
+__device__ __forceinline__ uint32_t find_item(const BatchItem *list, uint32_t n, uint64_t x) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t span = hi - lo;
+        const uint32_t p = lo + uint32_t((uint64_t(lane) * span) >> 6);
+        // the starts do not decrease, so the lanes that pass are 0 .. L
+        const uint64_t pass = __ballot(list[p].start <= x);
+        const int L = 63 - __builtin_clzll(pass);
+        const uint32_t nlo = uint32_t(__builtin_amdgcn_readlane(int(p), L));
+        hi = L == 63 ? hi : uint32_t(__builtin_amdgcn_readlane(int(p), L + 1));
+        lo = nlo;
+    }
+    return lo;
+}
+
+// Cost units per share, roughly: a list larger than one share per wave is
+// cut into rounds of nwaves shares, wave w taking share w of every round, so
+// that at any time all waves work in the same region (a few hundred MiB)
+// instead of each streaming through its own part of the whole batch.
+constexpr uint64_t kShareCost = 4096 * 16;
+// A list of at least this many rounds (some milliseconds of work) hands out
+// the shares of its second half of rounds from a counter instead: over a
+// long kernel the waves drift apart in speed, and the waves that are ahead
+// take the rest.  Shorter lists are split statically only, without atomics.
+constexpr uint64_t kDynamicMinRounds = 8;
+
+// Share s of S over a list of total cost C: the cost units
+// [s C / S, (s+1) C / S), from the item holding its start through the one
+// holding its end.
+template <int CLASS, int BPT>
+__device__ __forceinline__ void run_share(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
+                                          const BatchItem *list, uint32_t n, uint64_t C, uint64_t s, uint64_t S) {
+    const uint64_t lo = mul_div_floor(s, C, S), hi = mul_div_floor(s + 1, C, S);
+    if (lo < hi) {
+        for (uint32_t i = uniform32(find_item(list, n, lo)); i < n; i++) {
+            const uint64_t start = uniform64(list[i].start);
+            if (start >= hi)
+                break;
+            const uint32_t msg = uniform32(list[i].msg);
+            const aes_msg_desc d = a.desc[msg];
+            const uint64_t nblk = (d.nbytes + 15) >> 4, unit = block_cost(d), step = split_step(d, a.split_blocks);
+            const uint64_t first = uniform64(split_point(lo, start, unit, step, nblk));
+            const uint64_t end = uniform64(split_point(hi, start, unit, step, nblk));
+            if (first >= end)
+                continue;
+            const int nr = desc_nr(d);
+            if (d.mode == AES_MODE_XTS) {
+                constexpr int XDIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
+                if (nr == 10) run_xts_range<10, XDIR, BPT>(lds, lc, a, d, msg, first, end);
+                else if (nr == 12) run_xts_range<12, XDIR, BPT>(lds, lc, a, d, msg, first, end);
+                else run_xts_range<14, XDIR, BPT>(lds, lc, a, d, msg, first, end);
+            } else if (CLASS == 1 && d.mode == AES_MODE_CBC) {
+                if (nr == 10) run_range<10, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
+                else if (nr == 12) run_range<12, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
+                else run_range<14, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
+            } else if (CLASS == 1) {
+                if (nr == 10) run_range<10, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
+                else if (nr == 12) run_range<12, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
+                else run_range<14, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
+            } else if (d.mode == AES_MODE_ECB) {
+                if (nr == 10) run_range<10, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, msg, first, end);
+                else if (nr == 12) run_range<12, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, msg, first, end);
+                else run_range<14, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, msg, first, end);
+            } else {
+                if (nr == 10) run_range<10, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, msg, first, end);
+                else if (nr == 12) run_range<12, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, msg, first, end);
+                else run_range<14, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, msg, first, end);
+            }
         }
     }
 }
 
+// A wave's part of the forward (CLASS 0) or inverse (CLASS 1) list: share w
+// of every static round, then (long lists only) shares of the remaining
+// rounds taken off the list's counter until none is left.
 template <int CLASS, int BPT>
-__global__ __launch_bounds__(1024) void batch_kernel(const BatchKArgs a) {
+__device__ __forceinline__ void run_shares(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
+                                           uint32_t n, uint32_t wave, uint32_t nwaves) {
+    const uint64_t C = a.header->cost[CLASS];
+    if (C == 0)
+        return;
+    const uint64_t per_round = uint64_t(nwaves) * kShareCost;
+    const uint64_t rounds = max<uint64_t>(1, (C + per_round - 1) / per_round);
+    const uint64_t dynamic = rounds >= kDynamicMinRounds ? rounds / 2 : 0;
+    const uint64_t S = rounds * nwaves, S_static = (rounds - dynamic) * nwaves;
+    const BatchItem *list = a.items + size_t(CLASS) * a.max_msgs;
+    for (uint64_t s = wave; s < S_static; s += nwaves)
+        run_share<CLASS, BPT>(lds, lc, a, list, n, C, s, S);
+    if (dynamic == 0)
+        return;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (;;) {
+        uint64_t c = 0;
+        if (lane == 0)
+            c = atomicAdd(reinterpret_cast<unsigned long long *>(&a.header->next[CLASS]), 1ull);
+        const uint64_t s = S_static + uniform64(c);
+        if (s >= S)
+            break;
+        run_share<CLASS, BPT>(lds, lc, a, list, n, C, s, S);
+    }
+}
+
+// One per list: CLASS 0 runs the serial list and then its shares of the
+// forward list with the encryption tables, CLASS 1 its shares of the inverse
+// list with the decryption tables.  Persistent: one workgroup per compute
+// unit, every wave with its own shares.
+template <int CLASS, int BPT>
+__global__ __launch_bounds__(kBatchWavesPerGroup * 64) void batch_kernel(const BatchKArgs a) {
     constexpr int DIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
-    const uint32_t ntiles = a.header->ntiles[CLASS];
-    if (ntiles == 0 && (CLASS != 0 || a.header->ntiles[2] == 0))
+    const uint32_t n = a.header->ntiles[CLASS];
+    const uint32_t nserial = CLASS == 0 ? a.header->ntiles[2] : 0u;
+    if (n == 0 && nserial == 0)
         return;
     __shared__ uint32_t lds[lds_words<DIR>()];
     stage_tables<LAYOUT_T4X32, DIR>(lds);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
-    if (CLASS == 0)
-        run_serial_tiles(lds, a);
-    const BatchTile *list = a.tiles + size_t(CLASS) * a.tile_capacity;
-    for (;;) {
-        uint32_t t = 0;
-        if (lane == 0)
-            t = atomicAdd(&a.header->next[CLASS], 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= ntiles)
-            break;
-        const BatchTile tile = list[t];
-        const aes_msg_desc d = a.desc[tile.msg];
-        const int nr = desc_nr(d);
-        if (d.mode == AES_MODE_XTS) {
-            constexpr int XDIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
-            if (nr == 10) run_xts_tile<10, XDIR, BPT>(lds, lc, a, d, tile);
-            else if (nr == 12) run_xts_tile<12, XDIR, BPT>(lds, lc, a, d, tile);
-            else run_xts_tile<14, XDIR, BPT>(lds, lc, a, d, tile);
-        } else if (CLASS == 1 && d.mode == AES_MODE_CBC) {
-            if (nr == 10) run_tile<10, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
-            else if (nr == 12) run_tile<12, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
-            else run_tile<14, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, tile);
-        } else if (CLASS == 1) {
-            if (nr == 10) run_tile<10, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
-            else if (nr == 12) run_tile<12, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
-            else run_tile<14, MODE_ECB, DIR_DEC, BPT>(lds, lc, a, d, tile);
-        } else if (d.mode == AES_MODE_ECB) {
-            if (nr == 10) run_tile<10, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, tile);
-            else if (nr == 12) run_tile<12, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, tile);
-            else run_tile<14, MODE_ECB, DIR_ENC, BPT>(lds, lc, a, d, tile);
-        } else {
-            if (nr == 10) run_tile<10, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, tile);
-            else if (nr == 12) run_tile<12, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, tile);
-            else run_tile<14, MODE_CTR, DIR_ENC, BPT>(lds, lc, a, d, tile);
-        }
-    }
+    const uint32_t wave = blockIdx.x * kBatchWavesPerGroup + uniform32(threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * kBatchWavesPerGroup;
+    if (CLASS == 0 && nserial)
+        run_serial(lds, a, nserial, wave, nwaves);
+    if (n)
+        run_shares<CLASS, BPT>(lds, lc, a, n, wave, nwaves);
 }
-
 
 // ---- synthetic payloads for the request loop ------------------------------
 // The payload of a request is the SplitMix64 stream of its seed: word i =
@@ -443,21 +622,26 @@ __global__ __launch_bounds__(256) void fill_kernel(const FillKArgs a) {
 
 hipError_t upload_tables_batch(const HostTables &t) { return upload_base_tables(t); }
 
-hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL(keyexp_kernel, dim3((a.max_msgs + 255) / 256), dim3(256), 0, stream, a);
+hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists) {
+    if (grid < 1 || grid * kBatchWavesPerGroup > kBatchMaxWaves)
+        return hipErrorInvalidConfiguration;
+    const int prep_grid = 1 + (a.max_msgs + kPlanThreads - 1) / kPlanThreads;
+    hipLaunchKernelGGL(prep_kernel, dim3(prep_grid), dim3(kPlanThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
+    if (e != hipSuccess || !(lists & 7u))
         return e;
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, a);
-    e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((batch_kernel<0, 2>), dim3(grid), dim3(1024), 0, stream, a);
-    e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((batch_kernel<1, 2>), dim3(grid), dim3(1024), 0, stream, a);
-    return hipGetLastError();
+    // the forward kernel also runs the serial list
+    if (lists & 5u) {
+        hipLaunchKernelGGL((batch_kernel<0, 2>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (lists & 2u) {
+        hipLaunchKernelGGL((batch_kernel<1, 2>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream) {

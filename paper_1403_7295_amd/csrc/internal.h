@@ -110,27 +110,39 @@ hipError_t upload_tables_gcm(const HostTables &t);
 hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream);
 
 // ---- batches (batch_kernels.hip) -------------------------------------------
-// Workspace = header | key schedules (max_msgs slots) | tiles[3][capacity].
+// Workspace = header | key schedules (max_msgs slots) | items[3][max_msgs].
 struct BatchHeader {
-    uint32_t ntiles[3];   // forward list (ECB encrypt, CTR, XTS encrypt), inverse list (ECB,
-                          // CBC and XTS decrypt), serial list (CBC encrypt: one whole
-                          // message each)
-    uint32_t next[3];     // next tile to hand out, per list
+    uint32_t ntiles[3];   // messages in the forward list (ECB encrypt, CTR, XTS encrypt),
+                          // the inverse list (ECB, CBC and XTS decrypt) and the serial
+                          // list (CBC encrypt)
     uint32_t rejected;    // messages whose descriptor failed the checks
-    uint32_t overflow;    // 1 if the tiles did not fit the workspace
-    uint32_t pad[56];
+    uint64_t next[3];     // forward and inverse lists: next share handed out from the
+                          // counter; serial list: next message
+    uint64_t cost[2];     // work of the forward and inverse lists, in cost units
+    uint32_t pad[50];
 };
 static_assert(sizeof(BatchHeader) == 256, "header is one 256-byte line");
 
-struct BatchTile {
+// One message in a list.  Forward and inverse lists: start = the cost units of
+// the messages before it in the list.  Serial list: count = its blocks.
+struct BatchItem {
     uint32_t msg;     // message index
-    uint32_t count;   // blocks in this tile
-    uint64_t first;   // first block of the tile within its message
+    uint32_t count;
+    uint64_t start;
 };
 
 // encryption schedule at 0, decryption schedule at 64; an XTS message keeps
 // its tweak key's encryption schedule in the half its direction leaves free
 constexpr int kKeySlotWords = 128;
+// A wave's share of a message starts and ends on a multiple of this many
+// blocks by default (four steps of the block loop, 64 lanes x 2 blocks; the
+// best of 128 .. 1024 over batch sizes from one message to gigabytes).  The
+// largest allowed keeps the rounding well below a share (thousands of blocks).
+constexpr int kDefaultSplitBlocks = 512;
+constexpr int kMaxSplitBlocks = 1024;
+// The cipher kernels run at most this many waves (256 workgroups of 16).
+constexpr int kBatchMaxWaves = 4096;
+constexpr int kBatchWavesPerGroup = 16;
 
 struct BatchKArgs {
     const aes_msg_desc *desc;
@@ -145,9 +157,8 @@ struct BatchKArgs {
     uint64_t out_bytes;
     BatchHeader *header;
     uint32_t *keytab;
-    BatchTile *tiles;
-    uint64_t tile_capacity;
-    uint32_t tile_blocks;
+    BatchItem *items;        // three lists of max_msgs entries
+    uint32_t split_blocks;   // a share starts and ends on a multiple of this
 };
 
 // Synthetic payloads of the request loop (batch_kernels.hip).
@@ -167,6 +178,9 @@ struct FillKArgs {
 hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream);
 
 hipError_t upload_tables_batch(const HostTables &t);
-hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream);
+// lists: bit k set if list k may hold tiles (bit 0 forward, 1 inverse, 2
+// serial); a cipher kernel whose lists are all known to be empty is not
+// launched.  Key Expansion and the plan always run.
+hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists = 7u);
 
 }  // namespace aesgpu

@@ -24,8 +24,8 @@
 
 namespace aesgpu {
 int serve_fail(int status, const std::string &msg);
-int serve_device(int *cus);
-size_t serve_batch_layout(int max_msgs, uint64_t max_total_blocks, int tile_blocks, uint64_t *cap);
+int serve_device(int *cus, int *batch_grid);
+size_t serve_batch_layout(int max_msgs);
 int serve_batch_args(const aes_batch *b, BatchKArgs *a);
 }  // namespace aesgpu
 
@@ -52,22 +52,18 @@ struct ServeLayout {
     size_t arena;
     size_t desc_off, fill_off, ws_off, ws_bytes, slot_bytes, staged_bytes;
     size_t total;
-    int tile_blocks;
 };
 
 bool make_layout(const aes_serve_cfg &c, ServeLayout *L) {
     if (c.streams < 1 || c.streams > kMaxStreams || c.max_batch_msgs < 1 || c.max_batch_msgs > 65536 ||
-        c.budget_bytes < kAlign || c.tile_blocks < 0)
+        c.budget_bytes < kAlign || c.tile_blocks < 0 || c.tile_blocks > kMaxSplitBlocks)
         return false;
     L->arena = c.budget_bytes / kAlign * kAlign;
-    L->tile_blocks = c.tile_blocks ? c.tile_blocks : 8192;
     L->desc_off = sizeof(SlotHeader);
     L->fill_off = L->desc_off + round_up(size_t(c.max_batch_msgs) * sizeof(aes_msg_desc), kAlign);
     L->staged_bytes = L->fill_off + round_up(size_t(c.max_batch_msgs) * sizeof(FillDesc), kAlign);
     L->ws_off = L->staged_bytes;
-    L->ws_bytes = serve_batch_layout(c.max_batch_msgs, c.budget_bytes / 16, L->tile_blocks, nullptr);
-    if (L->ws_bytes == 0)
-        return false;
+    L->ws_bytes = serve_batch_layout(c.max_batch_msgs);
     L->slot_bytes = L->ws_off + round_up(L->ws_bytes, kAlign);
     L->total = L->arena + size_t(c.streams) * L->slot_bytes;
     return true;
@@ -92,6 +88,7 @@ struct Loop {
     aes_serve_stats st{};
     bool sim;
     int cus = 0;
+    int batch_grid = 0;
     const uint8_t *keys;
     int nkeys;
     uint8_t *arena_base;
@@ -119,6 +116,7 @@ struct Loop {
         aes_msg_desc *d = reinterpret_cast<aes_msg_desc *>(s.host + L.desc_off);
         FillDesc *f = reinterpret_cast<FillDesc *>(s.host + L.fill_off);
         uint64_t chunks = 0;
+        unsigned lists = 0;   // the batch kernel's lists this batch uses
         for (int k = 0; k < n; k++) {
             const aes_request &q = reqs[s.reqs[k]];
             const aes_request_result &r = res[s.reqs[k]];
@@ -136,6 +134,9 @@ struct Loop {
             f[k].seed = q.payload_seed;
             f[k].chunk_first = chunks;
             chunks += (q.nbytes + kFillChunk - 1) / kFillChunk;
+            const bool inverse = q.decrypt && (q.mode == AES_MODE_ECB || q.mode == AES_MODE_CBC);
+            const bool serial = !q.decrypt && q.mode == AES_MODE_CBC;
+            lists |= serial ? 4u : inverse ? 2u : 1u;
         }
         h->nmsg = n;
         h->nchunks = chunks;
@@ -163,13 +164,12 @@ struct Loop {
             b.workspace = s.dev + L.ws_off;
             b.workspace_bytes = L.ws_bytes;
             b.max_msgs = cfg.max_batch_msgs;
-            b.max_total_blocks = cfg.budget_bytes / 16;
-            b.tile_blocks = L.tile_blocks;
+            b.tile_blocks = cfg.tile_blocks;
             BatchKArgs ka;
             int st = serve_batch_args(&b, &ka);
             if (st != AES_OK)
                 return st;
-            e = launch_batch(ka, cus, s.stream);
+            e = launch_batch(ka, batch_grid, s.stream, lists);
         }
         if (e == hipSuccess)
             e = hipEventRecord(s.event, s.stream);
@@ -314,7 +314,7 @@ int aes_serve_scratch_size(const aes_serve_cfg *cfg, size_t *bytes) {
     ServeLayout L;
     if (!make_layout(*cfg, &L))
         return serve_fail(AES_E_ARG, "streams 1..16, max_batch_msgs 1..65536, budget_bytes >= 256, "
-                                     "tile_blocks >= 0");
+                                     "tile_blocks 0 .. 1024");
     *bytes = L.total;
     return AES_OK;
 }
@@ -356,7 +356,7 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
             return serve_fail(AES_E_ALIGN, "d_scratch must be 256-byte aligned");
         if (scratch_bytes < L.total)
             return serve_fail(AES_E_LENGTH, "scratch smaller than aes_serve_scratch_size reports");
-        rc = serve_device(&loop.cus);
+        rc = serve_device(&loop.cus, &loop.batch_grid);
         if (rc != AES_OK)
             return rc;
         loop.arena_base = static_cast<uint8_t *>(d_scratch);

@@ -164,27 +164,22 @@ def test_launch_config_validation(A):
 
 
 def test_batch_workspace_size(A):
-    n = A.aes_batch_workspace_size(10, 1000, 100)
-    # header + 10 key slots of 512 bytes + three tile lists of (10 + 10) 16-byte tiles
-    assert n == 256 + 10 * 512 + 3 * 20 * 16
-    assert A.aes_batch_workspace_size(10, 1000, 0) == 256 + 10 * 512 + 3 * (10 + 1) * 16
-    for bad in ((0, 10, 0), (5, 10, -1)):
+    # header + 10 key slots of 512 bytes + three lists of 10 16-byte items
+    assert A.aes_batch_workspace_size(10) == 256 + 10 * 512 + 3 * 10 * 16
+    assert A.aes_batch_workspace_size(1) == 256 + 512 + 3 * 16
+    for bad in (0, -3):
         with pytest.raises(A.AESError) as e:
-            A.aes_batch_workspace_size(*bad)
+            A.aes_batch_workspace_size(bad)
         assert e.value.code == A.AES_E_ARG
-    with pytest.raises(A.AESError) as e:
-        A.aes_batch_workspace_size(1, 1 << 62, 1)
-    assert e.value.code == A.AES_E_LENGTH
 
 
 def test_batch_argument_checks(A):
-    ws = A.aes_batch_workspace_size(4, 64, 0)
+    ws = A.aes_batch_workspace_size(4)
 
     def batch(**kw):
         f = dict(desc=0x100000, nmsg=4, d_nmsg=None, keys=0x200000, nkeys=4,
                  in_base=0x300000, in_bytes=4096, out_base=0x400000, out_bytes=4096,
-                 workspace=0x500000, workspace_bytes=ws, max_msgs=4, max_total_blocks=64,
-                 tile_blocks=0)
+                 workspace=0x500000, workspace_bytes=ws, max_msgs=4, tile_blocks=0)
         f.update(kw)
         return A.aes_batch(**f)
 
@@ -201,6 +196,8 @@ def test_batch_argument_checks(A):
     assert code(batch(in_base=0x300008)) == A.AES_E_ALIGN
     assert code(batch(workspace=0x500010)) == A.AES_E_ALIGN
     assert code(batch(workspace_bytes=ws - 1)) == A.AES_E_LENGTH
+    assert code(batch(tile_blocks=-1)) == A.AES_E_ARG
+    assert code(batch(tile_blocks=1025)) == A.AES_E_ARG
 
 
 def test_descriptor_layout(A):

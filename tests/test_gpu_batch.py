@@ -1,6 +1,6 @@
-"""The batched path (on-device key expansion, tile plan, persistent kernels,
-graph replay) against the oracle and against the single-buffer path, bit for
-bit, through the C ABI."""
+"""The batched path (on-device key expansion, the plan that splits the work
+into one share per wave, persistent kernels, graph replay) against the oracle
+and against the single-buffer path, bit for bit, through the C ABI."""
 import numpy as np
 import pytest
 
@@ -98,13 +98,13 @@ def test_batch_matches_oracle(A, O):
     x, xd, yd = buffers(descs, 41)
     b = A.Batch(descs, keys, xd, yd)
     b.run()
-    tiles, rejected = b.query()
-    assert rejected == 0 and tiles > 0
+    planned, rejected = b.query()
+    assert rejected == 0 and planned > 0
     check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
 
 
-@pytest.mark.parametrize("tile_blocks", [1, 64, 777, 8192])
-def test_tile_size_and_order_do_not_matter(A, tile_blocks):
+@pytest.mark.parametrize("tile_blocks", [1, 64, 777, 1024])
+def test_split_granularity_and_order_do_not_matter(A, tile_blocks):
     descs, keys = mixed_messages(A, 120, 42, max_len=1 << 18)
     x, xd, y0 = buffers(descs, 42)
     A.Batch(descs, keys, xd, y0).run()
@@ -163,8 +163,8 @@ def test_invalid_descriptors_are_skipped(A, O):
         bad["nbytes"][m] = nbytes
     b = A.Batch(bad, keys, xd, yd)
     b.run()
-    tiles, rejected = b.query()
-    assert rejected == 8
+    planned, rejected = b.query()
+    assert rejected == 8 and planned == len(bad) - 8
     y = yd.cpu().numpy()
     for m in range(8):
         o, n = int(descs["out_off"][m]), int(descs["nbytes"][m])
@@ -172,16 +172,55 @@ def test_invalid_descriptors_are_skipped(A, O):
     check_against_oracle(O, descs[8:], keys, x, y)
 
 
-def test_tile_overflow_is_reported(A):
-    descs, keys = mixed_messages(A, 20, 47, max_len=4096, min_len=4096, mode=0, decrypt=0)
-    x, xd, yd = buffers(descs, 47)
-    # the caller under-declares the batch: 20 messages of 256 blocks in tiles of
-    # 64 blocks need 80 tiles, the workspace has room for 20 + 1
-    b = A.Batch(descs, keys, xd, yd, tile_blocks=64, max_total_blocks=64)
+@pytest.mark.parametrize("kind", ["ctr", "xts", "ecb_dec", "cbc_dec"])
+def test_one_message_is_split_over_every_wave(A, O, kind):
+    """A single message in a batch: the plan splits it over all the cipher
+    kernel's waves (thousands of shares, each a few blocks), and the result
+    is the oracle's."""
+    n = 2 * 1024 * 1024 + (5 if kind == "ctr" else 0)
+    mode = {"ctr": 1, "xts": 3, "ecb_dec": 0, "cbc_dec": 2}[kind]
+    keys = np.zeros((2, 32), np.uint8)
+    keys[0, :16] = seedgen.key(48, 0, 128)
+    keys[1, :16] = seedgen.key(48, 1, 128)
+    ctr0 = A.xts_ctr0(1000, 1, 512) if kind == "xts" else seedgen.nonce(48, 0)
+    descs = A.make_descs([n], keybits=128, mode=mode, decrypt=kind in ("ecb_dec", "cbc_dec"), ctr0=ctr0)
+    x, xd, yd = buffers(descs, 48)
+    b = A.Batch(descs, keys, xd, yd)
     b.run()
-    with pytest.raises(A.AESError) as e:
-        b.query()
-    assert e.value.code == A.AES_E_LENGTH
+    planned, rejected = b.query()
+    assert (planned, rejected) == (1, 0)
+    check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
+
+
+def test_many_tiny_messages(A, O):
+    """More messages than waves, most of them one or two blocks, some empty:
+    shares hold many messages each."""
+    rng = np.random.default_rng(49)
+    n = 6000
+    lens = rng.integers(0, 3, n) * 16 + np.where(rng.random(n) < 0.3, rng.integers(1, 16, n), 0)
+    mode = np.where(lens % 16 != 0, 1, rng.integers(0, 2, n))
+    keybits = rng.choice([128, 256], n)
+    keys = np.zeros((n, 32), np.uint8)
+    for m in range(n):
+        keys[m, :keybits[m] // 8] = seedgen.key(49, m, int(keybits[m]))
+    descs = A.make_descs(lens, keybits=keybits, mode=mode, decrypt=rng.integers(0, 2, n),
+                         ctr0=seedgen.nonce(49, 0))
+    x, xd, yd = buffers(descs, 49)
+    b = A.Batch(descs, keys, xd, yd)
+    b.run()
+    planned, rejected = b.query()
+    assert (planned, rejected) == (n, 0)
+    check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
+
+
+def test_empty_messages_only(A):
+    descs = A.make_descs([0, 0, 0], mode=["ecb", "ctr", "cbc"], decrypt=[1, 0, 0])
+    keys = np.zeros((3, 32), np.uint8)
+    xd = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    yd = torch.full_like(xd, SENTINEL)
+    b = A.Batch(descs, keys, xd, yd)
+    b.run()
+    assert b.query() == (3, 0)
     assert (yd.cpu().numpy() == SENTINEL).all()
 
 
@@ -219,14 +258,14 @@ def test_cbc_in_place_decryption_is_rejected(A, O):
     x, xd, _ = buffers(descs, 48)
     b = A.Batch(descs, keys, xd, xd)
     b.run()
-    tiles, rejected = b.query()
-    assert rejected == 30 and tiles == 0
+    planned, rejected = b.query()
+    assert rejected == 30 and planned == 0
     assert np.array_equal(xd.cpu().numpy(), x)
 
 
 def test_many_serial_cbc_messages(A, O):
-    # more CBC-encrypt messages than one wave takes (64 per claim), with
-    # parallel tiles mixed in
+    # more CBC-encrypt messages than one wave takes (64, one per lane), with
+    # parallel work mixed in
     descs, keys = mixed_messages(A, 200, 49, max_len=1 << 14, min_len=16)
     descs["mode"][:150] = 2
     descs["decrypt"][:150] = 0
@@ -234,9 +273,30 @@ def test_many_serial_cbc_messages(A, O):
     x, xd, yd = buffers(descs, 49)
     b = A.Batch(descs, keys, xd, yd)
     b.run()
-    tiles, rejected = b.query()
+    planned, rejected = b.query()
     assert rejected == 0
     check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
+
+
+def test_serial_list_beyond_the_static_chunks(A, O):
+    """More CBC-encrypt messages than 64 per wave of the largest grid
+    (4,096 waves), so the rest are handed out from the counter: one-block
+    messages under one key with their own IVs, C = Cipher(P xor IV), checked
+    in one oracle ECB pass."""
+    n = 64 * 4096 + 7000
+    rng = np.random.default_rng(50)
+    ivs = rng.integers(0, 256, (n, 16), dtype=np.uint8)
+    keys = np.zeros((1, 32), np.uint8)
+    keys[0, :16] = seedgen.key(50, 0, 128)
+    descs = A.make_descs(np.full(n, 16), key_idx=0, keybits=128, mode="cbc", ctr0=ivs)
+    x, xd, yd = buffers(descs, 50)
+    b = A.Batch(descs, keys, xd, yd)
+    b.run()
+    assert b.query() == (n, 0)
+    rk, nr = O.expand_key(keys[0][:16])
+    want = O.ecb_encrypt(rk, nr, (x[:16 * n].reshape(n, 16) ^ ivs).reshape(-1))
+    assert np.array_equal(yd.cpu().numpy()[:16 * n], want)
+    b.close()
 
 
 @pytest.mark.parametrize("decrypt", [0, 1])
