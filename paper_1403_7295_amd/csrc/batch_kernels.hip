@@ -480,6 +480,10 @@ constexpr uint64_t kShareCost = 4096 * 16;
 // take the rest.  Shorter lists are split statically only, without atomics.
 constexpr uint64_t kDynamicMinRounds = 8;
 
+// Blocks per thread of XTS pieces: the tweak work's registers on top of four
+// blocks per thread would spill in the forward kernel.
+constexpr int kXtsBpt = 2;
+
 // Share s of S over a list of total cost C: the cost units
 // [s C / S, (s+1) C / S), from the item holding its start through the one
 // holding its end.
@@ -502,9 +506,9 @@ __device__ __forceinline__ void run_share(const uint32_t *lds, const LaneConsts 
             const int nr = desc_nr(d);
             if (d.mode == AES_MODE_XTS) {
                 constexpr int XDIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
-                if (nr == 10) run_xts_range<10, XDIR, BPT>(lds, lc, a, d, msg, first, end);
-                else if (nr == 12) run_xts_range<12, XDIR, BPT>(lds, lc, a, d, msg, first, end);
-                else run_xts_range<14, XDIR, BPT>(lds, lc, a, d, msg, first, end);
+                if (nr == 10) run_xts_range<10, XDIR, kXtsBpt>(lds, lc, a, d, msg, first, end);
+                else if (nr == 12) run_xts_range<12, XDIR, kXtsBpt>(lds, lc, a, d, msg, first, end);
+                else run_xts_range<14, XDIR, kXtsBpt>(lds, lc, a, d, msg, first, end);
             } else if (CLASS == 1 && d.mode == AES_MODE_CBC) {
                 if (nr == 10) run_range<10, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
                 else if (nr == 12) run_range<12, MODE_CBC, DIR_DEC, BPT>(lds, lc, a, d, msg, first, end);
@@ -632,12 +636,13 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
         return e;
     // the forward kernel also runs the serial list
     if (lists & 5u) {
-        hipLaunchKernelGGL((batch_kernel<0, 2>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        hipLaunchKernelGGL((batch_kernel<0, 4>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
     if (lists & 2u) {
+        // two blocks per thread: four spill with the inverse tables' registers
         hipLaunchKernelGGL((batch_kernel<1, 2>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
         e = hipGetLastError();
     }
