@@ -169,8 +169,8 @@ def bench_size_sweep(torch, A, dev, stream, sizes=(1 << 20, 1 << 22, 1 << 24, 1 
 def bench_batched(torch, A, dev, stream, reps=5):
     """The ragged multi-message workload: 10,000 messages, lengths
     log-uniform in [16 B, 16 MiB], half AES-128 and half AES-256 keys, ECB
-    encrypt.  One graph launch (on-device key expansion, tile plan,
-    persistent kernels) against one aes_expand_key + aes_encrypt per message."""
+    encrypt.  One graph launch (on-device key expansion, the plan, persistent
+    kernels) against one aes_expand_key + aes_encrypt per message."""
     lens, keybits, keys, _ = seedgen.ragged_batch(4, 10000)
     descs = A.make_descs(lens, keybits=keybits, mode="ecb")
     total = int(lens.sum())

@@ -1,4 +1,4 @@
-"""Launch autotuner for the buffer kernels and the batch tile size.
+"""Launch autotuner for the buffer kernels and the batch split step.
 
 For every operation (ECB encrypt, ECB decrypt, CTR), key size and buffer
 size bucket it times every candidate launch configuration (table layout,
@@ -31,7 +31,7 @@ BITSLICED = dict(layout=2, blocks_per_thread=0, wg_size=0, grid=0)
 OPS = (("ecb_enc", "ecb", 0), ("ecb_dec", "ecb", 1), ("ctr", "ctr", 0))
 # size buckets: the size tuned at, and the smallest size the result applies to
 BUCKETS = ((1 << 16, 0), (1 << 20, 1 << 18), (1 << 24, 1 << 22), (1 << 30, 1 << 27))
-TILE_CANDIDATES = (128, 256, 512, 1024)
+SPLIT_CANDIDATES = (128, 256, 512, 1024)
 
 
 def _time(torch, fn, reps, warm=2):
@@ -95,13 +95,13 @@ def tune_batch(A, torch, nmsg=2000, verbose=False):
     x = seedgen.data_torch(4, 0, total, "cuda")
     y = torch.empty_like(x)
     results = []
-    for tile in TILE_CANDIDATES:
-        b = A.Batch(descs, keys, x, y, tile_blocks=tile)
+    for split in SPLIT_CANDIDATES:
+        b = A.Batch(descs, keys, x, y, tile_blocks=split)
         t = _time(torch, lambda: b.launch_graph(), 5)
         b.close()
-        results.append(dict(tile_blocks=tile, seconds=t, GBps=total / t / 1e9))
+        results.append(dict(tile_blocks=split, seconds=t, GBps=total / t / 1e9))
         if verbose:
-            print("batch split %6d: %.1f GB/s" % (tile, total / t / 1e9), flush=True)
+            print("batch split %6d: %.1f GB/s" % (split, total / t / 1e9), flush=True)
     best = min(results, key=lambda r: r["seconds"])
     return best["tile_blocks"], results
 
@@ -150,8 +150,8 @@ def main():
     entries, log = tune_plain(A, torch, tuple(args.nr), verbose=True)
     table = {"device": device_key(torch), "entries": entries, "measurements": log}
     if not args.no_batch:
-        tile, blog = tune_batch(A, torch, verbose=True)
-        table["batch_tile_blocks"] = tile
+        split, blog = tune_batch(A, torch, verbose=True)
+        table["batch_tile_blocks"] = split
         table["batch_measurements"] = blog
     table["seconds"] = round(time.time() - t0, 1)
     if args.out:

@@ -570,7 +570,7 @@ int aes_batch_query(const aes_batch *b, void *stream, uint64_t *planned, uint64_
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch query: ") + hipGetErrorString(e));
     if (planned)
-        *planned = uint64_t(h.ntiles[0]) + h.ntiles[1] + h.ntiles[2];
+        *planned = uint64_t(h.nitems[0]) + h.nitems[1] + h.nitems[2];
     if (rejected)
         *rejected = h.rejected;
     return AES_OK;

@@ -1,27 +1,27 @@
 // Batches of independent messages (each with its own key, length, mode and
 // direction) in one launch sequence:
 //
-//   prep_kernel     workgroup 0 plans: it checks every descriptor, cuts
-//                   each message into tiles of at most T blocks (a tile never
-//                   spans two messages; an XTS tile is whole groups of 64
-//                   data units), and lays the tiles out in three lists:
-//                   forward (ECB encryption, CTR, XTS encryption: the
-//                   encryption tables), inverse (ECB, CBC and XTS decryption:
-//                   the inverse ones) and serial (CBC encryption, one message
-//                   per tile).  It also zeroes the tile counters, so the
+//   prep_kernel     workgroup 0 plans: it checks every descriptor and puts
+//                   the messages in three lists: forward (ECB encryption,
+//                   CTR, XTS encryption: the encryption tables), inverse
+//                   (ECB, CBC and XTS decryption: the inverse ones) and
+//                   serial (CBC encryption), each message with the work of
+//                   the list before it.  It also zeroes the counters, so the
 //                   sequence can be replayed from a graph without any memset.
 //                   The other workgroups run Key Expansion (FIPS-197 section
 //                   5.2), one lane per message, plus the equivalent-inverse
 //                   schedule (section 5.3.5) for decryption and the tweak
 //                   key's schedule for XTS.
-//   batch_kernel    persistent, one per list: every wave takes the next tile
-//                   off its list's counter, reads that message's round keys
-//                   into scalar registers and runs the same block loop as the
-//                   single-buffer kernels, until the list is empty.
+//   batch_kernel    persistent, one per list: the list's work is cut into
+//                   equal shares, one per wave and round, each covering parts
+//                   of one or more messages; a wave runs its shares (for
+//                   long lists, the second half of them taken off a counter)
+//                   with every message's round keys in scalar registers and
+//                   the same block loop as the single-buffer kernels.
 //
-// This is the paper's method (cut the data into chunks, process the chunks
-// in parallel, Section IV) applied per message, with the chunk size chosen
-// for the GPU rather than by the number of cores.
+// This is the paper's method (cut the data into one chunk per processor and
+// process the chunks in parallel, Section IV) applied across messages, with
+// the processors being the GPU's waves.
 #include <hip/hip_runtime.h>
 
 #include "aesgpu.h"
@@ -71,7 +71,7 @@ __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKAr
     if (d.mode == AES_MODE_CBC && d.decrypt && a.in_base == a.out_base && d.nbytes &&
         d.in_off < d.out_off + d.nbytes && d.out_off < d.in_off + d.nbytes)
         return false;
-    // a CBC encryption is one serial tile; its block count must fit the tile
+    // a CBC encryption runs on one lane; its block count must fit the list item
     if (d.mode == AES_MODE_CBC && !d.decrypt && (d.nbytes >> 4) >= 0xFFFFFFFFull)
         return false;
     if ((d.in_off | d.out_off) & 15u)
@@ -291,7 +291,7 @@ __device__ __forceinline__ void plan_lists(const BatchKArgs &a, uint64_t (*wsum)
     if (tid == 0) {
         BatchHeader *h = a.header;
         for (int k = 0; k < 3; k++) {
-            h->ntiles[k] = uint32_t(total[k]);
+            h->nitems[k] = uint32_t(total[k]);
             h->next[k] = 0;
         }
         h->cost[0] = total[3];
@@ -567,8 +567,8 @@ __device__ __forceinline__ void run_shares(const uint32_t *lds, const LaneConsts
 template <int CLASS, int BPT>
 __global__ __launch_bounds__(kBatchWavesPerGroup * 64) void batch_kernel(const BatchKArgs a) {
     constexpr int DIR = CLASS == 0 ? DIR_ENC : DIR_DEC;
-    const uint32_t n = a.header->ntiles[CLASS];
-    const uint32_t nserial = CLASS == 0 ? a.header->ntiles[2] : 0u;
+    const uint32_t n = a.header->nitems[CLASS];
+    const uint32_t nserial = CLASS == 0 ? a.header->nitems[2] : 0u;
     if (n == 0 && nserial == 0)
         return;
     __shared__ uint32_t lds[lds_words<DIR>()];

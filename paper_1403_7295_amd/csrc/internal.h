@@ -112,7 +112,7 @@ hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream);
 // ---- batches (batch_kernels.hip) -------------------------------------------
 // Workspace = header | key schedules (max_msgs slots) | items[3][max_msgs].
 struct BatchHeader {
-    uint32_t ntiles[3];   // messages in the forward list (ECB encrypt, CTR, XTS encrypt),
+    uint32_t nitems[3];   // messages in the forward list (ECB encrypt, CTR, XTS encrypt),
                           // the inverse list (ECB, CBC and XTS decrypt) and the serial
                           // list (CBC encrypt)
     uint32_t rejected;    // messages whose descriptor failed the checks
@@ -178,7 +178,7 @@ struct FillKArgs {
 hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream);
 
 hipError_t upload_tables_batch(const HostTables &t);
-// lists: bit k set if list k may hold tiles (bit 0 forward, 1 inverse, 2
+// lists: bit k set if list k may hold messages (bit 0 forward, 1 inverse, 2
 // serial); a cipher kernel whose lists are all known to be empty is not
 // launched.  Key Expansion and the plan always run.
 hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists = 7u);
