@@ -355,9 +355,12 @@ int gcm_crypt(int decrypt, const void *in, void *out, size_t nbytes, const void 
 
 
 // Workspace bytes for up to max_msgs messages: header, one key slot and one
-// list entry per message in each of the three lists.
+// list entry per message in each of the three lists, the plan's counters
+// per chunk of messages.
 size_t batch_layout(int max_msgs) {
-    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(max_msgs) * sizeof(BatchItem);
+    const size_t chunks = (size_t(max_msgs) + kBatchChunk - 1) / kBatchChunk;
+    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(max_msgs) * sizeof(BatchItem) +
+           chunks * kBatchChunkCounters * sizeof(uint64_t);
 }
 
 // Cipher-kernel workgroups for a batch launch on this device.
@@ -393,6 +396,7 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
     a->header = reinterpret_cast<BatchHeader *>(ws);
     a->keytab = reinterpret_cast<uint32_t *>(ws + sizeof(BatchHeader));
     a->items = reinterpret_cast<BatchItem *>(ws + items);
+    a->chunk_totals = reinterpret_cast<uint64_t *>(ws + items + 3 * size_t(b->max_msgs) * sizeof(BatchItem));
     a->split_blocks = uint32_t(b->tile_blocks ? b->tile_blocks : kDefaultSplitBlocks);
     return AES_OK;
 }

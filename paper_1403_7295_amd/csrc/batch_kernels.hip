@@ -1,17 +1,18 @@
 // Batches of independent messages (each with its own key, length, mode and
 // direction) in one launch sequence:
 //
-//   prep_kernel     workgroup 0 plans: it checks every descriptor and puts
-//                   the messages in three lists: forward (ECB encryption,
-//                   CTR, XTS encryption: the encryption tables), inverse
-//                   (ECB, CBC and XTS decryption: the inverse ones) and
-//                   serial (CBC encryption), each message with the work of
-//                   the list before it.  It also zeroes the counters, so the
-//                   sequence can be replayed from a graph without any memset.
-//                   The other workgroups run Key Expansion (FIPS-197 section
-//                   5.2), one lane per message, plus the equivalent-inverse
-//                   schedule (section 5.3.5) for decryption and the tweak
-//                   key's schedule for XTS.
+//   prep_kernel     one lane per message: checks the descriptor, runs Key
+//                   Expansion (FIPS-197 section 5.2) plus the
+//                   equivalent-inverse schedule (section 5.3.5) for
+//                   decryption and the tweak key's schedule for XTS, and
+//                   adds up per chunk of 256 messages what the plan needs.
+//   plan_kernel     one lane per message: puts the messages in three lists,
+//                   forward (ECB encryption, CTR, XTS encryption: the
+//                   encryption tables), inverse (ECB, CBC and XTS
+//                   decryption: the inverse ones) and serial (CBC
+//                   encryption), each message with the work of the list
+//                   before it.  It also zeroes the counters, so the sequence
+//                   can be replayed from a graph without any memset.
 //   batch_kernel    persistent, one per list: the list's work is cut into
 //                   equal shares, one per wave and round, each covering parts
 //                   of one or more messages; a wave runs its shares (for
@@ -24,6 +25,8 @@
 // the processors being the GPU's waves.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "aesgpu.h"
 #include "cipher_core.h"
 #include "internal.h"
@@ -35,7 +38,7 @@ namespace {
 // Workgroup size of the prep kernel: four waves, so that its workgroups fit
 // beside a cipher kernel's 16 waves on a compute unit (the request loop runs
 // several batches at once).
-constexpr int kPlanThreads = 256;
+constexpr int kPlanThreads = kBatchChunk;
 
 __device__ __forceinline__ int desc_nr(const aes_msg_desc &d) { return 10 + 2 * int(d.keybits_code); }
 
@@ -234,7 +237,7 @@ __device__ __forceinline__ void block_exclusive_scan(uint64_t (&v)[N], uint64_t 
     }
 }
 
-constexpr int kPlanCounters = 6;   // items in lists 0, 1, 2; cost of lists 0, 1; rejected
+constexpr int kPlanCounters = kBatchChunkCounters;   // items in lists 0, 1, 2; cost of lists 0, 1; rejected
 
 // floor(a b / c) without overflow (messages may overlap, so a list's cost is
 // not bounded by the memory size).
@@ -242,83 +245,54 @@ __device__ __forceinline__ uint64_t mul_div_floor(uint64_t a, uint64_t b, uint64
     return uint64_t((unsigned __int128)a * b / c);
 }
 
-// The plan (one workgroup).  Every thread takes a contiguous range of
-// messages; a scan gives each thread its place in the three lists and, for
-// the forward and inverse lists, the cost units before its messages (each
-// item's start), from which every wave finds its shares.
-__device__ __forceinline__ void plan_lists(const BatchKArgs &a, uint64_t (*wsum)[kPlanThreads / 64]) {
-    const uint32_t n = batch_count(a);
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (n + kPlanThreads - 1) / kPlanThreads;
-    const uint32_t m0 = min(n, tid * per), m1 = min(n, m0 + per);
-    uint64_t c[kPlanCounters] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t m = m0; m < m1; m++) {
-        const aes_msg_desc d = a.desc[m];
-        if (!desc_valid(d, a)) {
-            c[5]++;
-            continue;
-        }
-        // (selects, not indexed stores: keeps c[] in registers)
-        const int k = desc_class(d);
-        const uint64_t cost = ((d.nbytes + 15) >> 4) * block_cost(d);
-        c[0] += k == 0 ? 1 : 0;
-        c[1] += k == 1 ? 1 : 0;
-        c[2] += k == 2 ? 1 : 0;
-        c[3] += k == 0 ? cost : 0;
-        c[4] += k == 1 ? cost : 0;
-    }
-    uint64_t total[kPlanCounters];
-    block_exclusive_scan<kPlanCounters>(c, wsum, total);
-    for (uint32_t m = m0; m < m1; m++) {
-        const aes_msg_desc d = a.desc[m];
-        if (!desc_valid(d, a))
-            continue;
-        const int k = desc_class(d);
-        const uint64_t nblk = (d.nbytes + 15) >> 4;
-        const uint64_t i = k == 0 ? c[0] : k == 1 ? c[1] : c[2];
-        BatchItem it;
-        it.msg = m;
-        it.count = k == 2 ? uint32_t(nblk) : 0u;   // desc_valid keeps a serial message below 2^32 blocks
-        it.start = k == 0 ? c[3] : k == 1 ? c[4] : 0;
-        a.items[size_t(k) * a.max_msgs + i] = it;
-        const uint64_t cost = nblk * block_cost(d);
-        c[3] += k == 0 ? cost : 0;
-        c[4] += k == 1 ? cost : 0;
-        c[0] += k == 0 ? 1 : 0;
-        c[1] += k == 1 ? 1 : 0;
-        c[2] += k == 2 ? 1 : 0;
-    }
-    if (tid == 0) {
-        BatchHeader *h = a.header;
-        for (int k = 0; k < 3; k++) {
-            h->nitems[k] = uint32_t(total[k]);
-            h->next[k] = 0;
-        }
-        h->cost[0] = total[3];
-        h->cost[1] = total[4];
-        h->rejected = uint32_t(total[5]);
-    }
-}
-
-// The launch before the cipher kernels: workgroup 0 plans the lists, every
-// other workgroup expands the keys of kPlanThreads messages, one per lane.
-__global__ __launch_bounds__(kPlanThreads) void prep_kernel(const BatchKArgs a) {
-    __shared__ uint32_t tab[512];
-    __shared__ uint64_t wsum[kPlanCounters][kPlanThreads / 64];
-    if (blockIdx.x == 0) {
-        plan_lists(a, wsum);
-        return;
-    }
-    for (uint32_t i = threadIdx.x; i < 512; i += kPlanThreads)
-        tab[i] = g_base[i];
-    __syncthreads();
-    const uint32_t n = batch_count(a);
-    const uint32_t m = (blockIdx.x - 1) * kPlanThreads + threadIdx.x;
+// One message's contribution to the plan's counters (all zero past the
+// batch's end).
+__device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, uint32_t n, bool &valid, int &k,
+                                               uint64_t (&c)[kPlanCounters]) {
+    for (int j = 0; j < kPlanCounters; j++)
+        c[j] = 0;
+    valid = false;
+    k = 0;
     if (m >= n)
         return;
     const aes_msg_desc d = a.desc[m];
-    if (!desc_valid(d, a))
+    if (!desc_valid(d, a)) {
+        c[5] = 1;
         return;
+    }
+    valid = true;
+    k = desc_class(d);
+    const uint64_t cost = ((d.nbytes + 15) >> 4) * block_cost(d);
+    // (selects, not indexed stores: keeps c[] in registers)
+    c[0] = k == 0 ? 1 : 0;
+    c[1] = k == 1 ? 1 : 0;
+    c[2] = k == 2 ? 1 : 0;
+    c[3] = k == 0 ? cost : 0;
+    c[4] = k == 1 ? cost : 0;
+}
+
+// The first launch of a batch, one message per thread, kPlanThreads messages
+// per workgroup (a chunk): Key Expansion, and the chunk's counters for the
+// plan (items and cost per list, rejected descriptors).
+__global__ __launch_bounds__(kPlanThreads) void prep_kernel(const BatchKArgs a) {
+    __shared__ uint32_t tab[512];
+    __shared__ uint64_t wsum[kPlanCounters][kPlanThreads / 64];
+    for (uint32_t i = threadIdx.x; i < 512; i += kPlanThreads)
+        tab[i] = g_base[i];
+    const uint32_t n = batch_count(a);
+    const uint32_t m = blockIdx.x * kPlanThreads + threadIdx.x;
+    bool valid;
+    int k;
+    uint64_t c[kPlanCounters], total[kPlanCounters];
+    message_counts(a, m, n, valid, k, c);
+    block_exclusive_scan<kPlanCounters>(c, wsum, total);   // its barrier also covers tab[]
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < kPlanCounters; j++)
+            a.chunk_totals[size_t(blockIdx.x) * kPlanCounters + j] = total[j];
+    }
+    if (!valid)
+        return;
+    const aes_msg_desc d = a.desc[m];
     uint32_t *slot = a.keytab + size_t(m) * kKeySlotWords;
     if (d.keybits_code == 0)
         expand_message_keys<4>(a, d, slot, tab);
@@ -326,6 +300,58 @@ __global__ __launch_bounds__(kPlanThreads) void prep_kernel(const BatchKArgs a) 
         expand_message_keys<6>(a, d, slot, tab);
     else
         expand_message_keys<8>(a, d, slot, tab);
+}
+
+// The second launch, same chunks: each workgroup adds up the counters of the
+// chunks before it, scans its own messages and writes their list items in
+// message order, each with the cost of the list before it (its start).
+// Workgroup 0 also writes the header and zeroes the counters, so the whole
+// sequence can be replayed from a graph without any memset.
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) {
+    __shared__ uint64_t wsum[kPlanCounters][kPlanThreads / 64];
+    const uint32_t n = batch_count(a);
+    const uint32_t chunks = gridDim.x;
+    // counters of the chunks before this one, and of all of them
+    uint64_t before[kPlanCounters], all[kPlanCounters];
+    for (int j = 0; j < kPlanCounters; j++)
+        before[j] = all[j] = 0;
+    for (uint32_t ch = threadIdx.x; ch < chunks; ch += kPlanThreads) {
+        for (int j = 0; j < kPlanCounters; j++) {
+            const uint64_t v = a.chunk_totals[size_t(ch) * kPlanCounters + j];
+            before[j] += ch < blockIdx.x ? v : 0;
+            all[j] += v;
+        }
+    }
+    uint64_t base[kPlanCounters], sum_all[kPlanCounters];
+    block_exclusive_scan<kPlanCounters>(before, wsum, base);
+    __syncthreads();   // wsum is used again
+    block_exclusive_scan<kPlanCounters>(all, wsum, sum_all);
+    __syncthreads();
+    const uint32_t m = blockIdx.x * kPlanThreads + threadIdx.x;
+    bool valid;
+    int k;
+    uint64_t c[kPlanCounters], chunk_total[kPlanCounters];
+    message_counts(a, m, n, valid, k, c);
+    block_exclusive_scan<kPlanCounters>(c, wsum, chunk_total);   // c: the messages before m in the chunk
+    if (valid) {
+        const aes_msg_desc d = a.desc[m];
+        BatchItem it;
+        it.msg = m;
+        it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;   // desc_valid keeps a serial message below 2^32 blocks
+        it.start = k == 0 ? base[3] + c[3] : k == 1 ? base[4] + c[4] : 0;
+        const uint64_t i = k == 0 ? base[0] + c[0] : k == 1 ? base[1] + c[1] : base[2] + c[2];
+        a.items[size_t(k) * a.max_msgs + i] = it;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        BatchHeader *h = a.header;
+        for (int j = 0; j < 3; j++) {
+            h->nitems[j] = uint32_t(sum_all[j]);
+            h->next[j] = 0;
+        }
+        h->cost[0] = sum_all[3];
+        h->cost[1] = sum_all[4];
+        h->rejected = uint32_t(sum_all[5]);
+    }
 }
 
 __device__ __forceinline__ uint32_t uniform32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -622,16 +648,34 @@ __global__ __launch_bounds__(256) void fill_kernel(const FillKArgs a) {
     }
 }
 
+// A small copy from pinned host memory (16 bytes per lane and step).
+__global__ __launch_bounds__(256) void stage_kernel(const u32x4 *src, u32x4 *dst, uint64_t n16) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += uint64_t(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
 }  // namespace
 
 hipError_t upload_tables_batch(const HostTables &t) { return upload_base_tables(t); }
 
+hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStream_t stream) {
+    const uint64_t n16 = nbytes / 16;
+    const uint64_t grid = std::min<uint64_t>(std::max<uint64_t>((n16 + 255) / 256, 1), 64);
+    hipLaunchKernelGGL(stage_kernel, dim3(uint32_t(grid)), dim3(256), 0, stream,
+                       static_cast<const u32x4 *>(host_dev), static_cast<u32x4 *>(dev), n16);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists) {
     if (grid < 1 || grid * kBatchWavesPerGroup > kBatchMaxWaves)
         return hipErrorInvalidConfiguration;
-    const int prep_grid = 1 + (a.max_msgs + kPlanThreads - 1) / kPlanThreads;
-    hipLaunchKernelGGL(prep_kernel, dim3(prep_grid), dim3(kPlanThreads), 0, stream, a);
+    const int chunks = (a.max_msgs + kPlanThreads - 1) / kPlanThreads;
+    hipLaunchKernelGGL(prep_kernel, dim3(chunks), dim3(kPlanThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(plan_kernel, dim3(chunks), dim3(kPlanThreads), 0, stream, a);
+    e = hipGetLastError();
     if (e != hipSuccess || !(lists & 7u))
         return e;
     // the forward kernel also runs the serial list

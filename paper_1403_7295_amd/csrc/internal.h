@@ -110,7 +110,8 @@ hipError_t upload_tables_gcm(const HostTables &t);
 hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream);
 
 // ---- batches (batch_kernels.hip) -------------------------------------------
-// Workspace = header | key schedules (max_msgs slots) | items[3][max_msgs].
+// Workspace = header | key schedules (max_msgs slots) | items[3][max_msgs] |
+// chunk totals (the plan's counters per chunk of messages).
 struct BatchHeader {
     uint32_t nitems[3];   // messages in the forward list (ECB encrypt, CTR, XTS encrypt),
                           // the inverse list (ECB, CBC and XTS decrypt) and the serial
@@ -143,6 +144,10 @@ constexpr int kMaxSplitBlocks = 1024;
 // The cipher kernels run at most this many waves (256 workgroups of 16).
 constexpr int kBatchMaxWaves = 4096;
 constexpr int kBatchWavesPerGroup = 16;
+// Messages per chunk of the plan (one workgroup of the prep and plan
+// kernels), and the plan's counters per chunk.
+constexpr int kBatchChunk = 256;
+constexpr int kBatchChunkCounters = 6;
 
 struct BatchKArgs {
     const aes_msg_desc *desc;
@@ -158,6 +163,7 @@ struct BatchKArgs {
     BatchHeader *header;
     uint32_t *keytab;
     BatchItem *items;        // three lists of max_msgs entries
+    uint64_t *chunk_totals;  // the plan's counters per chunk of messages
     uint32_t split_blocks;   // a share starts and ends on a multiple of this
 };
 
@@ -176,6 +182,11 @@ struct FillKArgs {
     uint8_t *base;
 };
 hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream);
+// Copies nbytes (a multiple of 16, both pointers 16-byte aligned) from pinned
+// host memory, read through its device address, to device memory, as a
+// kernel on `stream`: the request loop's descriptors then reach the next
+// kernels without a hand-off from the copy engine.
+hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStream_t stream);
 
 hipError_t upload_tables_batch(const HostTables &t);
 // lists: bit k set if list k may hold messages (bit 0 forward, 1 inverse, 2

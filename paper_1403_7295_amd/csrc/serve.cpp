@@ -76,6 +76,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
     uint8_t *host = nullptr;     // pinned staging for header + descriptors
+    void *host_dev = nullptr;    // its address on the device
     uint8_t *dev = nullptr;      // this slot's device area
 };
 
@@ -140,9 +141,11 @@ struct Loop {
         }
         h->nmsg = n;
         h->nchunks = chunks;
-        // header + descriptors + fill descriptors go up in one copy
-        const size_t up = L.fill_off + size_t(n) * sizeof(FillDesc);
-        hipError_t e = hipMemcpyAsync(s.dev, s.host, up, hipMemcpyHostToDevice, s.stream);
+        // header + descriptors + fill descriptors go up in one copy, made by
+        // a kernel on the slot's stream (a copy-engine transfer would add a
+        // hand-off of tens of microseconds before the next kernel starts)
+        const size_t up = round_up(L.fill_off + size_t(n) * sizeof(FillDesc), 16);
+        hipError_t e = launch_stage(s.host_dev, s.dev, up, s.stream);
         FillKArgs fa;
         fa.fd = reinterpret_cast<const FillDesc *>(s.dev + L.fill_off);
         fa.d_nmsg = &reinterpret_cast<const SlotHeader *>(s.dev)->nmsg;
@@ -369,6 +372,8 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
                 e = hipEventCreateWithFlags(&s.event, hipEventDisableTiming);
             if (e == hipSuccess)
                 e = hipHostMalloc(reinterpret_cast<void **>(&s.host), L.staged_bytes, hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipHostGetDevicePointer(&s.host_dev, s.host, 0);
         }
         if (e != hipSuccess) {
             loop.error = std::string("stream set-up: ") + hipGetErrorString(e);

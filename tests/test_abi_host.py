@@ -164,9 +164,11 @@ def test_launch_config_validation(A):
 
 
 def test_batch_workspace_size(A):
-    # header + 10 key slots of 512 bytes + three lists of 10 16-byte items
-    assert A.aes_batch_workspace_size(10) == 256 + 10 * 512 + 3 * 10 * 16
-    assert A.aes_batch_workspace_size(1) == 256 + 512 + 3 * 16
+    # header + key slots of 512 bytes + three lists of 16-byte items + the
+    # plan's six 8-byte counters per chunk of 256 messages
+    assert A.aes_batch_workspace_size(10) == 256 + 10 * 512 + 3 * 10 * 16 + 48
+    assert A.aes_batch_workspace_size(1) == 256 + 512 + 3 * 16 + 48
+    assert A.aes_batch_workspace_size(257) == 256 + 257 * 512 + 3 * 257 * 16 + 2 * 48
     for bad in (0, -3):
         with pytest.raises(A.AESError) as e:
             A.aes_batch_workspace_size(bad)
