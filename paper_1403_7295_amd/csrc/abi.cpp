@@ -556,7 +556,9 @@ int aes_batch_run(const aes_batch *b, void *stream) {
     const DeviceState *d = current_device(&st);
     if (!d)
         return st;
-    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream));
+    // without a device-side count the host knows how many messages there are
+    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), 7u,
+                                a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     return AES_OK;
@@ -597,7 +599,7 @@ int aes_batch_graph_create(const aes_batch *b, void **graph) {
     if (e == hipSuccess)
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_batch(a, batch_grid(*d), s);
+        hipError_t le = launch_batch(a, batch_grid(*d), s, 7u, a.max_msgs);   // the count may change per replay
         e = hipStreamEndCapture(s, &g);
         if (le != hipSuccess)
             e = le;

@@ -302,6 +302,48 @@ __global__ __launch_bounds__(kPlanThreads) void prep_kernel(const BatchKArgs a) 
         expand_message_keys<8>(a, d, slot, tab);
 }
 
+// Both launches in one, for batches of at most one chunk (a single
+// workgroup): Key Expansion, the scan of the messages' counters, the list
+// items and the header.
+__global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArgs a) {
+    __shared__ uint32_t tab[512];
+    __shared__ uint64_t wsum[kPlanCounters][kPlanThreads / 64];
+    for (uint32_t i = threadIdx.x; i < 512; i += kPlanThreads)
+        tab[i] = g_base[i];
+    const uint32_t n = min(batch_count(a), uint32_t(kPlanThreads));
+    const uint32_t m = threadIdx.x;
+    bool valid;
+    int k;
+    uint64_t c[kPlanCounters], total[kPlanCounters];
+    message_counts(a, m, n, valid, k, c);
+    block_exclusive_scan<kPlanCounters>(c, wsum, total);   // its barrier also covers tab[]
+    if (m == 0) {
+        BatchHeader *h = a.header;
+        for (int j = 0; j < 3; j++) {
+            h->nitems[j] = uint32_t(total[j]);
+            h->next[j] = 0;
+        }
+        h->cost[0] = total[3];
+        h->cost[1] = total[4];
+        h->rejected = uint32_t(total[5]);
+    }
+    if (!valid)
+        return;
+    const aes_msg_desc d = a.desc[m];
+    BatchItem it;
+    it.msg = m;
+    it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;
+    it.start = k == 0 ? c[3] : k == 1 ? c[4] : 0;
+    a.items[size_t(k) * a.max_msgs + (k == 0 ? c[0] : k == 1 ? c[1] : c[2])] = it;
+    uint32_t *slot = a.keytab + size_t(m) * kKeySlotWords;
+    if (d.keybits_code == 0)
+        expand_message_keys<4>(a, d, slot, tab);
+    else if (d.keybits_code == 1)
+        expand_message_keys<6>(a, d, slot, tab);
+    else
+        expand_message_keys<8>(a, d, slot, tab);
+}
+
 // The second launch, same chunks: each workgroup adds up the counters of the
 // chunks before it, scans its own messages and writes their list items in
 // message order, each with the cost of the list before it (its start).
@@ -666,16 +708,22 @@ hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists) {
+hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists, int max_count) {
     if (grid < 1 || grid * kBatchWavesPerGroup > kBatchMaxWaves)
         return hipErrorInvalidConfiguration;
-    const int chunks = (a.max_msgs + kPlanThreads - 1) / kPlanThreads;
-    hipLaunchKernelGGL(prep_kernel, dim3(chunks), dim3(kPlanThreads), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(plan_kernel, dim3(chunks), dim3(kPlanThreads), 0, stream, a);
-    e = hipGetLastError();
+    hipError_t e;
+    if (uint64_t(max_count) <= uint64_t(kPlanThreads)) {
+        hipLaunchKernelGGL(prep_plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, a);
+        e = hipGetLastError();
+    } else {
+        const int chunks = (a.max_msgs + kPlanThreads - 1) / kPlanThreads;
+        hipLaunchKernelGGL(prep_kernel, dim3(chunks), dim3(kPlanThreads), 0, stream, a);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(plan_kernel, dim3(chunks), dim3(kPlanThreads), 0, stream, a);
+            e = hipGetLastError();
+        }
+    }
     if (e != hipSuccess || !(lists & 7u))
         return e;
     // the forward kernel also runs the serial list

@@ -191,7 +191,9 @@ hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStr
 hipError_t upload_tables_batch(const HostTables &t);
 // lists: bit k set if list k may hold messages (bit 0 forward, 1 inverse, 2
 // serial); a cipher kernel whose lists are all known to be empty is not
-// launched.  Key Expansion and the plan always run.
-hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists = 7u);
+// launched.  max_count: a bound on the message count known to the caller
+// (at most max_msgs); up to one chunk, Key Expansion and the plan run as one
+// launch.  Key Expansion and the plan always run.
+hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists, int max_count);
 
 }  // namespace aesgpu

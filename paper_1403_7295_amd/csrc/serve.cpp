@@ -172,7 +172,7 @@ struct Loop {
             int st = serve_batch_args(&b, &ka);
             if (st != AES_OK)
                 return st;
-            e = launch_batch(ka, batch_grid, s.stream, lists);
+            e = launch_batch(ka, batch_grid, s.stream, lists, n);
         }
         if (e == hipSuccess)
             e = hipEventRecord(s.event, s.stream);
