@@ -401,19 +401,28 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
     return uint64_t(uniform32(uint32_t(x))) | (uint64_t(uniform32(uint32_t(x >> 32))) << 32);
 }
 
+// A message's round keys into scalar registers: one coalesced load (lane j
+// reads word j) and a lane read per word, instead of one load per word.
+template <int NR>
+__device__ __forceinline__ void load_round_keys(const uint32_t *rkp, uint32_t (&rk)[4 * (NR + 1)]) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t v = lane < 4u * (NR + 1) ? rkp[lane] : 0u;
+#pragma unroll
+    for (int i = 0; i < 4 * (NR + 1); i++)
+        rk[i] = uint32_t(__builtin_amdgcn_readlane(int(v), i));
+}
+
 // Blocks [first, end) of message `msg` through the buffer kernels' block loop.
 template <int NR, int MODE, int DIR, int BPT>
 __device__ __forceinline__ void run_range(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
                                           const aes_msg_desc &d, uint32_t msg, uint64_t first, uint64_t end) {
     // The round keys are the same for the whole wave: read them once per
     // range and keep them in scalar registers.  (The compiler cannot use
-    // scalar loads itself here: the kernel also stores to memory that it
-    // cannot prove distinct from the key table.)
+    // scalar loads here: the kernel also stores to memory that it cannot
+    // prove distinct from the key table.)
     const uint32_t *rkp = a.keytab + size_t(msg) * kKeySlotWords + (DIR == DIR_DEC ? kKeySlotWords / 2 : 0);
     uint32_t rk[4 * (NR + 1)];
-#pragma unroll
-    for (int i = 0; i < 4 * (NR + 1); i++)
-        rk[i] = uniform32(rkp[i]);
+    load_round_keys<NR>(rkp, rk);
     uint32_t ctr[4] = {0, 0, 0, 0};
     if (MODE == MODE_CBC) {
         for (int i = 0; i < 4; i++)
@@ -439,9 +448,7 @@ __device__ __forceinline__ void run_xts_range(const uint32_t *lds, const LaneCon
     const uint32_t *slot = a.keytab + size_t(msg) * kKeySlotWords;
     const uint32_t *rkp = slot + (DIR == DIR_DEC ? kKeySlotWords / 2 : 0);
     uint32_t rk[4 * (NR + 1)];
-#pragma unroll
-    for (int i = 0; i < 4 * (NR + 1); i++)
-        rk[i] = uniform32(rkp[i]);
+    load_round_keys<NR>(rkp, rk);
     const uint32_t *rk2 = slot + (DIR == DIR_DEC ? 0 : kKeySlotWords / 2);   // read once per group
     const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
     uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
