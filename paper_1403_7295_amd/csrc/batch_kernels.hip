@@ -519,8 +519,16 @@ __device__ __forceinline__ uint64_t split_point(uint64_t x, uint64_t start, uint
                                                 uint64_t nblk) {
     if (x <= start)
         return 0;
-    uint64_t b = (x - start + unit - 1) / unit;
-    b = (b + step - 1) / step * step;
+    // unit is block_cost: Nr + 2, so 12, 14 or 16 for a valid descriptor; step
+    // is mostly a power of two: constant divisors and masks instead of a
+    // general 64-bit division
+    const uint64_t v = x - start + unit - 1;
+    uint64_t b = unit == 12 ? v / 12 : unit == 14 ? v / 14 : v / 16;
+    if ((step & (step - 1)) == 0) {
+        b = (b + step - 1) & ~(step - 1);
+    } else {
+        b = (b + step - 1) / step * step;
+    }
     return b < nblk ? b : nblk;
 }
 
