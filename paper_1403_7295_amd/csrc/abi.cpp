@@ -352,8 +352,6 @@ int gcm_crypt(int decrypt, const void *in, void *out, size_t nbytes, const void 
     return AES_OK;
 }
 
-
-
 // Workspace bytes for up to max_msgs messages: header, one key slot and one
 // list entry per message in each of the three lists, the plan's counters
 // per chunk of messages.
@@ -392,11 +390,11 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
     a->in_bytes = b->in_bytes;
     a->out_base = b->out_base;
     a->out_bytes = b->out_bytes;
-    const size_t items = sizeof(BatchHeader) + size_t(b->max_msgs) * kKeySlotWords * 4;
+    const size_t items_off = sizeof(BatchHeader) + size_t(b->max_msgs) * kKeySlotWords * 4;
     a->header = reinterpret_cast<BatchHeader *>(ws);
     a->keytab = reinterpret_cast<uint32_t *>(ws + sizeof(BatchHeader));
-    a->items = reinterpret_cast<BatchItem *>(ws + items);
-    a->chunk_totals = reinterpret_cast<uint64_t *>(ws + items + 3 * size_t(b->max_msgs) * sizeof(BatchItem));
+    a->items = reinterpret_cast<BatchItem *>(ws + items_off);
+    a->chunk_totals = reinterpret_cast<uint64_t *>(ws + items_off + 3 * size_t(b->max_msgs) * sizeof(BatchItem));
     a->split_blocks = uint32_t(b->tile_blocks ? b->tile_blocks : kDefaultSplitBlocks);
     return AES_OK;
 }

@@ -35,9 +35,9 @@
 namespace aesgpu {
 namespace {
 
-// Workgroup size of the prep kernel: four waves, so that its workgroups fit
-// beside a cipher kernel's 16 waves on a compute unit (the request loop runs
-// several batches at once).
+// Workgroup size of the prep and plan kernels, one lane per message of a
+// chunk: four waves, so that their workgroups fit beside a cipher kernel's
+// 16 waves on a compute unit (the request loop runs several batches at once).
 constexpr int kPlanThreads = kBatchChunk;
 
 __device__ __forceinline__ int desc_nr(const aes_msg_desc &d) { return 10 + 2 * int(d.keybits_code); }

@@ -184,8 +184,8 @@ struct FillKArgs {
 hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream);
 // Copies nbytes (a multiple of 16, both pointers 16-byte aligned) from pinned
 // host memory, read through its device address, to device memory, as a
-// kernel on `stream`: the request loop's descriptors then reach the next
-// kernels without a hand-off from the copy engine.
+// kernel on `stream` (the request loop's descriptors for the kernels after
+// it on the same stream).
 hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStream_t stream);
 
 hipError_t upload_tables_batch(const HostTables &t);

@@ -142,8 +142,8 @@ struct Loop {
         h->nmsg = n;
         h->nchunks = chunks;
         // header + descriptors + fill descriptors go up in one copy, made by
-        // a kernel on the slot's stream (a copy-engine transfer would add a
-        // hand-off of tens of microseconds before the next kernel starts)
+        // a kernel on the slot's stream: the next kernels follow it on the
+        // same queue, with no hand-off from the copy engine
         const size_t up = round_up(L.fill_off + size_t(n) * sizeof(FillDesc), 16);
         hipError_t e = launch_stage(s.host_dev, s.dev, up, s.stream);
         FillKArgs fa;
