@@ -35,7 +35,8 @@ def alone(A, q, key, payload):
     x = torch.from_numpy(payload).to("cuda")
     y = torch.empty_like(x)
     fn = A.aes_decrypt if q["decrypt"] else A.aes_encrypt
-    fn(x, y, x.numel(), rk, nr, "ctr", ctr0=q["ctr0"])
+    mode = {0: "ecb", 1: "ctr", 2: "cbc"}[int(q["mode"])]
+    fn(x, y, x.numel(), rk, nr, mode, ctr0=q["ctr0"])
     return y
 
 
@@ -92,3 +93,26 @@ def test_latencies_are_consistent(A):
     assert st["completed"] == 2000
     assert (res["latency_s"] > 0).all() and (res["latency_s"] >= res["admit_s"]).all()
     assert st["bytes_done"] == int(r["nbytes"].sum())
+
+
+def test_mixed_modes_same_alone_and_in_the_mix(A):
+    """ECB and CBC requests in both directions beside CTR ones: batches then
+    use the inverse list (ECB and CBC decryption) and the serial one (CBC
+    encryption) too, each launched only when a batch has such requests."""
+    r, keys = requests(A, 200, rate=1e6, seed=54, hi=1 << 18)
+    rng = np.random.default_rng(54)
+    r["mode"] = rng.choice([0, 1, 2], len(r))
+    r["decrypt"] = rng.integers(0, 2, len(r))
+    whole = r["mode"] != 1
+    r["nbytes"] = np.where(whole, np.maximum(r["nbytes"] // 16 * 16, 16), r["nbytes"])
+    # room for every request, so that no output is overwritten before it is read
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 255) // 256 * 256)
+    cfg = A.serve_cfg(streams=4, budget_bytes=int(fp.sum()) + (1 << 20), max_batch_msgs=16)
+    srv = A.Server(keys, cfg)
+    res, st = srv.run(r)
+    torch.cuda.synchronize()
+    assert st["completed"] == len(r) and st["rejected"] == 0 and st["launches"] > 4
+    for i, q in enumerate(r):
+        n = int(q["nbytes"])
+        payload = seedgen.bytes_np(int(q["payload_seed"]), n)
+        assert torch.equal(srv.output(res[i], n), alone(A, q, keys[i], payload)), "request %d (%s)" % (i, q)
