@@ -263,9 +263,9 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
  * offsets are multiples of 16.  Its key is the first 16/24/32 bytes of the
  * 32-byte slot key_idx of the key array.  ECB and CBC messages are whole
  * blocks; CTR messages may end in a partial block.  ctr0 is the initial
- * counter block (CTR) or the IV (CBC) exactly as for aes_encrypt.  A CBC
- * decryption whose input and output share bytes is rejected; a CBC
- * encryption runs serially on one lane.  XTS messages (whole blocks, as
+ * counter block (CTR) or the IV (CBC) exactly as for aes_encrypt.  Input
+ * and output are the same bytes or disjoint (CBC decryption: disjoint), else
+ * the message is rejected; a CBC encryption runs serially on one lane.  XTS messages (whole blocks, as
  * aes_xts_encrypt) use key_idx for the data key and ctr0 for the rest, all
  * little-endian: bytes 0..7 the tweak value of the message's first data
  * unit, 8..11 the key slot of the tweak key (same key size), 12..15 the
@@ -308,7 +308,8 @@ typedef struct {
  * persistent kernels, one workgroup per compute unit, in which every wave
  * runs its share.  A message with an invalid descriptor (bad key code or
  * mode, ECB length not a multiple of 16, misaligned offset, outside the
- * buffers, key_idx >= nkeys) is skipped and counted (aes_batch_query).
+ * buffers, input and output partly overlapping, key_idx >= nkeys) is
+ * skipped and counted (aes_batch_query).
  */
 typedef struct {
     const aes_msg_desc *desc;

@@ -69,10 +69,13 @@ __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKAr
         if (u < 16 || u > 4096 || (u & (u - 1)) != 0 || xts_key2(d) >= uint32_t(a.nkeys))
             return false;
     }
-    // CBC decryption reads block j-1 of the input after other waves may have
-    // written their outputs: input and output must not share bytes
-    if (d.mode == AES_MODE_CBC && d.decrypt && a.in_base == a.out_base && d.nbytes &&
-        d.in_off < d.out_off + d.nbytes && d.out_off < d.in_off + d.nbytes)
+    // Input and output are the same bytes or disjoint (waves of one message
+    // would race otherwise); for CBC decryption disjoint, as it reads block
+    // j-1 of the input after other waves may have written their outputs.
+    const uintptr_t ip = reinterpret_cast<uintptr_t>(a.in_base) + d.in_off;
+    const uintptr_t op = reinterpret_cast<uintptr_t>(a.out_base) + d.out_off;
+    const bool overlap = d.nbytes && ip < op + d.nbytes && op < ip + d.nbytes;
+    if (overlap && (ip != op || (d.mode == AES_MODE_CBC && d.decrypt)))
         return false;
     // a CBC encryption runs on one lane; its block count must fit the list item
     if (d.mode == AES_MODE_CBC && !d.decrypt && (d.nbytes >> 4) >= 0xFFFFFFFFull)

@@ -263,6 +263,21 @@ def test_cbc_in_place_decryption_is_rejected(A, O):
     assert np.array_equal(xd.cpu().numpy(), x)
 
 
+def test_partly_overlapping_messages_are_rejected(A, O):
+    """In one buffer, a message whose output starts one block after its
+    input is rejected; one that runs in place (CBC decryption aside) is not."""
+    descs, keys = mixed_messages(A, 12, 55, min_len=64, modes=3)
+    x, xd, _ = buffers(descs, 55)
+    shifted = descs.copy()
+    shifted["out_off"][:6] += 16
+    shifted["nbytes"][:6] = np.minimum(shifted["nbytes"][:6], descs["nbytes"][:6] - 16) // 16 * 16
+    cbc_in_place = (shifted["mode"] == 2) & (shifted["decrypt"] == 1)
+    b = A.Batch(shifted, keys, xd, xd)
+    b.run()
+    planned, rejected = b.query()
+    assert rejected == 6 + int(cbc_in_place[6:].sum()) and planned == 12 - rejected
+
+
 def test_many_serial_cbc_messages(A, O):
     # more CBC-encrypt messages than one wave takes (64, one per lane), with
     # parallel work mixed in
