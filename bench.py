@@ -135,11 +135,48 @@ def cpu_baseline(sample_bytes):
         secs.append(s)
     secs.sort()
     s = secs[len(secs) // 2]
+    # one thread on an eighth of the sample: the per-core figure (Table I's last column)
+    one_bytes = max(sample_bytes // 8, 1 << 20)
+    one = sorted(o.par_run(0, rk, nr, x[:one_bytes], 1)[1] for _ in range(3))[1]
     return {"value": round(sample_bytes / s / 1e9, 5), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": "AES-128 ECB encrypt of the first %d MiB of the same seeded input, "
                       "%d pthreads (contiguous whole-block chunks), median of 3 runs, %.2f s each"
-                      % (sample_bytes >> 20, threads, s)}
+                      % (sample_bytes >> 20, threads, s),
+            "single_thread_GB/s": round(one_bytes / one / 1e9, 5),
+            "single_thread_sample": "the first %d MiB, 1 thread, median of 3 runs, %.2f s each"
+                                    % (one_bytes >> 20, one)}
+
+
+LDS_GATHER_ROUNDS = 4096
+
+
+def bench_lds_gather(torch, A, dev, stream, rounds=LDS_GATHER_ROUNDS, steps=20, warmup=3):
+    """The LDS calibration kernel in the cipher's launch shape: the 32-bit,
+    own-bank lookups per second the LDS accepts with no global memory traffic
+    and the cipher's VALU cost per lookup, and the engine clock it ran at
+    (cycle counter over the constant-rate clock, per wave)."""
+    waves = torch.cuda.get_device_properties(dev).multi_processor_count * 16
+    rec = torch.zeros(waves * 3, dtype=torch.int64, device=dev)
+    got = {}
+
+    def launch():
+        got["waves"], got["khz"] = A.aes_lds_gather(rec, rounds, stream=stream)
+
+    _, k = timed_launches(torch, stream, launch, steps, warmup)
+    w = got["waves"]
+    lookups = w * 64 * 16 * rounds
+    r = rec.view(-1, 3)[:w].cpu().double()
+    cycles, ticks = float(r[:, 0].mean()), float(r[:, 1].mean())
+    clock = cycles / (ticks / (got["khz"] * 1e3)) / 1e9 if ticks > 0 and got["khz"] > 0 else None
+    if clock is not None and not 0.5 < clock < 3.5:
+        clock = None    # the cycle counter does not count engine clocks here
+    rate = lookups / k / 1e12
+    out = {"Tlookup/s": round(rate, 3), "kernel_us": round(k * 1e6, 1), "lookups_per_launch": lookups,
+           "waves": w, "clock_GHz": round(clock, 3) if clock else None}
+    if clock:
+        out["lookups_per_clk_per_cu"] = round(rate * 1e12 / (w / 16) / (clock * 1e9), 2)
+    return out
 
 
 def bench_size_sweep(torch, A, dev, stream, sizes=(1 << 20, 1 << 22, 1 << 24, 1 << 26, 1 << 28, 1 << 30, 1 << 32)):
@@ -231,7 +268,7 @@ def bench_sector_batch(torch, A, dev, stream, nmsg=65536, size=4096, reps=5):
 
 
 def bench_served(torch, A, dev, capacity_gbs, nreq, warm=1000,
-                 loads=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
+                 loads=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
     """The served workload: Poisson arrivals of CTR requests (70 % encrypt,
     30 % decrypt), sizes log-uniform in [64 B, 64 MiB], AES-128/256 half and
     half, each with its own key and nonce, admitted against an 8 GiB HBM
@@ -265,12 +302,22 @@ def bench_served(torch, A, dev, capacity_gbs, nreq, warm=1000,
                        "p99_ms": round(float(np.percentile(m["latency_s"], 99)) * 1e3, 3),
                        "p50_admit_wait_ms": round(float(np.percentile(m["admit_s"], 50)) * 1e3, 3),
                        "launches": st["launches"], "max_inflight_reqs": st["max_inflight_reqs"]})
+    # the loop's own ceiling: every request 64 bytes and already waiting, so
+    # admission, planning and completion are all there is to do
+    r = base.copy()
+    r["arrival_s"] = 0.0
+    r["nbytes"] = 64
+    res, st = srv.run(r)
+    span = float(res["latency_s"].max())
+    loop_rate = {"requests": len(r), "request_bytes": 64, "req_per_s": round(len(r) / span, 1),
+                 "launches": st["launches"], "not_ok": int((res["status"] != 0).sum())}
     del srv
     torch.cuda.empty_cache()
     return {"workload": "Poisson CTR requests, 70/30 encrypt/decrypt, log-uniform 64 B..64 MiB, "
                         "AES-128/256 50/50, per-request key and nonce, 8 GiB HBM budget, 4 streams",
             "requests_per_point": nreq, "warmup_requests": warm,
-            "capacity_GB/s": round(capacity_gbs, 1), "points": points}
+            "capacity_GB/s": round(capacity_gbs, 1), "points": points,
+            "max_admitted": loop_rate}
 
 
 def main():
@@ -317,6 +364,13 @@ def main():
                   "frac": round(issue_achieved / LDS_PEAK_TLOOKUPS, 4), "traffic": traffic,
                   "note": "LDS table lookups (16 per round per block); peak = 256 CUs x 2.4 GHz "
                           "x 32 lanes per clock"}
+    # the lookup rate the LDS accepts on this device, measured right after
+    lds = bench_lds_gather(torch, A, dev, stream)
+    roof_issue["measured_peak"] = lds["Tlookup/s"]
+    roof_issue["frac_of_measured"] = round(issue_achieved / lds["Tlookup/s"], 4)
+    roof_issue["measured_peak_note"] = ("the LDS calibration kernel in the same run: the cipher's lookup "
+                                        "instructions without global memory, round keys or round-to-round "
+                                        "dependence")
     binding = roof_issue if roof_issue["frac"] >= roof_hbm["frac"] else roof_hbm
 
     out = {
@@ -341,6 +395,7 @@ def main():
         "roofline": binding,
         "roofline_hbm": roof_hbm,
         "roofline_issue": roof_issue,
+        "lds_gather": lds,
     }
 
     if not args.no_secondary:

@@ -251,6 +251,31 @@ int aes_get_launch(size_t nbytes, int mode, int decrypt, int Nr, aes_launch *cfg
  */
 int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
 
+/*
+ * Measurement helper (not part of the cipher): the LDS lookup rate the table
+ * kernels are compared with.  Launches the cipher's shape (one 1024-thread
+ * workgroup per compute unit, 128 KiB of LDS) with every lane reading 32-bit
+ * words from its own LDS bank, 16 reads per round for `rounds` rounds, and no
+ * global memory traffic.  Each wave writes one record to `out` (device
+ * memory, caller-owned): the engine clock cycles (s_memtime) and the
+ * constant-rate clock ticks (s_memrealtime) its loop took, and a fold of the
+ * words it read.  Lookups per launch = waves x 64 x 16 x rounds, waves =
+ * compute units x 16; *waves receives that count and *tick_khz the rate of
+ * the constant-rate clock (hipDeviceAttributeWallClockRate), both set before
+ * the size check.  out_bytes must hold waves records.
+ * Errors: AES_E_NULL, AES_E_ARG (rounds < 1), AES_E_LENGTH (out_bytes too
+ * small), AES_E_DEVICE.
+ */
+typedef struct {
+    uint64_t cycles;    /* engine clock cycles of the wave's loop       */
+    uint64_t ticks;     /* constant-rate clock ticks of the same loop    */
+    uint32_t fold;      /* XOR of every word the wave read               */
+    uint32_t pad;
+} aes_lds_gather_stat;
+
+int aes_lds_gather(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int *waves, int *tick_khz,
+                   void *stream);
+
 
 /* ---------------------------------------------------------------------- */
 /* Batches: many independent messages, each with its own key, length and  */

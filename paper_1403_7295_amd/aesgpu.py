@@ -66,6 +66,9 @@ _SIGNATURES = {
     "aes_set_tuned": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "aes_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                 ctypes.c_void_p]),
+    "aes_lds_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.c_void_p]),
     "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "aes_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "aes_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
@@ -330,6 +333,18 @@ def aes_copy(inp, out, nbytes=None, stream=None):
         nbytes = inp.numel() * inp.element_size()
     _check(lib.aes_copy(_dptr(inp), _dptr(out), nbytes, _stream_handle(stream, inp)))
     return out
+
+
+LDS_GATHER_RECORD_BYTES = 24   # aes_lds_gather_stat: cycles, ticks (uint64), fold, pad (uint32)
+
+
+def aes_lds_gather(out, rounds, stream=None):
+    """Runs the LDS gather calibration kernel; `out` is a device tensor holding
+    one 24-byte record per wave.  Returns (waves, constant-rate clock in kHz)."""
+    waves, khz = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib.aes_lds_gather(_dptr(out), out.numel() * out.element_size(), int(rounds),
+                              ctypes.byref(waves), ctypes.byref(khz), _stream_handle(stream, out)))
+    return waves.value, khz.value
 
 
 # --- conveniences on top of the calls above (allocation through torch) ----

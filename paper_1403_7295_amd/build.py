@@ -15,8 +15,8 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libaesgpu.so")
 ARCH = "gfx950"
 
-SOURCES = ("aes_kernels.hip", "batch_kernels.hip", "bitslice.hip", "xts.hip", "gcm.hip", "tables.cpp", "abi.cpp",
-           "serve.cpp")
+SOURCES = ("aes_kernels.hip", "batch_kernels.hip", "bitslice.hip", "xts.hip", "gcm.hip", "lds_gather.hip",
+           "tables.cpp", "abi.cpp", "serve.cpp")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

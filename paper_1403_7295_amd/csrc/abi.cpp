@@ -537,6 +537,32 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream) {
     return AES_OK;
 }
 
+int aes_lds_gather(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int *waves, int *tick_khz,
+                   void *stream) {
+    if (!out || !waves || !tick_khz)
+        return fail(AES_E_NULL, "out, waves and tick_khz must not be NULL");
+    if (rounds < 1)
+        return fail(AES_E_ARG, "need rounds >= 1");
+    int st = AES_OK;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+    int dev = 0;
+    hipError_t a = hipGetDevice(&dev);
+    if (a == hipSuccess)
+        a = hipDeviceGetAttribute(tick_khz, hipDeviceAttributeWallClockRate, dev);
+    if (a != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("wall clock rate: ") + hipGetErrorString(a));
+    const int nw = d->cus * kLdsGatherWavesPerGroup;
+    *waves = nw;
+    if (out_bytes < size_t(nw) * sizeof(aes_lds_gather_stat))
+        return fail(AES_E_LENGTH, "out must hold one record per wave (" + std::to_string(nw) + " waves)");
+    hipError_t e = launch_lds_gather(out, uint32_t(rounds), d->cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
 int aes_batch_workspace_size(int max_msgs, size_t *bytes) {
     if (!bytes)
         return fail(AES_E_NULL, "bytes must not be NULL");

@@ -55,6 +55,11 @@ hipError_t upload_tables(const HostTables &t);
 hipError_t launch_cipher(int nr, int mode, int dir, const LaunchCfg &cfg, const CipherArgs &a,
                          hipStream_t stream);
 hipError_t launch_copy(const void *in, void *out, uint64_t nbytes, int grid, hipStream_t stream);
+// The LDS gather calibration kernel (lds_gather.hip): grid workgroups of 16 waves.
+using LdsGatherStat = aes_lds_gather_stat;
+constexpr int kLdsGatherWavesPerGroup = 16;
+uint32_t lds_gather_reads_per_round();
+hipError_t launch_lds_gather(LdsGatherStat *out, uint32_t rounds, int grid, hipStream_t stream);
 // CBC encryption is serial: one lane walks the whole buffer.
 hipError_t launch_cbc_encrypt(int nr, const CipherArgs &a, hipStream_t stream);
 // The bitsliced comparison kernel (bitslice.hip): encryption only.

@@ -183,6 +183,53 @@ def test_copy_helper(A):
     assert torch.equal(x, y)
 
 
+def lds_gather_folds(blocks, rounds):
+    """What each workgroup of the LDS calibration kernel must report: word i
+    of the LDS holds i * 0x9E3779B1; lane l of workgroup b starts column word
+    c at (l + 64 c + 1) * 0x9E3779B1 ^ b, adds 0x3B5D7F91 + c per round and
+    reads, in table K, entry byte K of that word, copy l & 31; the wave's
+    fold is the XOR of every word read and of the lane numbers."""
+    m = np.uint64(0xFFFFFFFF)
+    phi = np.uint64(0x9E3779B1)
+    lane = np.arange(64, dtype=np.uint64)[None, :]
+    b = np.arange(blocks, dtype=np.uint64)[:, None]
+    lc = [((lane & np.uint64(31)) << np.uint64(2)) | np.uint64((t & 1) << 7) | np.uint64((t >> 1) << 16)
+          for t in range(4)]
+    w = [(((lane + np.uint64(64 * c + 1)) * phi) & m) ^ b for c in range(4)]
+    acc = np.zeros((blocks, 64), np.uint64)
+    for _ in range(rounds):
+        for c in range(4):
+            w[c] = (w[c] + np.uint64(0x3B5D7F91 + c)) & m
+            for k in range(4):
+                addr = lc[k] | (((w[c] >> np.uint64(8 * k)) & np.uint64(0xFF)) << np.uint64(8))
+                acc ^= ((addr >> np.uint64(2)) * phi) & m
+    acc ^= lane
+    return np.bitwise_xor.reduce(acc, axis=1)
+
+
+def test_lds_gather_helper(A):
+    """The LDS calibration kernel: one record per wave, both clocks advance,
+    and every wave's fold of the words it read is the one computed here."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    waves = cus * 16
+    rounds = 64
+    rec = torch.full((waves * 3,), -1, dtype=torch.int64, device="cuda")
+    w, khz = A.aes_lds_gather(rec, rounds)
+    torch.cuda.synchronize()
+    assert w == waves and khz > 0
+    r = rec.view(-1, 3).cpu().numpy()
+    assert (r[:, 0] > 0).all() and (r[:, 1] > 0).all()
+    fold = r[:, 2].astype(np.uint64)
+    expect = np.repeat(lds_gather_folds(cus, rounds), 16)     # 16 waves per workgroup read alike
+    assert np.array_equal(fold, expect)                         # fold in the low word, pad (0) above
+    with pytest.raises(A.AESError) as e:
+        A.aes_lds_gather(rec[:3], rounds)
+    assert e.value.code == A.AES_E_LENGTH
+    with pytest.raises(A.AESError) as e:
+        A.aes_lds_gather(rec, 0)
+    assert e.value.code == A.AES_E_ARG
+
+
 def test_device_generator_matches_host(A):
     for n in (1, 1000, (1 << 22) + 5):
         d = seedgen.data_torch(9, 1, n, "cuda").cpu().numpy()
