@@ -429,21 +429,45 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
 
 // CBC encryption of one whole message by one lane (each block depends on the
 // previous ciphertext, SP 800-38A section 6.2).  rk holds this lane's round
-// keys (registers), iv the initial chaining value.
+// keys (registers), iv the initial chaining value.  The chain is serial but
+// the plaintext is not: blocks are read a group of kCbcGroup ahead, so a
+// group's loads are in flight while the previous group is enciphered and
+// neither the read latency nor the completion of the last store stalls a
+// block.
+constexpr int kCbcGroup = 4;
+
 template <int NR, int LAYOUT>
 __device__ __forceinline__ void cbc_encrypt_serial(const uint32_t *lds, const LaneConsts &lc,
                                                    const uint32_t *rk, const uint32_t *iv,
                                                    const uint8_t *in, uint8_t *out, uint64_t nblocks) {
     uint32_t c0 = iv[0], c1 = iv[1], c2 = iv[2], c3 = iv[3];
-    for (uint64_t j = 0; j < nblocks; j++) {
-        const u32x4 x = *reinterpret_cast<const u32x4 *>(in + 16 * j);
-        uint32_t s[1][4] = {{x.x ^ c0 ^ rk[0], x.y ^ c1 ^ rk[1], x.z ^ c2 ^ rk[2], x.w ^ c3 ^ rk[3]}};
-        rounds<NR, DIR_ENC, LAYOUT, 1>(s, lds, lc, rk, 1);
-        c0 = s[0][0];
-        c1 = s[0][1];
-        c2 = s[0][2];
-        c3 = s[0][3];
-        *reinterpret_cast<u32x4 *>(out + 16 * j) = vec4(c0, c1, c2, c3);
+    u32x4 cur[kCbcGroup];
+#pragma unroll
+    for (int i = 0; i < kCbcGroup; i++)
+        cur[i] = uint64_t(i) < nblocks ? *reinterpret_cast<const u32x4 *>(in + 16 * i) : vec4(0, 0, 0, 0);
+    for (uint64_t g = 0; g < nblocks; g += kCbcGroup) {
+        u32x4 nxt[kCbcGroup];
+#pragma unroll
+        for (int i = 0; i < kCbcGroup; i++) {
+            const uint64_t j = g + kCbcGroup + i;
+            nxt[i] = j < nblocks ? *reinterpret_cast<const u32x4 *>(in + 16 * j) : vec4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < kCbcGroup; i++) {
+            if (g + i < nblocks) {
+                const u32x4 x = cur[i];
+                uint32_t st[1][4] = {{x.x ^ c0 ^ rk[0], x.y ^ c1 ^ rk[1], x.z ^ c2 ^ rk[2], x.w ^ c3 ^ rk[3]}};
+                rounds<NR, DIR_ENC, LAYOUT, 1>(st, lds, lc, rk, 1);
+                c0 = st[0][0];
+                c1 = st[0][1];
+                c2 = st[0][2];
+                c3 = st[0][3];
+                *reinterpret_cast<u32x4 *>(out + 16 * (g + i)) = vec4(c0, c1, c2, c3);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kCbcGroup; i++)
+            cur[i] = nxt[i];
     }
 }
 
