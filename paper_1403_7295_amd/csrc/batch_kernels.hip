@@ -143,7 +143,7 @@ __device__ __forceinline__ uint32_t inv_mix_column(const uint32_t *tab, uint32_t
 
 // Key Expansion (FIPS-197 section 5.2) of the Nk-word key at `key`, fully
 // unrolled: each word w[i], i = 0 .. 4Nr+3, is handed to emit(i, w[i]) as
-// soon as it exists, so only the last Nk words stay live in registers.
+// soon as it exists (only the last Nk words are needed to go on).
 template <int NK, typename Emit>
 __device__ __forceinline__ void expand_key(const uint8_t *key, const uint32_t *tab, Emit emit) {
     uint32_t w[4 * (NK + 7)];
@@ -171,27 +171,39 @@ __device__ __forceinline__ void expand_key(const uint8_t *key, const uint32_t *t
 // list the equivalent-inverse schedule (section 5.3.5) at kKeySlotWords / 2,
 // whose round r is InvMixColumns of encryption round Nr - r (rounds 0 and Nr
 // swapped, unmixed); for XTS the tweak key's encryption schedule in the half
-// the data key's direction leaves free.
+// the data key's direction leaves free.  A lane expands its message's key
+// into registers and stores each round key as one 16-byte write (the slot
+// is 512-byte aligned): each lane writes a slot of its own, so word-sized
+// stores would each touch a different cache line for every lane.
+template <int NK>
+__device__ __forceinline__ void store_schedule(uint32_t *dst, const uint32_t (&w)[4 * (NK + 7)]) {
+#pragma unroll
+    for (int r = 0; r <= NK + 6; r++)
+        reinterpret_cast<u32x4 *>(dst)[r] = vec4(w[4 * r], w[4 * r + 1], w[4 * r + 2], w[4 * r + 3]);
+}
+
 template <int NK>
 __device__ __forceinline__ void expand_message_keys(const BatchKArgs &a, const aes_msg_desc &d, uint32_t *slot,
                                                     const uint32_t *tab) {
     constexpr int NR = NK + 6;
-    const bool inverse = desc_class(d) == 1;
-    uint32_t *dk = slot + kKeySlotWords / 2;
-    expand_key<NK>(a.keys + size_t(d.key_idx) * 32, tab, [&](int i, uint32_t v) {
-        slot[i] = v;
-        if (inverse) {
-            if (i < 4)
-                dk[4 * NR + i] = v;
-            else if (i >= 4 * NR)
-                dk[i - 4 * NR] = v;
-            else
-                dk[4 * (NR - i / 4) + (i & 3)] = inv_mix_column(tab, v);
+    uint32_t w[4 * (NR + 1)];
+    expand_key<NK>(a.keys + size_t(d.key_idx) * 32, tab, [&](int i, uint32_t v) { w[i] = v; });
+    store_schedule<NK>(slot, w);
+    if (desc_class(d) == 1) {
+        u32x4 *dk = reinterpret_cast<u32x4 *>(slot + kKeySlotWords / 2);
+        dk[0] = vec4(w[4 * NR], w[4 * NR + 1], w[4 * NR + 2], w[4 * NR + 3]);
+#pragma unroll
+        for (int r = 1; r < NR; r++) {
+            const int e = 4 * (NR - r);
+            dk[r] = vec4(inv_mix_column(tab, w[e]), inv_mix_column(tab, w[e + 1]), inv_mix_column(tab, w[e + 2]),
+                         inv_mix_column(tab, w[e + 3]));
         }
-    });
+        dk[NR] = vec4(w[0], w[1], w[2], w[3]);
+    }
     if (d.mode == AES_MODE_XTS) {
-        uint32_t *o = slot + (d.decrypt ? 0 : kKeySlotWords / 2);
-        expand_key<NK>(a.keys + size_t(xts_key2(d)) * 32, tab, [&](int i, uint32_t v) { o[i] = v; });
+        uint32_t w2[4 * (NR + 1)];
+        expand_key<NK>(a.keys + size_t(xts_key2(d)) * 32, tab, [&](int i, uint32_t v) { w2[i] = v; });
+        store_schedule<NK>(slot + (d.decrypt ? 0 : kKeySlotWords / 2), w2);
     }
 }
 
