@@ -34,17 +34,23 @@ __device__ __forceinline__ void xts_group(const uint32_t *lds, const LaneConsts 
                                           const uint32_t *rk2, const uint8_t *in, uint8_t *out, uint64_t gb0,
                                           uint64_t gb1, uint64_t unit0, uint32_t ushift) {
     const uint32_t lane = threadIdx.x & 63u;
-    // the tweak of unit unit0 + lane: Cipher_K2 of the unit number, little-endian
+    // the tweak of unit unit0 + lane: Cipher_K2 of the unit number, little-endian;
+    // only lanes that own one of the group's units compute it (a batch of
+    // one-unit messages has one per group, and inactive lanes cost the LDS
+    // and the vector memory path nothing); the others' tweaks are never used
     const uint64_t unit = unit0 + lane;
+    const uint32_t units = uint32_t((gb1 - gb0 + (uint64_t(1) << ushift) - 1) >> ushift);
     uint32_t tw[4] = {uint32_t(unit), uint32_t(unit >> 32), 0u, 0u};
-    if (DIR == DIR_ENC) {
-        uint32_t t1[1][4] = {{tw[0] ^ rk2[0], tw[1] ^ rk2[1], rk2[2], rk2[3]}};
-        rounds<NR, DIR_ENC, LAYOUT_T4X32, 1>(t1, lds, lc, rk2, 1);
+    if (lane < units) {
+        if (DIR == DIR_ENC) {
+            uint32_t t1[1][4] = {{tw[0] ^ rk2[0], tw[1] ^ rk2[1], rk2[2], rk2[3]}};
+            rounds<NR, DIR_ENC, LAYOUT_T4X32, 1>(t1, lds, lc, rk2, 1);
 #pragma unroll
-        for (int c = 0; c < 4; c++)
-            tw[c] = t1[0][c];
-    } else {
-        encrypt_global<NR>(rk2, tw);
+            for (int c = 0; c < 4; c++)
+                tw[c] = t1[0][c];
+        } else {
+            encrypt_global<NR>(rk2, tw);
+        }
     }
     for (uint64_t base = gb0; base < gb1; base += 64u * BPT) {
         const uint32_t nwhole = uint32_t(min<uint64_t>(gb1 - base, 64u * BPT));
