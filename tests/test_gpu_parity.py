@@ -358,7 +358,8 @@ def test_cbc_decrypt_matches_oracle(A, O, bits, nbytes):
 
 
 @pytest.mark.parametrize("bits", [128, 256])
-@pytest.mark.parametrize("nbytes", [16, 48, 4096, 1 << 18])
+# 1, 3, 5, 7 blocks: partial groups of the four blocks read ahead, first and later
+@pytest.mark.parametrize("nbytes", [16, 48, 80, 112, 4096, 1 << 18])
 def test_cbc_encrypt_matches_oracle(A, O, bits, nbytes):
     seed = 8000 + bits + nbytes
     rk, nr = A.aes_expand_key(seedgen.key(13, seed, bits))
