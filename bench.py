@@ -154,8 +154,8 @@ LDS_GATHER_ROUNDS = 4096
 def bench_lds_gather(torch, A, dev, stream, rounds=LDS_GATHER_ROUNDS, steps=20, warmup=3):
     """The LDS calibration kernel in the cipher's launch shape: the 32-bit,
     own-bank lookups per second the LDS accepts with no global memory traffic
-    and the cipher's VALU cost per lookup, and the engine clock it ran at
-    (cycle counter over the constant-rate clock, per wave)."""
+    and the cipher's VALU cost per lookup, and the rate of the cycle counter
+    its waves read (s_memtime over the constant-rate s_memrealtime)."""
     waves = torch.cuda.get_device_properties(dev).multi_processor_count * 16
     rec = torch.zeros(waves * 3, dtype=torch.int64, device=dev)
     got = {}
@@ -173,9 +173,9 @@ def bench_lds_gather(torch, A, dev, stream, rounds=LDS_GATHER_ROUNDS, steps=20, 
         clock = None    # the cycle counter does not count engine clocks here
     rate = lookups / k / 1e12
     out = {"Tlookup/s": round(rate, 3), "kernel_us": round(k * 1e6, 1), "lookups_per_launch": lookups,
-           "waves": w, "clock_GHz": round(clock, 3) if clock else None}
+           "waves": w, "counter_clock_GHz": round(clock, 3) if clock else None}
     if clock:
-        out["lookups_per_clk_per_cu"] = round(rate * 1e12 / (w / 16) / (clock * 1e9), 2)
+        out["lookups_per_counter_clk_per_cu"] = round(rate * 1e12 / (w / 16) / (clock * 1e9), 2)
     return out
 
 
