@@ -257,7 +257,7 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
  * workgroup per compute unit, 128 KiB of LDS) with every lane reading 32-bit
  * words from its own LDS bank, 16 reads per round for `rounds` rounds, and no
  * global memory traffic.  Each wave writes one record to `out` (device
- * memory, caller-owned): the engine clock cycles (s_memtime) and the
+ * memory, caller-owned): the cycle-counter delta (s_memtime) and the
  * constant-rate clock ticks (s_memrealtime) its loop took, and a fold of the
  * words it read.  Lookups per launch = waves x 64 x 16 x rounds, waves =
  * compute units x 16; *waves receives that count and *tick_khz the rate of
@@ -267,7 +267,7 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream);
  * small), AES_E_DEVICE.
  */
 typedef struct {
-    uint64_t cycles;    /* engine clock cycles of the wave's loop       */
+    uint64_t cycles;    /* cycle-counter delta of the wave's loop       */
     uint64_t ticks;     /* constant-rate clock ticks of the same loop    */
     uint32_t fold;      /* XOR of every word the wave read               */
     uint32_t pad;

@@ -16,9 +16,9 @@
 // words advance by a constant each round instead, so the loop measures what
 // the LDS accepts rather than how well the cipher hides its latency.
 //
-// Each wave also reads the engine cycle counter (s_memtime) and the
-// constant-rate wall clock (s_memrealtime) around its loop; from the two
-// deltas the host derives the clock the LDS ran at.
+// Each wave also reads the cycle counter (s_memtime) and the constant-rate
+// wall clock (s_memrealtime) around its loop; the host reports the ratio of
+// the two deltas as the counter's rate.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
