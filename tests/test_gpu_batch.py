@@ -348,3 +348,44 @@ def test_xts_sector_batch_equals_plain(A, O, decrypt):
     assert torch.equal(yd, zd)
     y = yd.cpu().numpy()
     check_against_oracle(O, descs[::97], keys, x, y)
+
+
+def test_sector_batch_full_size_sampled(A, O):
+    """The 4 KiB sector workload at its full size and in the graph launch
+    the benchmark times: 65,536 messages, each with its own AES-128 key and
+    IV (XTS: its own key pair, one 4 KiB data unit).  CBC encryption and XTS
+    encryption are compared with the oracle on 128 sampled messages; CBC
+    decryption of the whole CBC output must give back the input."""
+    nmsg, size = 65536, 4096
+    rng = np.random.default_rng(6)
+    keys = np.zeros((2 * nmsg, 32), np.uint8)
+    keys[:, :16] = rng.integers(0, 256, (2 * nmsg, 16), dtype=np.uint8)
+    ivs = rng.integers(0, 256, (nmsg, 16), dtype=np.uint8)
+    xts = np.stack([A.xts_ctr0(m, nmsg + m, size) for m in range(nmsg)])
+    x = seedgen.data_torch(6, 0, nmsg * size, "cuda")
+    idx = np.sort(np.random.default_rng(61).choice(nmsg, 128, replace=False))
+    rows = torch.from_numpy(idx).cuda()
+    xs = x.view(nmsg, size)[rows].cpu().numpy()
+
+    def run(descs, src):
+        out = torch.full_like(src, SENTINEL)
+        b = A.Batch(descs, keys, src, out)
+        b.launch_graph()
+        torch.cuda.synchronize()
+        assert b.query() == (nmsg, 0)
+        b.close()
+        return out
+
+    cbc = A.make_descs(np.full(nmsg, size), keybits=128, mode="cbc", decrypt=0, ctr0=ivs)
+    y = run(cbc, x)
+    ys = y.view(nmsg, size)[rows].cpu().numpy()
+    for j, m in enumerate(idx):
+        assert np.array_equal(ys[j], oracle_message(O, cbc[m], keys, xs[j])), ("CBC encrypt", m)
+    z = run(A.make_descs(np.full(nmsg, size), keybits=128, mode="cbc", decrypt=1, ctr0=ivs), y)
+    assert torch.equal(z, x)
+    del z
+    xd = A.make_descs(np.full(nmsg, size), keybits=128, mode="xts", decrypt=0, ctr0=xts)
+    w = run(xd, x)
+    ws = w.view(nmsg, size)[rows].cpu().numpy()
+    for j, m in enumerate(idx):
+        assert np.array_equal(ws[j], oracle_message(O, xd[m], keys, xs[j])), ("XTS encrypt", m)
