@@ -765,7 +765,6 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
             return e;
     }
     if (lists & 2u) {
-        // two blocks per thread: four spill with the inverse tables' registers
         hipLaunchKernelGGL((batch_kernel<1, 4>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
         e = hipGetLastError();
     }
