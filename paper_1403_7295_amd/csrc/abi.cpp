@@ -122,11 +122,11 @@ LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes, int mode, int dec
     c.bpt = set && o.blocks_per_thread ? o.blocks_per_thread : 2;
     c.wg = set && o.wg_size ? o.wg_size : 1024;
     if (c.layout == LAYOUT_BITSLICED) {
-        // 256-thread workgroups (one wave per SIMD), one per CU; each lane
+        // 256-thread workgroups, two per CU (two waves per SIMD); each lane
         // carries 32 blocks
         c.bpt = 32;
         c.wg = 256;
-        uint64_t grid = set && o.grid ? uint64_t(o.grid) : uint64_t(d.cus);
+        uint64_t grid = set && o.grid ? uint64_t(o.grid) : 2 * uint64_t(d.cus);
         const uint64_t useful = ((nbytes + 15) / 16 + 256 * 32 - 1) / (256 * 32);
         if (!(set && o.grid) && useful < grid)
             grid = useful;

@@ -84,6 +84,14 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
             a[k] ^= t << j;
         }
     }
+#pragma unroll
+    for (int k = 0; k < 32; k++)
+        asm volatile("" : "+v"(a[k]));
+}
+
+// One 4-byte word of the input, streamed like the 16-byte loads.
+__device__ __forceinline__ uint32_t load4(const uint8_t *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p));
 }
 
 // Plane index of bit k of row r, column c.
@@ -103,9 +111,12 @@ __device__ __forceinline__ void sub_bytes(uint32_t (&st)[128]) {
 #pragma unroll
     for (int c = 0; c < 4; c++)
 #pragma unroll
-        for (int r = 0; r < 4; r++)
+        for (int r = 0; r < 4; r++) {
             sbox_circuit(st[P(c, r, 7)], st[P(c, r, 6)], st[P(c, r, 5)], st[P(c, r, 4)], st[P(c, r, 3)],
                          st[P(c, r, 2)], st[P(c, r, 1)], st[P(c, r, 0)]);
+            asm volatile("" : "+v"(st[P(c, r, 7)]), "+v"(st[P(c, r, 6)]), "+v"(st[P(c, r, 5)]), "+v"(st[P(c, r, 4)]),
+                              "+v"(st[P(c, r, 3)]), "+v"(st[P(c, r, 2)]), "+v"(st[P(c, r, 1)]), "+v"(st[P(c, r, 0)]));
+        }
 }
 
 // ShiftRows and MixColumns, in place.  Output column c takes row r from
@@ -140,8 +151,10 @@ __device__ __forceinline__ void shift_mix(uint32_t (&st)[128]) {
 #pragma unroll
             for (int r = 0; r < 4; r++)
 #pragma unroll
-                for (int k = 0; k < 8; k++)
+                for (int k = 0; k < 8; k++) {
                     st[P((c + r) & 3, r, k)] = o[r][k];
+                    asm volatile("" : "+v"(st[P((c + r) & 3, r, k)]));
+                }
         }
     }
     // ShiftRows as a renaming: row r of column c now comes from column c + r
@@ -175,13 +188,15 @@ __device__ __forceinline__ void encrypt_planes(uint32_t (&st)[128], const uint32
 }
 
 // Every wave takes 2048 consecutive blocks per step: lane l holds blocks
-// base + 64 t + l for t = 0..31, so each of the 32 loads per word position is
-// one coalesced 1 KiB access of the wave.  One wave per SIMD: the 128-plane
-// state plus the circuit's temporaries then fit in the unified register file
-// (what does not fit in VGPRs goes to AGPRs rather than to scratch memory),
-// which measured faster than two waves per SIMD with scratch spills.
+// base + 64 t + l for t = 0..31.  Two waves per SIMD (256 registers each):
+// the 128-plane state plus one S-box circuit's or one MixColumns column's
+// temporaries.  Left to itself the compiler interleaves the 16 circuits of a
+// round and spills; the empty asm statements after each circuit, each
+// column and each transpose make it finish one before the next, so nothing
+// spills, and the second wave hides the other's memory waits and fills the
+// issue slots its scalar instructions leave.
 template <int NR, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bitslice_kernel(const CipherArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t nfull = a.nbytes >> 4;
@@ -192,22 +207,20 @@ void bitslice_kernel(const CipherArgs a) {
     for (uint64_t base = wave * 2048u; base < nblk; base += nwaves * 2048u) {
         uint32_t st[128];
         if (MODE == MODE_ECB) {
-            // one 16-byte load per block; word w of block t goes to st[32w + t],
-            // then each word position is transposed in place
+            // word position by word position: word w of block t goes to
+            // st[32w + t] and the 32 words are transposed in place before the
+            // next position is read (all 16-byte loads at once would keep 128
+            // loaded words and their addresses live and spill)
 #pragma unroll
-            for (int t = 0; t < 32; t++) {
-                const uint64_t j = base + 64u * t + lane;
-                u32x4 x = vec4(0, 0, 0, 0);
-                if (j < nfull)
-                    x = load16(a.in + 16 * j);
-                st[t] = x.x;
-                st[32 + t] = x.y;
-                st[64 + t] = x.z;
-                st[96 + t] = x.w;
-            }
+            for (int w = 0; w < 4; w++) {
 #pragma unroll
-            for (int w = 0; w < 4; w++)
+                for (int t = 0; t < 32; t++) {
+                    const uint64_t j = base + 64u * t + lane;
+                    st[32 * w + t] = j < nfull ? load4(a.in + 16 * j + 4 * w) : 0u;
+                }
                 transpose32(*reinterpret_cast<uint32_t(*)[32]>(st + 32 * w));
+                asm volatile("" ::: "memory");   // the next position's loads stay after this transpose
+            }
         } else {
             // counter blocks: words 0..2 are the nonce in every block (planes
             // of all zeros or all ones); only word 3 needs a transpose
@@ -230,9 +243,13 @@ void bitslice_kernel(const CipherArgs a) {
 #pragma unroll
         for (int w = 0; w < 4; w++)
             transpose32(*reinterpret_cast<uint32_t(*)[32]>(st + 32 * w));
+        // the block addresses again from an opaque copy of the base, so the
+        // compiler does not keep the load phase's ones live across the rounds
+        uint64_t sbase = base;
+        asm volatile("" : "+s"(sbase));
 #pragma unroll
         for (int t = 0; t < 32; t++) {
-            const uint64_t j = base + 64u * t + lane;
+            const uint64_t j = sbase + 64u * t + lane;
             u32x4 o = vec4(st[t], st[32 + t], st[64 + t], st[96 + t]);
             if (MODE == MODE_CTR) {
                 if (j < nfull) {
