@@ -89,11 +89,6 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
         asm volatile("" : "+v"(a[k]));
 }
 
-// One 4-byte word of the input, streamed like the 16-byte loads.
-__device__ __forceinline__ uint32_t load4(const uint8_t *p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p));
-}
-
 // Plane index of bit k of row r, column c.
 __device__ __forceinline__ constexpr int P(int c, int r, int k) { return 32 * c + 8 * r + k; }
 
@@ -192,9 +187,11 @@ __device__ __forceinline__ void encrypt_planes(uint32_t (&st)[128], const uint32
 // the 128-plane state plus one S-box circuit's or one MixColumns column's
 // temporaries.  Left to itself the compiler interleaves the 16 circuits of a
 // round and spills; the empty asm statements after each circuit, each
-// column and each transpose make it finish one before the next, so nothing
-// spills, and the second wave hides the other's memory waits and fills the
-// issue slots its scalar instructions leave.
+// column and each transpose make it finish one before the next, and the
+// store phase recomputes the block addresses (else the load phase's are kept
+// live across the rounds), so nothing spills; the second wave hides the
+// other's memory waits and fills the issue slots its scalar instructions
+// leave.
 template <int NR, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bitslice_kernel(const CipherArgs a) {
@@ -207,20 +204,22 @@ void bitslice_kernel(const CipherArgs a) {
     for (uint64_t base = wave * 2048u; base < nblk; base += nwaves * 2048u) {
         uint32_t st[128];
         if (MODE == MODE_ECB) {
-            // word position by word position: word w of block t goes to
-            // st[32w + t] and the 32 words are transposed in place before the
-            // next position is read (all 16-byte loads at once would keep 128
-            // loaded words and their addresses live and spill)
+            // one 16-byte load per block; word w of block t goes to st[32w + t],
+            // then each word position is transposed in place
 #pragma unroll
-            for (int w = 0; w < 4; w++) {
-#pragma unroll
-                for (int t = 0; t < 32; t++) {
-                    const uint64_t j = base + 64u * t + lane;
-                    st[32 * w + t] = j < nfull ? load4(a.in + 16 * j + 4 * w) : 0u;
-                }
-                transpose32(*reinterpret_cast<uint32_t(*)[32]>(st + 32 * w));
-                asm volatile("" ::: "memory");   // the next position's loads stay after this transpose
+            for (int t = 0; t < 32; t++) {
+                const uint64_t j = base + 64u * t + lane;
+                u32x4 x = vec4(0, 0, 0, 0);
+                if (j < nfull)
+                    x = load16(a.in + 16 * j);
+                st[t] = x.x;
+                st[32 + t] = x.y;
+                st[64 + t] = x.z;
+                st[96 + t] = x.w;
             }
+#pragma unroll
+            for (int w = 0; w < 4; w++)
+                transpose32(*reinterpret_cast<uint32_t(*)[32]>(st + 32 * w));
         } else {
             // counter blocks: words 0..2 are the nonce in every block (planes
             // of all zeros or all ones); only word 3 needs a transpose
