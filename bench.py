@@ -36,6 +36,11 @@ HBM_PEAK_GBS = 8000.0             # MI355X HBM3E, published
 CUS, CLOCK_GHZ = 256, 2.4          # MI355X compute units, peak engine clock
 LDS_LANES_PER_CLK = 32             # LDS: 32 banks x 4 B per clock per CU
 LDS_PEAK_TLOOKUPS = CUS * CLOCK_GHZ * 1e9 * LDS_LANES_PER_CLK / 1e12   # 19.66
+# warm-up launches of each 1 GiB secondary measurement (≈ 10 ms): after a
+# pause on the host side the first launches run slower (GCM encryption, the
+# first measured after the XTS legs' set-up, came out 10 % below decryption
+# with two)
+SEC_WARMUP = 10
 KERNEL_SRC = os.path.join(ROOT, "paper_1403_7295_amd", "csrc", "aes_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cipher_kernel_aes128_ecb_enc_1GiB.json")
 
@@ -402,7 +407,7 @@ def main():
             rk, nr = A.aes_expand_key(key)
             fn = A.aes_decrypt if dec else A.aes_encrypt
             w, k = timed_launches(torch, stream,
-                                  lambda: fn(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream), 10, 2)
+                                  lambda: fn(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream), 10, SEC_WARMUP)
             sec[name] = {"GB/s": round(n / k / 1e9, 1)}
         rk, nr = A.aes_expand_key(key128)
         A.aes_set_launch(layout=2)
@@ -410,7 +415,7 @@ def main():
             for name, mode in (("aes128_ecb_enc_bitsliced", A.AES_MODE_ECB),
                                ("aes128_ctr_enc_bitsliced", A.AES_MODE_CTR)):
                 w, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0,
-                                                                            stream=stream), 10, 2)
+                                                                            stream=stream), 10, SEC_WARMUP)
                 sec[name] = {"GB/s": round(n / k / 1e9, 1)}
         finally:
             A.aes_set_launch(None)
@@ -422,7 +427,7 @@ def main():
                 for dec in (False, True):
                     fn = A.aes_xts_decrypt if dec else A.aes_xts_encrypt
                     w, k = timed_launches(torch, stream,
-                                          lambda: fn(x, y, n, rk1, rk2, nr, unit, 0, stream=stream), 10, 2)
+                                          lambda: fn(x, y, n, rk1, rk2, nr, unit, 0, stream=stream), 10, SEC_WARMUP)
                     sec["xts%d_%s_unit%d" % (bits, "dec" if dec else "enc", unit)] = {
                         "GB/s": round(n / k / 1e9, 1)}
         # GCM (CTR with the GHASH tag fused), 16 bytes of additional data
@@ -434,15 +439,15 @@ def main():
         for bits, key in ((128, key128), (256, key256)):
             rk, nr = A.aes_expand_key(key)
             w, k = timed_launches(torch, stream, lambda: A.aes_gcm_encrypt(
-                x, y, n, gaad, 16, rk, nr, giv, gtag, gws, stream=stream), 10, 2)
+                x, y, n, gaad, 16, rk, nr, giv, gtag, gws, stream=stream), 10, SEC_WARMUP)
             sec["aes%d_gcm_enc" % bits] = {"GB/s": round(n / k / 1e9, 1)}
             w, k = timed_launches(torch, stream, lambda: A.aes_gcm_decrypt(
-                y, x, n, gaad, 16, rk, nr, giv, gtag, 16, gok, gws, stream=stream), 10, 2)
+                y, x, n, gaad, 16, rk, nr, giv, gtag, 16, gok, gws, stream=stream), 10, SEC_WARMUP)
             sec["aes%d_gcm_dec" % bits] = {"GB/s": round(n / k / 1e9, 1)}
         # GMAC: the tag of 1 GiB of additional data with no plaintext
         rk, nr = A.aes_expand_key(key128)
         w, k = timed_launches(torch, stream, lambda: A.aes_gcm_encrypt(
-            x, y, 0, x, n, rk, nr, giv, gtag, gws, stream=stream), 10, 2)
+            x, y, 0, x, n, rk, nr, giv, gtag, gws, stream=stream), 10, SEC_WARMUP)
         sec["aes128_gmac"] = {"GB/s": round(n / k / 1e9, 1)}
         # the decryptions above wrote the plaintext back into x
         # the 1 MiB case (AES-128 ECB): it stays in the caches between launches
@@ -457,7 +462,7 @@ def main():
         w, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, share, rk, nr, A.AES_MODE_ECB,
                                                                     stream=stream), 40, 5)
         sec["aes128_ecb_enc_eighth_share"] = {"bytes": share, "GB/s": round(share / k / 1e9, 1)}
-        w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, 2)
+        w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, SEC_WARMUP)
         sec["copy_kernel"] = {"GB/s (read+write)": round(2 * n / k / 1e9, 1)}
         out["secondary"] = sec
         # the HBM fraction also against what a plain copy achieves on this device
