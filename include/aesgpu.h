@@ -206,7 +206,8 @@ const char *aes_last_error(void);
  *   wg_size           256, 512 or 1024 threads per workgroup (table layouts;
  *                     the bitsliced layout uses 256).
  *   grid              workgroups launched (each loops over the buffer); 0 =
- *                     one per compute unit.
+ *                     one per compute unit (two for the bitsliced layout,
+ *                     two waves per SIMD), fewer for small buffers.
  */
 typedef struct {
     int layout;
