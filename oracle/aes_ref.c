@@ -496,7 +496,11 @@ int ref_xts(int dir, const uint8_t *w1, const uint8_t *w2, int Nr, size_t unit_b
         uint8_t iv[16], t[16], x[16], y[16];
         uint64_t i = first_unit + u;
         for (int b = 0; b < 16; b++)
+#ifndef REF_PLANT_XTS_BE
             iv[b] = b < 8 ? (uint8_t)(i >> (8 * b)) : 0;
+#else
+            iv[b] = b >= 8 ? (uint8_t)(i >> (8 * (15 - b))) : 0;
+#endif
         ref_encrypt_block(w2, Nr, iv, t);
         size_t end = u0 + unit_bytes < nbytes ? u0 + unit_bytes : nbytes;
         for (size_t off = u0; off < end; off += 16) {

@@ -10,7 +10,7 @@ of them must fail.
 import numpy as np
 
 import seedgen
-from tests import openssl_cli
+from tests import libcrypto_evp, openssl_cli
 
 POLY = 0x11B  # x^8 + x^4 + x^3 + x + 1
 
@@ -304,9 +304,9 @@ def pin_xts(o):
     """XTS rebuilt block by block from pinned pieces: T_j from the ECB
     encryption (pinned against openssl) of the little-endian unit number and
     an independent GF(2^128) (Python integers: x^j by repeated doubling, and
-    by a general carry-less product with x^j), each block through ECB.  No
-    external XTS implementation is available here, so the conventions (byte
-    order of the tweak, placement of alpha) are the standard's as read."""
+    by a general carry-less product with x^j), each block through ECB.  The
+    conventions themselves (tweak byte order, placement of alpha^j) are
+    pinned against an independent XTS by pin_xts_evp."""
     fails = []
     for k in range(200):
         t = int.from_bytes(seedgen.bytes_np(seedgen.stream_seed(81, seedgen.TAG_DATA, k), 16).tobytes(), "little")
@@ -338,6 +338,75 @@ def pin_xts(o):
                 fails.append("XTS-%d unit %d" % (bits, unit))
             if not np.array_equal(o.xts(True, w1, w2, nr, unit, first, ct), pt):
                 fails.append("XTS-%d decrypt(encrypt(x)) != x" % bits)
+    return fails
+
+
+def pin_xts_evp(o):
+    """XTS against an independent implementation, libcrypto's EVP AES-XTS
+    (called, never read).  Each data unit goes through EVP with key K1 || K2
+    and the tweak block = the unit's sequence number as a 16-byte
+    little-endian number (IEEE 1619's encoding of the data-unit sequence
+    number); the oracle runs the whole buffer in one call.  Units of 16 B to
+    4 KiB, a shorter last unit, sequence numbers across 2^32 and up to the
+    wrap at 2^64, both directions.  This pins the tweak's byte order and
+    where alpha^j enters, which pin_xts only restates."""
+    fails = []
+    if not (libcrypto_evp.available(b"AES-128-XTS") and libcrypto_evp.available(b"AES-256-XTS")):
+        return ["libcrypto AES-XTS not available"]
+    cases = ((16, 7, 0), (32, 9, 123456789), (512, 70, (1 << 32) - 2), (4096, 600, 5),
+             (4096, 300, (1 << 64) - 1), (512, 33, (1 << 64) - 5), (1024, 200, 1 << 40))
+    for bits in (128, 256):
+        k1, k2 = seedgen.key(83, bits, bits), seedgen.key(83, bits + 1, bits)
+        w1, nr = o.expand_key(k1)
+        w2, _ = o.expand_key(k2)
+        for ci, (unit, nblocks, first) in enumerate(cases):
+            data = seedgen.data_np(83, 1000 * bits + ci, 16 * nblocks)
+            for decrypt in (False, True):
+                got = o.xts(decrypt, w1, w2, nr, unit, first, data)
+                want = np.empty_like(data)
+                for u0 in range(0, data.size, unit):
+                    tweak = ((first + u0 // unit) % (1 << 64)).to_bytes(16, "little")
+                    seg = data[u0:u0 + unit]
+                    want[u0:u0 + seg.size] = libcrypto_evp.xts_unit(k1, k2, tweak, seg, decrypt)
+                if not np.array_equal(got, want):
+                    fails.append("XTS-%d %s, unit %d, first unit %d" % (bits, "dec" if decrypt else "enc",
+                                                                         unit, first))
+    return fails
+
+
+def pin_gcm_evp(o):
+    """GCM against an independent implementation, libcrypto's EVP AES-GCM
+    (called, never read): ciphertext and full tag for 128-, 192- and 256-bit
+    keys, IVs of 1 .. 128 bytes (libcrypto takes at most 128), additional
+    data and plaintext of 0 .. 1000 bytes with partial last blocks;
+    decryption's plaintext and verdict for the tag, truncated tags and a
+    changed tag."""
+    fails = []
+    if not all(libcrypto_evp.available(n) for n in (b"AES-128-GCM", b"AES-192-GCM", b"AES-256-GCM")):
+        return ["libcrypto AES-GCM not available"]
+    shapes = ((12, 0, 0), (12, 16, 64), (12, 45, 1000), (1, 7, 33), (13, 0, 16), (16, 1, 15),
+              (60, 1000, 5), (128, 17, 16 * 37))
+    for bits in (128, 192, 256):
+        for si, (ivlen, alen, plen) in enumerate(shapes):
+            key = seedgen.key(97, 100 * bits + si, bits)
+            w, nr = o.expand_key(key)
+            iv = seedgen.bytes_np(seedgen.stream_seed(97, seedgen.TAG_NONCE, 1000 * bits + si), ivlen)
+            aad = seedgen.data_np(98, 1000 * bits + si, alen)
+            pt = seedgen.data_np(99, 1000 * bits + si, plen)
+            ct, tag = o.gcm_encrypt(w, nr, iv, aad, pt)
+            ect, etag = libcrypto_evp.gcm_encrypt(key, iv, aad, pt)
+            if not np.array_equal(ct, ect) or not np.array_equal(tag, etag):
+                fails.append("GCM-%d encrypt, IV %d B, AAD %d B, %d B" % (bits, ivlen, alen, plen))
+                continue
+            for tlen in (16, 12, 8, 4):
+                back, ok = o.gcm_decrypt(w, nr, iv, aad, ct, etag[:tlen])
+                eback, eok = libcrypto_evp.gcm_decrypt(key, iv, aad, ct, etag[:tlen])
+                if not (ok and eok and np.array_equal(back, eback) and np.array_equal(back, pt)):
+                    fails.append("GCM-%d decrypt, %d-byte tag" % (bits, tlen))
+            bad = etag.copy()
+            bad[-1] ^= 0x01
+            if o.gcm_decrypt(w, nr, iv, aad, ct, bad)[1] or libcrypto_evp.gcm_decrypt(key, iv, aad, ct, bad)[1]:
+                fails.append("GCM-%d changed tag accepted" % bits)
     return fails
 
 
@@ -438,7 +507,8 @@ def pin_gcm(o, nkeys=2):
 
 
 ALL_PINS = (pin_gf, pin_sbox, pin_mix_columns, pin_shift_rows, pin_key_expansion,
-            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking, pin_cbc, pin_xts, pin_gcm)
+            pin_openssl, pin_ctr_structure, pin_roundtrip, pin_chunking, pin_cbc, pin_xts, pin_xts_evp, pin_gcm,
+            pin_gcm_evp)
 
 
 def run_all(o, fast=False):

@@ -8,7 +8,7 @@ import pytest
 
 import seedgen
 from oracle import ref
-from tests import openssl_cli, pins
+from tests import libcrypto_evp, openssl_cli, pins
 
 
 @pytest.fixture(scope="module")
@@ -84,6 +84,16 @@ def test_xts(o):
 
 def test_gcm(o):
     assert pins.pin_gcm(o) == []
+
+
+@pytest.mark.skipif(not libcrypto_evp.available(b"AES-128-XTS"), reason="libcrypto AES-XTS not present")
+def test_xts_against_libcrypto(o):
+    assert pins.pin_xts_evp(o) == []
+
+
+@pytest.mark.skipif(not libcrypto_evp.available(b"AES-128-GCM"), reason="libcrypto AES-GCM not present")
+def test_gcm_against_libcrypto(o):
+    assert pins.pin_gcm_evp(o) == []
 
 
 def test_gf128_reference_is_a_field_multiplication():

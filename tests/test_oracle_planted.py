@@ -20,6 +20,7 @@ PLANTS = {
     "REF_PLANT_CTR_LE": "CTR counter stored little-endian",
     "REF_PLANT_CBC_PLAIN": "CBC chains the previous plaintext instead of the ciphertext",
     "REF_PLANT_XTS_NOREDUCE": "XTS tweak doubling without the reduction",
+    "REF_PLANT_XTS_BE": "XTS tweak value written as a big-endian number",
     "REF_PLANT_GCM_R": "GHASH reduction constant at the wrong end of the block",
     "REF_PLANT_GCM_LEN": "GCM length block counts bytes instead of bits",
 }
