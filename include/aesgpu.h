@@ -48,7 +48,8 @@ typedef enum {
     AES_E_OVERLAP = 6,  /* in and out overlap without being identical        */
     AES_E_MODE = 7,     /* unknown mode                                      */
     AES_E_DEVICE = 8,   /* no usable gfx950 device, or a HIP call failed     */
-    AES_E_ARG = 9       /* any other invalid argument                        */
+    AES_E_ARG = 9,      /* any other invalid argument                        */
+    AES_E_BUDGET = 10   /* a served request larger than the admission budget */
 } aes_status;
 
 /* ECB and CTR: every block independent.  CBC (SP 800-38A section 6.2, one of
@@ -79,9 +80,11 @@ int aes_expand_key(const uint8_t *key, int keybits, uint8_t *roundkeys, int *Nr)
  * applied to every 16-byte block; the paper's Section III-A step list).
  *   in, out    device pointers, 16-byte aligned.  in == out (in place) is
  *              allowed; any other overlap is AES_E_OVERLAP.
- *   nbytes     ECB and CBC: a multiple of 16.  CTR: any length; a final
- *              partial block uses the leading bytes of its keystream block.
- *              nbytes == 0 returns AES_OK and enqueues nothing.
+ *   nbytes     ECB and CBC: a multiple of 16.  CTR: any length up to 2^36
+ *              bytes (2^32 blocks: beyond that the 32-bit counter would
+ *              repeat a keystream block within the call; AES_E_LENGTH); a
+ *              final partial block uses the leading bytes of its keystream
+ *              block.  nbytes == 0 returns AES_OK and enqueues nothing.
  *   roundkeys  host pointer to the 16*(Nr+1)-byte ENCRYPTION schedule as
  *              written by aes_expand_key.
  *   Nr         10, 12 or 14.
@@ -288,7 +291,8 @@ int aes_lds_gather(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int *
  * nbytes bytes at in_base + in_off, written to out_base + out_off; both
  * offsets are multiples of 16.  Its key is the first 16/24/32 bytes of the
  * 32-byte slot key_idx of the key array.  ECB and CBC messages are whole
- * blocks; CTR messages may end in a partial block.  ctr0 is the initial
+ * blocks; CTR messages may end in a partial block and hold at most 2^36
+ * bytes (as for aes_encrypt).  ctr0 is the initial
  * counter block (CTR) or the IV (CBC) exactly as for aes_encrypt.  Input
  * and output are the same bytes or disjoint (CBC decryption: disjoint), else
  * the message is rejected; a CBC encryption runs serially on one lane.  XTS messages (whole blocks, as
@@ -357,6 +361,14 @@ typedef struct {
  * Host only. */
 int aes_batch_workspace_size(int max_msgs, size_t *bytes);
 
+/* The same figure under the name of the batched call's planning step: the
+ * workspace a batch of nmsg messages needs.  The size depends on the count
+ * only (one key-schedule slot and one list entry per message), so d_desc is
+ * not read and may be NULL; it is in the signature so that a caller that
+ * plans from its descriptor table passes it unchanged.  Host only.
+ * Errors: AES_E_NULL (workspace_bytes), AES_E_ARG (nmsg < 1). */
+int aes_batch_plan(const aes_msg_desc *d_desc, int nmsg, size_t *workspace_bytes);
+
 /* Enqueue the whole batch on `stream`.  Errors are found on the host from
  * the aes_batch fields; descriptor contents are checked on the device. */
 int aes_batch_run(const aes_batch *b, void *stream);
@@ -404,7 +416,7 @@ typedef struct {
  *                  requests admitted and not yet finished (each rounded up to
  *                  256 bytes) never exceed it.  It is also the size of the
  *                  device arena they are carved from.  A request that alone
- *                  exceeds it is rejected (status AES_E_LENGTH), never queued.
+ *                  exceeds it is rejected (status AES_E_BUDGET), never queued.
  * max_batch_msgs   requests per launch (1..65536).
  * tile_blocks      as for aes_batch (0 = library choice).
  * timeout_s        the run fails with AES_E_DEVICE if nothing completes for
@@ -428,8 +440,15 @@ typedef struct {
     double admit_s;     /* admission time minus arrival (queueing for budget) */
     uint64_t in_off;    /* input and output location in the arena */
     uint64_t out_off;
-    int status;         /* AES_OK, or AES_E_LENGTH if larger than the budget */
+    int status;         /* AES_OK; AES_E_BUDGET if larger than the budget;
+                           AES_E_ARG if the device-side descriptor check
+                           refused it (the host checks make this unexpected) */
     int launch;         /* sequence number of the launch it ran in */
+    int overwritten;    /* 1 if a later request of the same call was given
+                           arena memory that overlaps this request's output
+                           (its bytes at out_off are then no longer its
+                           result), else 0 */
+    int reserved;
 } aes_request_result;
 
 typedef struct {
@@ -455,8 +474,15 @@ int aes_serve_scratch_size(const aes_serve_cfg *cfg, size_t *bytes);
  * yet launched as one batch (payload fill, Key Expansion, the plan,
  * persistent cipher kernels) on it.  Batches on different streams overlap on
  * the device.  results[i] describes reqs[i].  d_scratch (256-byte aligned)
- * holds aes_serve_scratch_size(cfg) bytes; the results stay in its arena at
- * out_off until the next call.
+ * holds aes_serve_scratch_size(cfg) bytes.  A request's arena memory goes
+ * back to the budget when its launch finishes, so a later request may be
+ * carved from it: a result is readable at out_off from its completion until
+ * that happens, and after the call returns exactly for the results whose
+ * `overwritten` is 0 (until the next call on the same scratch).  Every
+ * request is checked before anything runs: key slot < nkeys (nkeys >= 1),
+ * key size, mode (ECB, CTR or CBC), direction, ECB/CBC lengths in whole
+ * blocks and CTR lengths up to 2^36 bytes; a failure returns AES_E_ARG or
+ * AES_E_LENGTH for the whole call.
  */
 int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int nkeys,
                   void *d_scratch, size_t scratch_bytes, const aes_serve_cfg *cfg,

@@ -26,6 +26,7 @@ AES_E_OVERLAP = 6
 AES_E_MODE = 7
 AES_E_DEVICE = 8
 AES_E_ARG = 9
+AES_E_BUDGET = 10
 
 AES_MODE_ECB = 0
 AES_MODE_CTR = 1
@@ -70,6 +71,7 @@ _SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_void_p]),
     "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "aes_batch_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "aes_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "aes_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_uint64),
@@ -120,8 +122,9 @@ REQUEST_DTYPE = np.dtype([("arrival_s", "<f8"), ("nbytes", "<u8"), ("payload_see
                           ("key_idx", "<u4"), ("keybits_code", "u1"), ("mode", "u1"),
                           ("decrypt", "u1"), ("reserved", "u1"), ("ctr0", "u1", (16,))])
 RESULT_DTYPE = np.dtype([("latency_s", "<f8"), ("admit_s", "<f8"), ("in_off", "<u8"),
-                         ("out_off", "<u8"), ("status", "<i4"), ("launch", "<i4")])
-assert REQUEST_DTYPE.itemsize == 48 and RESULT_DTYPE.itemsize == 40
+                         ("out_off", "<u8"), ("status", "<i4"), ("launch", "<i4"),
+                         ("overwritten", "<i4"), ("reserved", "<i4")])
+assert REQUEST_DTYPE.itemsize == 48 and RESULT_DTYPE.itemsize == 48
 
 
 class aes_serve_cfg(ctypes.Structure):
@@ -188,6 +191,36 @@ def _dptr(t):
     return t.data_ptr()
 
 
+def _nbytes_arg(n, name="nbytes"):
+    n = int(n)
+    if n < 0:
+        raise ValueError("%s must be >= 0, got %d" % (name, n))
+    return n
+
+
+def _dev(*specs):
+    """Device addresses of buffer arguments, each given as (tensor, bytes the
+    call will touch, name).  Checked here before any library call, since the
+    kernels trust the extents they are given: every torch tensor must hold
+    its bytes (all extents are checked first), be contiguous, and live on
+    the device (CUDA).  An int is taken as a raw device address, which the
+    caller vouches for; None stays None (a NULL pointer, which the library
+    refuses where it needs one).  One address for one spec, else a list."""
+    tensors = [(t, need, name) for t, need, name in specs if t is not None and not isinstance(t, int)]
+    for t, need, name in tensors:
+        have = t.numel() * t.element_size()
+        if need > have:
+            raise ValueError("%s holds %d bytes but the call would touch %d" % (name, have, need))
+    for t, _, name in tensors:
+        if not t.is_contiguous():
+            raise ValueError("%s must be a contiguous tensor" % name)
+    for t, _, name in tensors:
+        if not t.is_cuda:
+            raise ValueError("%s must be a device (CUDA) tensor, not %s" % (name, t.device))
+    ptrs = [t if t is None or isinstance(t, int) else t.data_ptr() for t, _, _ in specs]
+    return ptrs[0] if len(ptrs) == 1 else ptrs
+
+
 def _stream_handle(stream, like=None):
     if stream is None:
         import torch
@@ -221,8 +254,9 @@ def _crypt(fn, inp, out, nbytes, roundkeys, Nr, mode, ctr0, stream):
     c0 = _host_bytes(ctr0, 16) if ctr0 is not None else None
     if nbytes is None:
         nbytes = inp.numel() * inp.element_size()
-    _check(fn(_dptr(inp), _dptr(out), nbytes, _hptr(rk), Nr, mode, _hptr(c0),
-              _stream_handle(stream, inp)))
+    nbytes = _nbytes_arg(nbytes)
+    pi, po = _dev((inp, nbytes, "inp"), (out, nbytes, "out"))
+    _check(fn(pi, po, nbytes, _hptr(rk), Nr, mode, _hptr(c0), _stream_handle(stream, inp)))
     return out
 
 
@@ -240,7 +274,9 @@ def _xts(fn, inp, out, nbytes, roundkeys1, roundkeys2, Nr, unit_bytes, first_uni
     rk1, rk2 = _host_bytes(roundkeys1), _host_bytes(roundkeys2)
     if nbytes is None:
         nbytes = inp.numel() * inp.element_size()
-    _check(fn(_dptr(inp), _dptr(out), nbytes, _hptr(rk1), _hptr(rk2), Nr, unit_bytes, first_unit,
+    nbytes = _nbytes_arg(nbytes)
+    pi, po = _dev((inp, nbytes, "inp"), (out, nbytes, "out"))
+    _check(fn(pi, po, nbytes, _hptr(rk1), _hptr(rk2), Nr, unit_bytes, first_unit,
               _stream_handle(stream, inp)))
     return out
 
@@ -270,9 +306,12 @@ def aes_gcm_encrypt(inp, out, nbytes, aad, aad_bytes, roundkeys, Nr, iv, tag, wo
     rk, v = _host_bytes(roundkeys), _host_bytes(iv)
     if workspace_bytes is None:
         workspace_bytes = workspace.numel() * workspace.element_size()
-    _check(lib.aes_gcm_encrypt(_dptr(inp), _dptr(out), nbytes, _dptr(aad), aad_bytes, _hptr(rk), Nr,
-                               _hptr(v), v.size, _dptr(tag), _dptr(workspace), workspace_bytes,
-                               _stream_handle(stream, tag)))
+    nbytes, aad_bytes = _nbytes_arg(nbytes), _nbytes_arg(aad_bytes, "aad_bytes")
+    workspace_bytes = _nbytes_arg(workspace_bytes, "workspace_bytes")
+    pi, po, pa, pt, pw = _dev((inp, nbytes, "inp"), (out, nbytes, "out"), (aad, aad_bytes, "aad"),
+                              (tag, 16, "tag"), (workspace, workspace_bytes, "workspace"))
+    args = (pi, po, nbytes, pa, aad_bytes, _hptr(rk), Nr, _hptr(v), v.size, pt, pw, workspace_bytes)
+    _check(lib.aes_gcm_encrypt(*args, _stream_handle(stream, tag)))
     return out
 
 
@@ -282,9 +321,15 @@ def aes_gcm_decrypt(inp, out, nbytes, aad, aad_bytes, roundkeys, Nr, iv, tag, ta
     rk, v = _host_bytes(roundkeys), _host_bytes(iv)
     if workspace_bytes is None:
         workspace_bytes = workspace.numel() * workspace.element_size()
-    _check(lib.aes_gcm_decrypt(_dptr(inp), _dptr(out), nbytes, _dptr(aad), aad_bytes, _hptr(rk), Nr,
-                               _hptr(v), v.size, _dptr(tag), tag_bytes, _dptr(ok), _dptr(workspace),
-                               workspace_bytes, _stream_handle(stream, tag)))
+    nbytes, aad_bytes = _nbytes_arg(nbytes), _nbytes_arg(aad_bytes, "aad_bytes")
+    workspace_bytes = _nbytes_arg(workspace_bytes, "workspace_bytes")
+    tag_bytes = _nbytes_arg(tag_bytes, "tag_bytes")
+    pi, po, pa, pt, pk, pw = _dev((inp, nbytes, "inp"), (out, nbytes, "out"), (aad, aad_bytes, "aad"),
+                                  (tag, tag_bytes, "tag"), (ok, 4, "ok"),
+                                  (workspace, workspace_bytes, "workspace"))
+    args = (pi, po, nbytes, pa, aad_bytes, _hptr(rk), Nr, _hptr(v), v.size, pt, tag_bytes, pk, pw,
+            workspace_bytes)
+    _check(lib.aes_gcm_decrypt(*args, _stream_handle(stream, tag)))
     return out
 
 
@@ -331,7 +376,9 @@ def aes_set_tuned(entries):
 def aes_copy(inp, out, nbytes=None, stream=None):
     if nbytes is None:
         nbytes = inp.numel() * inp.element_size()
-    _check(lib.aes_copy(_dptr(inp), _dptr(out), nbytes, _stream_handle(stream, inp)))
+    nbytes = _nbytes_arg(nbytes)
+    pi, po = _dev((inp, nbytes, "inp"), (out, nbytes, "out"))
+    _check(lib.aes_copy(pi, po, nbytes, _stream_handle(stream, inp)))
     return out
 
 
@@ -342,7 +389,7 @@ def aes_lds_gather(out, rounds, stream=None):
     """Runs the LDS gather calibration kernel; `out` is a device tensor holding
     one 24-byte record per wave.  Returns (waves, constant-rate clock in kHz)."""
     waves, khz = ctypes.c_int(0), ctypes.c_int(0)
-    _check(lib.aes_lds_gather(_dptr(out), out.numel() * out.element_size(), int(rounds),
+    _check(lib.aes_lds_gather(_dev((out, 0, "out")), out.numel() * out.element_size(), int(rounds),
                               ctypes.byref(waves), ctypes.byref(khz), _stream_handle(stream, out)))
     return waves.value, khz.value
 
@@ -364,6 +411,14 @@ def decrypt(x, roundkeys, Nr, mode="ecb", ctr0=None, out=None, stream=None):
 def aes_batch_workspace_size(max_msgs):
     n = ctypes.c_size_t(0)
     _check(lib.aes_batch_workspace_size(max_msgs, ctypes.byref(n)))
+    return n.value
+
+
+def aes_batch_plan(nmsg, d_desc=None):
+    """Workspace bytes of a batch of nmsg messages (the descriptor table is
+    not read: the size depends on the count only)."""
+    n = ctypes.c_size_t(0)
+    _check(lib.aes_batch_plan(_dptr(d_desc), int(nmsg), ctypes.byref(n)))
     return n.value
 
 
@@ -438,6 +493,7 @@ class Batch:
     def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None, device=None):
         import torch
         self.device = device or inp.device
+        _dev((inp, 0, "inp"), (out, 0, "out"))
         descs = np.ascontiguousarray(descs, dtype=MSG_DESC_DTYPE)
         keys = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
         self.max_msgs = max(1, int(max_msgs or len(descs)))

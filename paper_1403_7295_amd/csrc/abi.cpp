@@ -175,6 +175,8 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
         return fail(AES_E_NULL, "CBC needs the initialization vector in ctr0");
     if ((mode == AES_MODE_ECB || mode == AES_MODE_CBC) && nbytes % 16 != 0)
         return fail(AES_E_LENGTH, "ECB and CBC lengths must be a multiple of 16 bytes");
+    if (mode == AES_MODE_CTR && nbytes > kCtrMaxBytes)
+        return fail(AES_E_LENGTH, "CTR is limited to 2^36 bytes per call (the 32-bit counter would repeat)");
     if (nbytes == 0)
         return AES_OK;
     int st = check_buffers(in, out, nbytes);
@@ -396,6 +398,7 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
     a->items = reinterpret_cast<BatchItem *>(ws + items_off);
     a->chunk_totals = reinterpret_cast<uint64_t *>(ws + items_off + 3 * size_t(b->max_msgs) * sizeof(BatchItem));
     a->split_blocks = uint32_t(b->tile_blocks ? b->tile_blocks : kDefaultSplitBlocks);
+    a->reject_flags = nullptr;
     return AES_OK;
 }
 
@@ -569,6 +572,16 @@ int aes_batch_workspace_size(int max_msgs, size_t *bytes) {
     if (max_msgs < 1)
         return fail(AES_E_ARG, "need max_msgs >= 1");
     *bytes = batch_layout(max_msgs);
+    return AES_OK;
+}
+
+int aes_batch_plan(const aes_msg_desc *d_desc, int nmsg, size_t *workspace_bytes) {
+    (void)d_desc;   // the workspace depends on the message count only
+    if (!workspace_bytes)
+        return fail(AES_E_NULL, "workspace_bytes must not be NULL");
+    if (nmsg < 1)
+        return fail(AES_E_ARG, "need nmsg >= 1");
+    *workspace_bytes = batch_layout(nmsg);
     return AES_OK;
 }
 

@@ -77,6 +77,9 @@ __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKAr
     const bool overlap = d.nbytes && ip < op + d.nbytes && op < ip + d.nbytes;
     if (overlap && (ip != op || (d.mode == AES_MODE_CBC && d.decrypt)))
         return false;
+    // a CTR message's 32-bit counter must not repeat a block within it
+    if (d.mode == AES_MODE_CTR && d.nbytes > kCtrMaxBytes)
+        return false;
     // a CBC encryption runs on one lane; its block count must fit the list item
     if (d.mode == AES_MODE_CBC && !d.decrypt && (d.nbytes >> 4) >= 0xFFFFFFFFull)
         return false;
@@ -300,6 +303,8 @@ __global__ __launch_bounds__(kPlanThreads) void prep_kernel(const BatchKArgs a) 
     int k;
     uint64_t c[kPlanCounters], total[kPlanCounters];
     message_counts(a, m, n, valid, k, c);
+    if (m < n && !valid && a.reject_flags)
+        a.reject_flags[m] = 1;
     block_exclusive_scan<kPlanCounters>(c, wsum, total);   // its barrier also covers tab[]
     if (threadIdx.x == 0) {
         for (int j = 0; j < kPlanCounters; j++)
@@ -331,6 +336,8 @@ __global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArg
     int k;
     uint64_t c[kPlanCounters], total[kPlanCounters];
     message_counts(a, m, n, valid, k, c);
+    if (m < n && !valid && a.reject_flags)
+        a.reject_flags[m] = 1;
     block_exclusive_scan<kPlanCounters>(c, wsum, total);   // its barrier also covers tab[]
     if (m == 0) {
         BatchHeader *h = a.header;

@@ -26,6 +26,11 @@ uint32_t inv_mix_column_word(uint32_t col);
 // Equivalent-inverse-cipher schedule, in the order the rounds use it.
 void decryption_schedule(const uint32_t *w, int nr, uint32_t *dk);
 
+// CTR: at most 2^32 blocks per message or buffer, so that the 32-bit
+// counter (incremented modulo 2^32 without a carry into the nonce) never
+// repeats a keystream block within it.
+constexpr uint64_t kCtrMaxBytes = uint64_t(1) << 36;
+
 // ---- kernels (aes_kernels.hip) --------------------------------------------
 enum Mode { MODE_ECB = 0, MODE_CTR = 1, MODE_CBC = 2 };
 enum Dir { DIR_ENC = 0, DIR_DEC = 1 };
@@ -170,6 +175,10 @@ struct BatchKArgs {
     BatchItem *items;        // three lists of max_msgs entries
     uint64_t *chunk_totals;  // the plan's counters per chunk of messages
     uint32_t split_blocks;   // a share starts and ends on a multiple of this
+    uint8_t *reject_flags;   // NULL, or one byte per message, set to 1 for each
+                             // message the descriptor check refuses (the
+                             // caller clears them; the request loop points
+                             // this at pinned host memory)
 };
 
 // Synthetic payloads of the request loop (batch_kernels.hip).

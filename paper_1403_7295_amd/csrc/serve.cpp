@@ -3,7 +3,10 @@
 //
 // Every request owns one arena region (input then output, each rounded up to
 // 256 bytes) from admission until its launch has finished; the arena is the
-// budget, so admitted bytes never exceed it.  Whenever a stream is free,
+// budget, so admitted bytes never exceed it.  A finished request's output
+// stays readable until a later admission is carved from its memory; the loop
+// keeps the finished outputs still intact and marks a result overwritten
+// when that happens.  Whenever a stream is free,
 // everything admitted since the last launch goes out as one batch on it:
 // descriptor upload, payload fill, and the batch sequence of
 // batch_kernels.hip.  Launches on different streams overlap on the device;
@@ -13,6 +16,7 @@
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <string>
 #include <thread>
@@ -51,6 +55,7 @@ static_assert(sizeof(SlotHeader) == kAlign, "slot header is 256 bytes");
 struct ServeLayout {
     size_t arena;
     size_t desc_off, fill_off, ws_off, ws_bytes, slot_bytes, staged_bytes;
+    size_t flags_off, host_bytes;   // pinned memory: staged part, then one reject flag per message
     size_t total;
 };
 
@@ -65,6 +70,8 @@ bool make_layout(const aes_serve_cfg &c, ServeLayout *L) {
     L->ws_off = L->staged_bytes;
     L->ws_bytes = serve_batch_layout(c.max_batch_msgs);
     L->slot_bytes = L->ws_off + round_up(L->ws_bytes, kAlign);
+    L->flags_off = L->staged_bytes;
+    L->host_bytes = L->flags_off + round_up(size_t(c.max_batch_msgs), kAlign);
     L->total = L->arena + size_t(c.streams) * L->slot_bytes;
     return true;
 }
@@ -75,7 +82,7 @@ struct Slot {
     double done_at = 0;          // simulated completion time
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
-    uint8_t *host = nullptr;     // pinned staging for header + descriptors
+    uint8_t *host = nullptr;     // pinned: staging for header + descriptors, then reject flags
     void *host_dev = nullptr;    // its address on the device
     uint8_t *dev = nullptr;      // this slot's device area
 };
@@ -141,6 +148,9 @@ struct Loop {
         }
         h->nmsg = n;
         h->nchunks = chunks;
+        // the prep kernel sets a message's flag if the device-side check
+        // refuses it (through the flags' device address)
+        std::memset(s.host + L.flags_off, 0, size_t(n));
         // header + descriptors + fill descriptors go up in one copy, made by
         // a kernel on the slot's stream: the next kernels follow it on the
         // same queue, with no hand-off from the copy engine
@@ -172,6 +182,7 @@ struct Loop {
             int st = serve_batch_args(&b, &ka);
             if (st != AES_OK)
                 return st;
+            ka.reject_flags = static_cast<uint8_t *>(s.host_dev) + L.flags_off;
             e = launch_batch(ka, batch_grid, s.stream, lists, n);
         }
         if (e == hipSuccess)
@@ -194,6 +205,26 @@ struct Loop {
             return 0;
         error = std::string("event query: ") + hipGetErrorString(e);
         return -1;
+    }
+
+    // Outputs of finished requests that no later admission has touched yet,
+    // by start offset: [start, end) and the request.  They never overlap each
+    // other (an admission removes every one it overlaps before its own
+    // output can join).
+    struct Region {
+        uint64_t end;
+        int req;
+    };
+    std::map<uint64_t, Region> intact;
+
+    void mark_overwritten(uint64_t lo, uint64_t hi) {
+        auto it = intact.upper_bound(lo);
+        if (it != intact.begin() && std::prev(it)->second.end > lo)
+            --it;
+        while (it != intact.end() && it->first < hi) {
+            res[it->second.req].overwritten = 1;
+            it = intact.erase(it);
+        }
     }
 
     int run() {
@@ -221,12 +252,17 @@ struct Loop {
                 if (f == 0)
                     continue;
                 const double t = sim ? s.done_at : now;
-                for (int i : s.reqs) {
+                const uint8_t *flags = sim ? nullptr : s.host + L.flags_off;
+                for (size_t k = 0; k < s.reqs.size(); k++) {
+                    const int i = s.reqs[k];
                     res[i].latency_s = t - reqs[i].arrival_s;
-                    res[i].status = AES_OK;
+                    res[i].status = flags && flags[k] ? AES_E_ARG : AES_OK;
                     const uint64_t fp = footprint(i);
-                    if (fp)
+                    if (fp) {
                         arena.release(res[i].in_off, fp);
+                        if (res[i].status == AES_OK)
+                            intact[res[i].out_off] = Region{res[i].out_off + fp / 2, i};
+                    }
                     inflight_bytes -= fp;
                     inflight--;
                     st.bytes_done += reqs[i].nbytes;
@@ -248,7 +284,7 @@ struct Loop {
                 const int i = queue.front();
                 const uint64_t fp = footprint(i);
                 if (fp > L.arena) {
-                    res[i].status = AES_E_LENGTH;
+                    res[i].status = AES_E_BUDGET;
                     res[i].latency_s = -1;
                     st.rejected++;
                     settled++;
@@ -259,6 +295,8 @@ struct Loop {
                 uint64_t off = 0;
                 if (fp && !arena.alloc(fp, &off))
                     break;
+                if (fp)
+                    mark_overwritten(off, off + fp);
                 res[i].in_off = off;
                 res[i].out_off = off + fp / 2;
                 res[i].admit_s = now - reqs[i].arrival_s;
@@ -332,14 +370,18 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
         return serve_fail(AES_E_ARG, "bad serve configuration");
     if (nreq < 0)
         return serve_fail(AES_E_ARG, "nreq must be >= 0");
+    if (nkeys < 1)
+        return serve_fail(AES_E_ARG, "nkeys must be >= 1");
     for (int i = 0; i < nreq; i++) {
         const aes_request &q = reqs[i];
         if (i && q.arrival_s < reqs[i - 1].arrival_s)
             return serve_fail(AES_E_ARG, "requests must be sorted by arrival_s");
-        if (q.keybits_code > 2 || q.mode > AES_MODE_CBC || q.decrypt > 1 || int(q.key_idx) >= nkeys)
+        if (q.keybits_code > 2 || q.mode > AES_MODE_CBC || q.decrypt > 1 || q.key_idx >= uint32_t(nkeys))
             return serve_fail(AES_E_ARG, "request " + std::to_string(i) + ": bad key, mode or direction");
         if (q.mode != AES_MODE_CTR && q.nbytes % 16)
             return serve_fail(AES_E_LENGTH, "request " + std::to_string(i) + ": ECB/CBC length not whole blocks");
+        if (q.mode == AES_MODE_CTR && q.nbytes > kCtrMaxBytes)
+            return serve_fail(AES_E_LENGTH, "request " + std::to_string(i) + ": CTR longer than 2^36 bytes");
     }
     const bool sim = cfg->simulate_gbps > 0;
     Loop loop(reqs, nreq, *cfg, L, results);
@@ -371,7 +413,7 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
             if (e == hipSuccess)
                 e = hipEventCreateWithFlags(&s.event, hipEventDisableTiming);
             if (e == hipSuccess)
-                e = hipHostMalloc(reinterpret_cast<void **>(&s.host), L.staged_bytes, hipHostMallocDefault);
+                e = hipHostMalloc(reinterpret_cast<void **>(&s.host), L.host_bytes, hipHostMallocDefault);
             if (e == hipSuccess)
                 e = hipHostGetDevicePointer(&s.host_dev, s.host, 0);
         }

@@ -87,6 +87,8 @@ def test_argument_checks(A, fn):
     assert code(IN + 16, IN, 64, rk, nr, "ctr", ctr0=bytes(16)) == A.AES_E_OVERLAP
     if fn == "aes_decrypt":
         assert code(IN, IN, 64, rk, nr, "cbc", ctr0=bytes(16)) == A.AES_E_OVERLAP   # not in place
+    # CTR: at most 2^32 blocks per call (the 32-bit counter must not repeat)
+    assert code(IN, OUT, (1 << 36) + 1, rk, nr, "ctr", ctr0=bytes(16)) == A.AES_E_LENGTH
     # empty buffers are a no-op, whatever the pointers
     call(None, None, 0, rk, nr, "ecb", stream=0)
     call(None, None, 0, rk, nr, "ctr", ctr0=bytes(16), stream=0)
@@ -175,6 +177,23 @@ def test_batch_workspace_size(A):
         assert e.value.code == A.AES_E_ARG
 
 
+def test_batch_plan_is_the_workspace_size(A):
+    for n in (1, 10, 256, 257, 10000):
+        assert A.aes_batch_plan(n) == A.aes_batch_workspace_size(n)
+        assert A.aes_batch_plan(n, d_desc=0x100000) == A.aes_batch_workspace_size(n)
+    with pytest.raises(A.AESError) as e:
+        A.aes_batch_plan(0)
+    assert e.value.code == A.AES_E_ARG
+
+
+def test_status_codes_match_the_header(A):
+    text = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"\b(AES_E_[A-Z]+|AES_OK) = (\d+)", text))
+    assert len(codes) == 11
+    for k, v in codes.items():
+        assert getattr(A, k) == v, k
+
+
 def test_batch_argument_checks(A):
     ws = A.aes_batch_workspace_size(4)
 
@@ -212,3 +231,55 @@ def test_descriptor_layout(A):
     raw = d.view(np.uint8).reshape(4, 48)
     assert raw[1, 8:16].view("<u8")[0] == 16       # out_off follows in_off
     assert raw[1, 28] == 1                          # keybits_code at byte 28
+
+
+class _Refused:
+    """Stands in for a library function that the binding must not reach."""
+
+    def __call__(self, *args):
+        raise AssertionError("the library was called")
+
+
+@pytest.mark.parametrize("fn", ["aes_encrypt", "aes_decrypt", "aes_copy"])
+def test_binding_checks_tensor_extents_before_the_library(A, monkeypatch, fn):
+    # CPU tensors stand in for device tensors: every check here fails before
+    # the binding would call into the library (which is replaced by a trap)
+    import torch
+    monkeypatch.setattr(A.lib, fn, _Refused())
+    rk, nr = A.aes_expand_key(np.zeros(16, np.uint8))
+    x, y = torch.zeros(64, dtype=torch.uint8), torch.zeros(64, dtype=torch.uint8)
+    call = getattr(A, fn)
+    args = (lambda i, o, n: (i, o, n)) if fn == "aes_copy" else (lambda i, o, n: (i, o, n, rk, nr, "ecb"))
+    with pytest.raises(ValueError, match="holds 64 bytes"):
+        call(*args(x, y, 80), stream=0)                           # beyond both tensors
+    with pytest.raises(ValueError, match="out holds 48"):
+        call(*args(x, y[:48], 64), stream=0)                      # beyond the output
+    with pytest.raises(ValueError, match="contiguous"):
+        call(*args(x.view(8, 8).t(), y, 64), stream=0)            # a strided view
+    with pytest.raises(ValueError, match="device"):
+        call(*args(x, y, 64), stream=0)                           # fits, but on the host
+    with pytest.raises(ValueError, match=">= 0"):
+        call(*args(x, y, -16), stream=0)
+
+
+def test_binding_checks_xts_and_gcm_extents(A, monkeypatch):
+    import torch
+    for name in ("aes_xts_encrypt", "aes_gcm_encrypt", "aes_gcm_decrypt"):
+        monkeypatch.setattr(A.lib, name, _Refused())
+    rk, nr = A.aes_expand_key(np.zeros(16, np.uint8))
+    x, y = torch.zeros(512, dtype=torch.uint8), torch.zeros(512, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="inp holds 512"):
+        A.aes_xts_encrypt(x, y, 1024, rk, rk, nr, 512, stream=0)
+    ws = torch.zeros(A.aes_gcm_workspace_size(), dtype=torch.uint8)
+    tag, aad, ok = torch.zeros(16, dtype=torch.uint8), torch.zeros(32, dtype=torch.uint8), torch.zeros(1, dtype=torch.int32)
+    with pytest.raises(ValueError, match="aad holds 32"):
+        A.aes_gcm_encrypt(x, y, 512, aad, 48, rk, nr, bytes(12), tag, ws, stream=0)
+    with pytest.raises(ValueError, match="tag holds 8"):
+        A.aes_gcm_encrypt(x, y, 512, aad, 32, rk, nr, bytes(12), tag[:8], ws, stream=0)
+    with pytest.raises(ValueError, match="workspace holds"):
+        A.aes_gcm_encrypt(x, y, 512, aad, 32, rk, nr, bytes(12), tag, ws[:100], workspace_bytes=8192, stream=0)
+    with pytest.raises(ValueError, match="ok holds 2"):
+        A.aes_gcm_decrypt(x, y, 512, aad, 32, rk, nr, bytes(12), tag, 16, ok.view(torch.uint8)[:2], ws,
+                          stream=0)
+    with pytest.raises(ValueError, match="device"):
+        A.aes_gcm_decrypt(x, y, 512, aad, 32, rk, nr, bytes(12), tag, 16, ok, ws, stream=0)

@@ -2,11 +2,14 @@
 
 AES output is fully determined by (key, mode, counter block, input), so the
 tolerance everywhere is zero: every compared byte must be equal.  Small and
-ragged sizes are compared in full; the 1 GiB and 4 GiB buffers, in the launch
-configuration the benchmark uses, are compared on sampled blocks that the
-oracle computes one by one, plus decrypt(encrypt(x)) == x over the whole
-buffer.
+ragged sizes are compared in full.  The 1 GiB buffer of the throughput
+workload is compared in full too (ECB encryption, ECB decryption of random
+input, CTR), streamed through the oracle 64 MiB at a time; the 4 GiB buffers
+are compared on sampled blocks that the oracle computes one by one, and in
+full against the independent bitsliced kernel.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -324,12 +327,15 @@ def test_bitsliced_matches_oracle(A, O, bits, grid):
         A.aes_set_launch(None)
 
 
-def test_bitsliced_1gib_equals_table_kernel(A, O):
-    k = seedgen.key(2, 0, 128)
+@pytest.mark.parametrize("bits,n", [(128, 1 << 30), (256, 1 << 32)], ids=["aes128-1GiB", "aes256-4GiB"])
+def test_bitsliced_equals_table_kernel_whole_buffer(A, O, bits, n):
+    """Two independent kernels (round tables in LDS; a Boolean S-box circuit
+    on bit-planes) agree on every byte of the 1 GiB and 4 GiB workloads."""
+    master = 2 if bits == 128 else 3
+    k = seedgen.key(master, 0, bits)
     rk, nr = A.aes_expand_key(k)
-    ctr0 = seedgen.nonce(2, 0)
-    n = 1 << 30
-    x = seedgen.data_torch(2, 0, n, "cuda")
+    ctr0 = seedgen.nonce(master, 0)
+    x = seedgen.data_torch(master, 0, n, "cuda")
     y = torch.empty_like(x)
     z = torch.empty_like(x)
     for mode in ("ecb", "ctr"):
@@ -342,7 +348,47 @@ def test_bitsliced_1gib_equals_table_kernel(A, O):
         torch.cuda.synchronize()
         assert torch.equal(y, z), mode
     idx = sample_blocks(n // 16, 256, 7)
-    check_sampled(O, z, 2, 0, rk, nr, "ctr", ctr0, idx, "bitsliced CTR 1 GiB")
+    check_sampled(O, z, master, 0, rk, nr, "ctr", ctr0, idx, "bitsliced CTR %d bytes" % n)
+    del x, y, z
+    torch.cuda.empty_cache()
+
+
+def ctr_block_offset(ctr0, j):
+    """The counter block of block j: the nonce bytes, then the 32-bit
+    big-endian counter advanced by j modulo 2^32 (no carry into the nonce)."""
+    c = np.array(ctr0, dtype=np.uint8).copy()
+    v = (int.from_bytes(bytes(c[12:16]), "big") + j) & 0xFFFFFFFF
+    c[12:16] = np.frombuffer(v.to_bytes(4, "big"), np.uint8)
+    return c
+
+
+@pytest.mark.parametrize("op", ["enc", "dec", "ctr"])
+def test_headline_buffer_whole_against_oracle(A, O, op):
+    """Every byte of the 1 GiB AES-128 throughput workload, computed in the
+    launch configuration the benchmark times, against the oracle: the input
+    is regenerated on the host 64 MiB at a time and the oracle runs the
+    paper's method on it (one contiguous chunk per host thread)."""
+    master, index, n, chunk = 2, 0, 1 << 30, 1 << 26
+    k = seedgen.key(master, index, 128)
+    rk, nr = A.aes_expand_key(k)
+    ctr0 = seedgen.nonce(master, index)
+    x = seedgen.data_torch(master, index, n, "cuda")
+    y = torch.empty_like(x)
+    if op == "dec":
+        A.aes_decrypt(x, y, n, rk, nr, "ecb")
+    else:
+        A.aes_encrypt(x, y, n, rk, nr, "ecb" if op == "enc" else "ctr", ctr0=ctr0)
+    torch.cuda.synchronize()
+    del x
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    opcode = {"enc": ref.OP_ECB_ENC, "dec": ref.OP_ECB_DEC, "ctr": ref.OP_CTR}[op]
+    for off in range(0, n, chunk):
+        xc = seedgen.data_np(master, index, chunk, offset=off)
+        c0 = ctr_block_offset(ctr0, off // 16) if op == "ctr" else None
+        want, _ = O.par_run(opcode, rk, nr, xc, threads, ctr0=c0)
+        assert_same(y[off:off + chunk].cpu().numpy(), want, "%s 1 GiB, chunk at %d" % (op, off))
+    del y
+    torch.cuda.empty_cache()
 
 
 # --- CBC ----------------------------------------------------------------

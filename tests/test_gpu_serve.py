@@ -1,7 +1,8 @@
 """The request loop on the GPU: payloads filled on the device match the
 shared generator, and every request's result is the same alone (a single
 aes_encrypt / aes_decrypt call on its own buffer) as in the mix of
-overlapping batches (tolerance: zero bits), with and without arena reuse."""
+overlapping batches (tolerance: zero bits), with and without arena reuse,
+and equals the oracle's over the served workload's whole size range."""
 import numpy as np
 import pytest
 
@@ -80,9 +81,80 @@ def test_results_with_arena_reuse(A):
         off = int(res["in_off"][i])
         if off not in last or res["launch"][i] >= res["launch"][last[off]]:
             last[off] = i
-    for off, i in last.items():
+    intact = set(np.nonzero(res["overwritten"] == 0)[0].tolist())
+    assert set(last.values()) == intact
+    # and every result the loop reports intact is that request's output
+    for i in sorted(intact):
         payload = seedgen.bytes_np(int(r["payload_seed"][i]), 65536)
         assert torch.equal(srv.output(res[i], 65536), alone(A, r[i], keys[i], payload)), i
+
+
+def oracle_check(O, q, key, out_dev, whole_limit=1 << 20, samples=64):
+    """One served CTR request's output against the oracle: all of it up to
+    whole_limit bytes, else the first and last (partial) blocks and
+    `samples` blocks between them, each recomputed from its own counter."""
+    n = int(q["nbytes"])
+    bits = 128 + 64 * int(q["keybits_code"])
+    rk, nr = O.expand_key(key[:bits // 8])
+    seed = int(q["payload_seed"])
+    if n <= whole_limit:
+        want = O.ctr(rk, nr, q["ctr0"], seedgen.bytes_np(seed, n))
+        return np.array_equal(out_dev.cpu().numpy(), want)
+    nblk = (n + 15) // 16
+    rng = np.random.default_rng(seed & 0xFFFFFFFF)
+    idx = np.unique(np.concatenate([[0, nblk - 1], rng.integers(1, nblk - 1, samples)]))
+    for j in idx.tolist():
+        lo, hi = 16 * j, min(16 * j + 16, n)
+        want = O.ctr(rk, nr, q["ctr0"], seedgen.bytes_np(seed, hi - lo, offset=lo), first_block=j)
+        if not np.array_equal(out_dev[lo:hi].cpu().numpy(), want):
+            return False
+    return True
+
+
+def test_served_workload_sizes_match_the_oracle(A):
+    """Requests shaped like the served workload (CTR, AES-128/256, 70 %
+    encryption, sizes log-uniform from 64 B to 64 MiB, byte-granular), with
+    room for all of them in the arena so that every output can be read after
+    the run: each equals the single-call result and the oracle's."""
+    r, keys = requests(A, 400, rate=2e4, seed=55, lo=64, hi=1 << 26)
+    assert r["nbytes"].max() > (32 << 20) and r["nbytes"].min() < 256
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 255) // 256 * 256)
+    cfg = A.serve_cfg(streams=4, budget_bytes=int(fp.sum()) + (1 << 20), max_batch_msgs=64)
+    srv = A.Server(keys, cfg)
+    res, st = srv.run(r)
+    torch.cuda.synchronize()
+    assert st["completed"] == len(r) and st["rejected"] == 0 and st["launches"] > 4
+    assert not res["overwritten"].any() and (res["status"] == A.AES_OK).all()
+    o = ref.default()
+    for i, q in enumerate(r):
+        n = int(q["nbytes"])
+        got = srv.output(res[i], n)
+        assert oracle_check(o, q, keys[i], got), "oracle, request %d (%d bytes)" % (i, n)
+        x = seedgen.bytes_torch(int(q["payload_seed"]), n, "cuda")
+        y = torch.empty_like(x)
+        fn = A.aes_decrypt if q["decrypt"] else A.aes_encrypt
+        bits = 128 + 64 * int(q["keybits_code"])
+        rk, nr = A.aes_expand_key(keys[i][:bits // 8])
+        fn(x, y, n, rk, nr, "ctr", ctr0=q["ctr0"])
+        assert torch.equal(got, y), "alone vs in the mix, request %d (%d bytes)" % (i, n)
+
+
+def test_served_workload_with_reuse_intact_results_match_the_oracle(A):
+    """The same shape under a budget a fraction of the total, so arena
+    memory is reused: every result the loop reports intact is checked."""
+    r, keys = requests(A, 400, rate=2e4, seed=56, lo=64, hi=1 << 26)
+    cfg = A.serve_cfg(streams=4, budget_bytes=512 << 20, max_batch_msgs=64)
+    srv = A.Server(keys, cfg)
+    res, st = srv.run(r)
+    torch.cuda.synchronize()
+    big = 2 * ((r["nbytes"].astype(np.int64) + 255) // 256 * 256) > (512 << 20)
+    assert st["completed"] == (~big).sum() and (res["status"][big] == A.AES_E_BUDGET).all()
+    intact = np.nonzero((res["overwritten"] == 0) & (res["status"] == A.AES_OK))[0]
+    assert res["overwritten"].sum() > 50 and len(intact) > 20
+    o = ref.default()
+    for i in intact.tolist():
+        n = int(r["nbytes"][i])
+        assert oracle_check(o, r[i], keys[i], srv.output(res[i], n)), "request %d (%d bytes)" % (i, n)
 
 
 def test_latencies_are_consistent(A):

@@ -29,7 +29,7 @@ def test_all_complete_and_budget_holds(A):
     fp = 2 * ((r["nbytes"] + 255) // 256 * 256)
     big = fp > budget
     assert st["completed"] == (~big).sum() and st["rejected"] == big.sum()
-    assert (res["status"][big] == A.AES_E_LENGTH).all()
+    assert (res["status"][big] == A.AES_E_BUDGET).all()
     assert (res["status"][~big] == A.AES_OK).all()
     assert st["max_inflight_bytes"] <= budget
     ok = ~big
@@ -93,6 +93,26 @@ def test_argument_checks(A):
     with pytest.raises(A.AESError) as e:
         A.aes_serve_run(bad, cfg)
     assert e.value.code == A.AES_E_LENGTH
+    # a key slot of 2^31 or more must not pass as a negative int
+    bad = r.copy()
+    bad["key_idx"][2] = 1 << 31
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, cfg, nkeys=8)
+    assert e.value.code == A.AES_E_ARG
+    bad["key_idx"][2] = 8
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, cfg, nkeys=8)
+    assert e.value.code == A.AES_E_ARG
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(r, cfg, nkeys=0)
+    assert e.value.code == A.AES_E_ARG
+    # CTR requests hold at most 2^36 bytes
+    bad = r.copy()
+    bad["mode"][1] = A.AES_MODE_CTR
+    bad["nbytes"][1] = (1 << 36) + 16
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, A.serve_cfg(budget_bytes=1 << 40, simulate_gbps=10.0))
+    assert e.value.code == A.AES_E_LENGTH
     for kw in ({"streams": 0}, {"streams": 17}, {"max_batch_msgs": 0}, {"budget_bytes": 100}):
         with pytest.raises(A.AESError) as e:
             A.aes_serve_scratch_size(A.serve_cfg(**kw))
@@ -119,3 +139,43 @@ def test_arena_is_not_reused_while_space_remains(A):
     spans = sorted(zip(res["in_off"].tolist(), fp.tolist()))
     for (a, na), (b, _) in zip(spans, spans[1:]):
         assert a + na <= b
+
+
+def _overwritten_by_later(A, r, res):
+    """For every request, whether a request after it in arrival order (the
+    loop admits in that order) was given memory overlapping its output."""
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 255) // 256 * 256)
+    ok = res["status"] == A.AES_OK
+    lo = res["in_off"].astype(np.int64)
+    hi = lo + fp
+    out_lo = res["out_off"].astype(np.int64)
+    out_hi = out_lo + fp // 2
+    n = len(r)
+    want = np.zeros(n, bool)
+    for i in range(n):
+        if not ok[i] or fp[i] == 0:
+            continue
+        later = np.arange(n) > i
+        later &= ok & (fp > 0)
+        want[i] = bool(np.any(later & (lo < out_hi[i]) & (out_lo[i] < hi)))
+    return want
+
+
+@pytest.mark.parametrize("budget_mib", [4, 16, 64])
+def test_overwritten_flags_name_exactly_the_reused_outputs(A, budget_mib):
+    # a small arena forces reuse; every result the loop reports intact has
+    # no later request over its output, and every reused one is flagged
+    r, _ = requests(A, 1500, rate=100000.0, hi=1 << 20)
+    cfg = A.serve_cfg(streams=3, budget_bytes=budget_mib << 20, max_batch_msgs=32, simulate_gbps=40.0)
+    res, st = A.aes_serve_run(r, cfg)
+    want = _overwritten_by_later(A, r, res)
+    assert np.array_equal(res["overwritten"].astype(bool), want)
+    assert want.any() and (~want & (res["status"] == A.AES_OK)).any()
+
+
+def test_nothing_is_overwritten_with_room_for_everything(A):
+    r, _ = requests(A, 400, rate=100000.0, hi=1 << 18)
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 255) // 256 * 256)
+    cfg = A.serve_cfg(streams=3, budget_bytes=int(fp.sum()), max_batch_msgs=16, simulate_gbps=50.0)
+    res, _ = A.aes_serve_run(r, cfg)
+    assert not res["overwritten"].any()
