@@ -125,35 +125,71 @@ def measured_traffic(launch):
     return t.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_runs(o, rk, nr, x, threads, reps=5):
+    """One warm-up run, then `reps` timed runs of the oracle's pthreads
+    method (seconds from thread creation to the last join, CLOCK_MONOTONIC
+    inside the oracle): the median, and the mean after dropping runs beyond
+    median +- 2 MAD (the paper's style, Section V)."""
+    o.par_run(0, rk, nr, x, threads)
+    t = sorted(o.par_run(0, rk, nr, x, threads)[1] for _ in range(reps))
+    med = t[len(t) // 2]
+    mad = sorted(abs(v - med) for v in t)[len(t) // 2]
+    kept = [v for v in t if abs(v - med) <= 2 * mad] or t
+    return med, sum(kept) / len(kept), t
+
+
 def cpu_baseline(sample_bytes):
-    """The oracle, untuned, on all host cores with the paper's pthreads split."""
-    import numpy as np  # noqa: F401
+    """The oracle, untuned, on all host cores with the paper's pthreads split,
+    and on one thread for the per-core figure (the paper's Table I reports
+    both).  A bounded sample of the headline workload: the oracle runs at
+    tens of MB/s, so the whole 1 GiB would take about a quarter of a minute
+    per repetition on all cores and several minutes on one."""
     from oracle import ref
     o = ref.default()
     key = seedgen.key(2, 0, 128)
     rk, nr = o.expand_key(key)
     x = seedgen.data_np(2, 0, sample_bytes)
     threads = len(os.sched_getaffinity(0))
-    secs = []
-    for _ in range(3):
-        _, s = o.par_run(0, rk, nr, x, threads)
-        secs.append(s)
-    secs.sort()
-    s = secs[len(secs) // 2]
-    # one thread on an eighth of the sample: the per-core figure (Table I's last column)
+    med, paper, _ = oracle_runs(o, rk, nr, x, threads)
+    # one thread on an eighth of the sample
     one_bytes = max(sample_bytes // 8, 1 << 20)
-    one = sorted(o.par_run(0, rk, nr, x[:one_bytes], 1)[1] for _ in range(3))[1]
-    return {"value": round(sample_bytes / s / 1e9, 5), "unit": "GB/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "AES-128 ECB encrypt of the first %d MiB of the same seeded input, "
-                      "%d pthreads (contiguous whole-block chunks), median of 3 runs, %.2f s each"
-                      % (sample_bytes >> 20, threads, s),
-            "single_thread_GB/s": round(one_bytes / one / 1e9, 5),
-            "single_thread_sample": "the first %d MiB, 1 thread, median of 3 runs, %.2f s each"
-                                    % (one_bytes >> 20, one)}
+    one_med, one_paper, _ = oracle_runs(o, rk, nr, x[:one_bytes], 1)
+    return {"value": round(sample_bytes / med / 1e9, 5), "unit": "GB/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "AES-128 ECB encrypt of the first %d MiB of the headline workload's seeded input "
+                      "(1 GiB would take ~%.0f s per run), %d pthreads over contiguous whole-block chunks; "
+                      "1 warm-up + median of 5 runs, %.2f s each"
+                      % (sample_bytes >> 20, med * (1 << 30) / sample_bytes, threads, med),
+            "paper_style_GB/s": round(sample_bytes / paper / 1e9, 5),
+            "single_thread_GB/s": round(one_bytes / one_med / 1e9, 5),
+            "single_thread_paper_style_GB/s": round(one_bytes / one_paper / 1e9, 5),
+            "single_thread_sample": "the first %d MiB, 1 thread, 1 warm-up + median of 5 runs, %.2f s each"
+                                    % (one_bytes >> 20, one_med)}
 
 
 LDS_GATHER_ROUNDS = 4096
+
+
+def leg(torch, stream, launch, nbytes, reps=10, warmup=None):
+    """One secondary measurement: `reps` launches after `warmup` untimed
+    ones (SEC_WARMUP by default), each timed with HIP events on `stream`;
+    GB/s of `nbytes` over the median launch, beside every launch statistic
+    (one slow launch moves the mean, not the median)."""
+    st = {}
+    timed_launches(torch, stream, launch, reps, SEC_WARMUP if warmup is None else warmup, stats=st)
+    return {"GB/s": round(nbytes / (st["median"] * 1e-6) / 1e9, 1), "launch_us": st}
 
 
 def bench_lds_gather(torch, A, dev, stream, rounds=LDS_GATHER_ROUNDS, steps=20, warmup=3):
@@ -198,11 +234,10 @@ def bench_size_sweep(torch, A, dev, stream, sizes=(1 << 20, 1 << 22, 1 << 24, 1 
     for n in sizes:
         for mode in ("ecb", "ctr"):
             reps = max(5, min(200, (1 << 31) // n))
-            _, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0,
-                                                                       stream=stream), reps, 3, median=True)
-            rows.append({"bytes": n, "mode": mode, "GB/s": round(n / k / 1e9, 1),
-                         "cache_resident": n <= (1 << 24),
-                         "launch": A.aes_get_launch(n, mode, False, nr)})
+            row = leg(torch, stream, lambda: A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream),
+                      n, reps, 3)
+            rows.append(dict({"bytes": n, "mode": mode}, **row, cache_resident=n <= (1 << 24),
+                             launch=A.aes_get_launch(n, mode, False, nr)))
     del x, y
     torch.cuda.empty_cache()
     return {"workload": "AES-256 encrypt, ECB and CTR, 1 MiB .. 4 GiB in steps of 4x",
@@ -264,23 +299,27 @@ def bench_sector_batch(torch, A, dev, stream, nmsg=65536, size=4096, reps=5):
                                   ("xts_encrypt", "xts", 0, xts)):
         descs = A.make_descs(np.full(nmsg, size), keybits=128, mode=mode, decrypt=dec, ctr0=ctr0)
         b = A.Batch(descs, keys, x, y)
-        _, k = timed_launches(torch, stream, lambda: b.launch_graph(stream), reps, 2, median=True)
+        r = leg(torch, stream, lambda: b.launch_graph(stream), total, reps, 2)
         b.close()
-        res[name + "_GB/s"] = round(total / k / 1e9, 1)
+        res[name + "_GB/s"] = r["GB/s"]
+        res[name + "_launch_us"] = r["launch_us"]
     del x, y
     torch.cuda.empty_cache()
     return res
 
 
-def bench_served(torch, A, dev, capacity_gbs, nreq, warm=1000,
+def bench_served(torch, A, dev, plain_ctr_gbs, nreq, warm=1000,
                  loads=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
     """The served workload: Poisson arrivals of CTR requests (70 % encrypt,
     30 % decrypt), sizes log-uniform in [64 B, 64 MiB], AES-128/256 half and
     half, each with its own key and nonce, admitted against an 8 GiB HBM
-    budget on 4 streams.  The arrival rate is swept over offered loads
-    rho = rate x mean size / capacity, capacity being the plain-kernel CTR
-    rate measured above.  Latency runs from arrival to completion seen by the
-    loop; the first `warm` requests of each run are excluded."""
+    budget on 4 streams.  The loop's capacity is measured first: the same
+    requests all waiting at once, completed bytes over the span (payload
+    fill included).  The arrival rate is then swept over offered loads
+    rho = rate x mean size / capacity.  Latency runs from arrival to
+    completion seen by the loop; the first `warm` requests of each run are
+    excluded.  Each point also reports the payload fill's share of the
+    launches' device time (HIP events around the fill and the batch)."""
     import numpy as np
     lo, hi = 64, 1 << 26
     mean = (hi - lo) / np.log(hi / lo)
@@ -290,6 +329,22 @@ def bench_served(torch, A, dev, capacity_gbs, nreq, warm=1000,
         base[k] = v
     cfg = A.serve_cfg(streams=4, budget_bytes=8 << 30, max_batch_msgs=4096)
     srv = A.Server(keys, cfg, device=dev)
+
+    def fill_share(st):
+        tot = st["fill_device_s"] + st["cipher_device_s"]
+        return round(st["fill_device_s"] / tot, 4) if tot > 0 else None
+
+    # capacity: everything waiting from the start (warm-up run first)
+    r = base.copy()
+    r["arrival_s"] = 0.0
+    srv.run(r)
+    res, st = srv.run(r)
+    capacity_gbs = float(r["nbytes"].sum()) / float(res["latency_s"].max()) / 1e9
+    capacity = {"GB/s": round(capacity_gbs, 1), "launches": st["launches"],
+                "fill_share_of_device_time": fill_share(st),
+                "plain_ctr_GB/s": round(plain_ctr_gbs, 1) if plain_ctr_gbs else None,
+                "note": "all requests waiting at once: completed payload bytes over the span, payload fill "
+                        "included; plain_ctr is the single-buffer CTR rate for the same 128/256 mix"}
     points = []
     for rho in loads:
         rate = rho * capacity_gbs * 1e9 / mean
@@ -306,7 +361,8 @@ def bench_served(torch, A, dev, capacity_gbs, nreq, warm=1000,
                        "p50_ms": round(float(np.percentile(m["latency_s"], 50)) * 1e3, 3),
                        "p99_ms": round(float(np.percentile(m["latency_s"], 99)) * 1e3, 3),
                        "p50_admit_wait_ms": round(float(np.percentile(m["admit_s"], 50)) * 1e3, 3),
-                       "launches": st["launches"], "max_inflight_reqs": st["max_inflight_reqs"]})
+                       "launches": st["launches"], "max_inflight_reqs": st["max_inflight_reqs"],
+                       "fill_share_of_device_time": fill_share(st)})
     # the loop's own ceiling: every request 64 bytes and already waiting, so
     # admission, planning and completion are all there is to do
     r = base.copy()
@@ -320,8 +376,8 @@ def bench_served(torch, A, dev, capacity_gbs, nreq, warm=1000,
     torch.cuda.empty_cache()
     return {"workload": "Poisson CTR requests, 70/30 encrypt/decrypt, log-uniform 64 B..64 MiB, "
                         "AES-128/256 50/50, per-request key and nonce, 8 GiB HBM budget, 4 streams",
-            "requests_per_point": nreq, "warmup_requests": warm,
-            "capacity_GB/s": round(capacity_gbs, 1), "points": points,
+            "requests_per_point": nreq, "warmup_requests": warm, "tile_blocks": cfg.tile_blocks,
+            "capacity_GB/s": round(capacity_gbs, 1), "capacity": capacity, "points": points,
             "max_admitted": loop_rate}
 
 
@@ -406,17 +462,14 @@ def main():
                                      ("aes256_ctr_enc", key256, A.AES_MODE_CTR, False)):
             rk, nr = A.aes_expand_key(key)
             fn = A.aes_decrypt if dec else A.aes_encrypt
-            w, k = timed_launches(torch, stream,
-                                  lambda: fn(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream), 10, SEC_WARMUP)
-            sec[name] = {"GB/s": round(n / k / 1e9, 1)}
+            sec[name] = leg(torch, stream, lambda: fn(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream), n)
         rk, nr = A.aes_expand_key(key128)
         A.aes_set_launch(layout=2)
         try:
             for name, mode in (("aes128_ecb_enc_bitsliced", A.AES_MODE_ECB),
                                ("aes128_ctr_enc_bitsliced", A.AES_MODE_CTR)):
-                w, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0,
-                                                                            stream=stream), 10, SEC_WARMUP)
-                sec[name] = {"GB/s": round(n / k / 1e9, 1)}
+                sec[name] = leg(torch, stream,
+                                lambda: A.aes_encrypt(x, y, n, rk, nr, mode, ctr0=ctr0, stream=stream), n)
         finally:
             A.aes_set_launch(None)
         # XTS over 512-byte and 4 KiB data units (tweak key: the next seeded key)
@@ -426,10 +479,8 @@ def main():
             for unit in (512, 4096):
                 for dec in (False, True):
                     fn = A.aes_xts_decrypt if dec else A.aes_xts_encrypt
-                    w, k = timed_launches(torch, stream,
-                                          lambda: fn(x, y, n, rk1, rk2, nr, unit, 0, stream=stream), 10, SEC_WARMUP)
-                    sec["xts%d_%s_unit%d" % (bits, "dec" if dec else "enc", unit)] = {
-                        "GB/s": round(n / k / 1e9, 1)}
+                    sec["xts%d_%s_unit%d" % (bits, "dec" if dec else "enc", unit)] = leg(
+                        torch, stream, lambda: fn(x, y, n, rk1, rk2, nr, unit, 0, stream=stream), n)
         # GCM (CTR with the GHASH tag fused), 16 bytes of additional data
         gws = torch.empty(A.aes_gcm_workspace_size(), dtype=torch.uint8, device=dev)
         gtag = torch.empty(16, dtype=torch.uint8, device=dev)
@@ -438,35 +489,30 @@ def main():
         giv = seedgen.nonce(2, 3)[:12]   # the standard 96-bit IV
         for bits, key in ((128, key128), (256, key256)):
             rk, nr = A.aes_expand_key(key)
-            w, k = timed_launches(torch, stream, lambda: A.aes_gcm_encrypt(
-                x, y, n, gaad, 16, rk, nr, giv, gtag, gws, stream=stream), 10, SEC_WARMUP)
-            sec["aes%d_gcm_enc" % bits] = {"GB/s": round(n / k / 1e9, 1)}
-            w, k = timed_launches(torch, stream, lambda: A.aes_gcm_decrypt(
-                y, x, n, gaad, 16, rk, nr, giv, gtag, 16, gok, gws, stream=stream), 10, SEC_WARMUP)
-            sec["aes%d_gcm_dec" % bits] = {"GB/s": round(n / k / 1e9, 1)}
+            sec["aes%d_gcm_enc" % bits] = leg(torch, stream, lambda: A.aes_gcm_encrypt(
+                x, y, n, gaad, 16, rk, nr, giv, gtag, gws, stream=stream), n)
+            sec["aes%d_gcm_dec" % bits] = leg(torch, stream, lambda: A.aes_gcm_decrypt(
+                y, x, n, gaad, 16, rk, nr, giv, gtag, 16, gok, gws, stream=stream), n)
         # GMAC: the tag of 1 GiB of additional data with no plaintext
         rk, nr = A.aes_expand_key(key128)
-        w, k = timed_launches(torch, stream, lambda: A.aes_gcm_encrypt(
-            x, y, 0, x, n, rk, nr, giv, gtag, gws, stream=stream), 10, SEC_WARMUP)
-        sec["aes128_gmac"] = {"GB/s": round(n / k / 1e9, 1)}
+        sec["aes128_gmac"] = leg(torch, stream, lambda: A.aes_gcm_encrypt(
+            x, y, 0, x, n, rk, nr, giv, gtag, gws, stream=stream), n)
         # the decryptions above wrote the plaintext back into x
         # the 1 MiB case (AES-128 ECB): it stays in the caches between launches
         rk, nr = A.aes_expand_key(key128)
-        w, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, 1 << 20, rk, nr, A.AES_MODE_ECB,
-                                                                    stream=stream), 200, 10, median=True)
-        sec["aes128_ecb_enc_1MiB"] = {"GB/s": round((1 << 20) / k / 1e9, 1), "us": round(k * 1e6, 2),
-                                      "cache_resident": True}
+        sec["aes128_ecb_enc_1MiB"] = dict(leg(torch, stream, lambda: A.aes_encrypt(
+            x, y, 1 << 20, rk, nr, A.AES_MODE_ECB, stream=stream), 1 << 20, 200, 10), cache_resident=True)
         # one GPU's share of the 1 GiB job if it were split over eight GPUs
         rk, nr = A.aes_expand_key(key128)
         share = n // 8
-        w, k = timed_launches(torch, stream, lambda: A.aes_encrypt(x, y, share, rk, nr, A.AES_MODE_ECB,
-                                                                    stream=stream), 40, 5)
-        sec["aes128_ecb_enc_eighth_share"] = {"bytes": share, "GB/s": round(share / k / 1e9, 1)}
-        w, k = timed_launches(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 10, SEC_WARMUP)
-        sec["copy_kernel"] = {"GB/s (read+write)": round(2 * n / k / 1e9, 1)}
+        sec["aes128_ecb_enc_eighth_share"] = dict(leg(torch, stream, lambda: A.aes_encrypt(
+            x, y, share, rk, nr, A.AES_MODE_ECB, stream=stream), share, 40, 5), bytes=share)
+        cp = leg(torch, stream, lambda: A.aes_copy(x, y, n, stream=stream), 2 * n)
+        sec["copy_kernel"] = {"GB/s (read+write)": cp["GB/s"], "launch_us": cp["launch_us"]}
+        sec["statistic"] = "GB/s over the median launch (HIP events); launch_us: every launch statistic"
         out["secondary"] = sec
         # the HBM fraction also against what a plain copy achieves on this device
-        copy_gbs = 2 * n / k / 1e9
+        copy_gbs = cp["GB/s"]
         out["roofline_hbm"]["copy_GB/s"] = round(copy_gbs, 1)
         out["roofline_hbm"]["frac_of_copy"] = round(out["roofline_hbm"]["achieved"] / copy_gbs, 4)
 
@@ -478,11 +524,11 @@ def main():
         out["sector_batch"] = bench_sector_batch(torch, A, dev, stream)
 
     if not args.no_served:
-        cap = None
+        plain = None
         if "secondary" in out:
             a, b = out["secondary"]["aes128_ctr_enc"]["GB/s"], out["secondary"]["aes256_ctr_enc"]["GB/s"]
-            cap = 2.0 / (1.0 / a + 1.0 / b)     # half the bytes at each key size
-        out["served"] = bench_served(torch, A, dev, cap or 1000.0, args.served_requests)
+            plain = 2.0 / (1.0 / a + 1.0 / b)     # half the bytes at each key size
+        out["served"] = bench_served(torch, A, dev, plain, args.served_requests)
 
     # the lookup rate the LDS accepts on this device, measured last: the
     # calibration kernel runs at a high clock and power, and measurements

@@ -459,6 +459,12 @@ typedef struct {
     int launches;
     int max_inflight_reqs;    /* most requests admitted at once */
     uint64_t max_inflight_bytes;
+    double fill_device_s;     /* summed over launches, from HIP events on each
+                                 launch's stream: device time of the payload
+                                 fill (with the descriptor upload) ... */
+    double cipher_device_s;   /* ... and of the batch sequence (0 when
+                                 simulating; launches on other streams may
+                                 overlap either span) */
 } aes_serve_stats;
 
 /* Device scratch bytes aes_serve_run needs for cfg (the arena plus per-stream

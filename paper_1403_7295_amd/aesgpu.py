@@ -137,7 +137,8 @@ class aes_serve_stats(ctypes.Structure):
     _fields_ = [("span_s", ctypes.c_double), ("bytes_done", ctypes.c_uint64),
                 ("completed", ctypes.c_int), ("rejected", ctypes.c_int),
                 ("launches", ctypes.c_int), ("max_inflight_reqs", ctypes.c_int),
-                ("max_inflight_bytes", ctypes.c_uint64)]
+                ("max_inflight_bytes", ctypes.c_uint64), ("fill_device_s", ctypes.c_double),
+                ("cipher_device_s", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -561,8 +562,12 @@ class Batch:
 
 
 # --- serving ----------------------------------------------------------------
-def serve_cfg(streams=4, budget_bytes=8 << 30, max_batch_msgs=4096, tile_blocks=0,
+def serve_cfg(streams=4, budget_bytes=8 << 30, max_batch_msgs=4096, tile_blocks=None,
               timeout_s=0.0, simulate_gbps=0.0):
+    """A request-loop configuration; tile_blocks None takes the autotuner's
+    split step, the one Batch uses too."""
+    if tile_blocks is None:
+        tile_blocks = TUNED_TILE_BLOCKS
     return aes_serve_cfg(streams=streams, budget_bytes=budget_bytes,
                          max_batch_msgs=max_batch_msgs, tile_blocks=tile_blocks,
                          timeout_s=timeout_s, simulate_gbps=simulate_gbps)

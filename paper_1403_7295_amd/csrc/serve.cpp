@@ -81,7 +81,9 @@ struct Slot {
     std::vector<int> reqs;
     double done_at = 0;          // simulated completion time
     hipStream_t stream = nullptr;
-    hipEvent_t event = nullptr;
+    hipEvent_t ev_start = nullptr;   // before the descriptor upload
+    hipEvent_t ev_fill = nullptr;    // after the payload fill
+    hipEvent_t event = nullptr;      // after the batch: the launch is finished
     uint8_t *host = nullptr;     // pinned: staging for header + descriptors, then reject flags
     void *host_dev = nullptr;    // its address on the device
     uint8_t *dev = nullptr;      // this slot's device area
@@ -155,7 +157,9 @@ struct Loop {
         // a kernel on the slot's stream: the next kernels follow it on the
         // same queue, with no hand-off from the copy engine
         const size_t up = round_up(L.fill_off + size_t(n) * sizeof(FillDesc), 16);
-        hipError_t e = launch_stage(s.host_dev, s.dev, up, s.stream);
+        hipError_t e = hipEventRecord(s.ev_start, s.stream);
+        if (e == hipSuccess)
+            e = launch_stage(s.host_dev, s.dev, up, s.stream);
         FillKArgs fa;
         fa.fd = reinterpret_cast<const FillDesc *>(s.dev + L.fill_off);
         fa.d_nmsg = &reinterpret_cast<const SlotHeader *>(s.dev)->nmsg;
@@ -163,6 +167,8 @@ struct Loop {
         fa.base = arena_base;
         if (e == hipSuccess)
             e = launch_fill(fa, std::min<uint64_t>(std::max<uint64_t>(chunks, 1), uint64_t(cus) * 8), s.stream);
+        if (e == hipSuccess)
+            e = hipEventRecord(s.ev_fill, s.stream);
         if (e == hipSuccess) {
             aes_batch b;
             b.desc = reinterpret_cast<const aes_msg_desc *>(s.dev + L.desc_off);
@@ -199,8 +205,18 @@ struct Loop {
         if (sim)
             return now >= s.done_at ? 1 : 0;
         hipError_t e = hipEventQuery(s.event);
-        if (e == hipSuccess)
+        if (e == hipSuccess) {
+            // device time of the payload fill (with the descriptor upload)
+            // and of the batch, per launch (launches on other streams may
+            // share the device meanwhile)
+            float fill_ms = 0, cipher_ms = 0;
+            if (hipEventElapsedTime(&fill_ms, s.ev_start, s.ev_fill) == hipSuccess &&
+                hipEventElapsedTime(&cipher_ms, s.ev_fill, s.event) == hipSuccess) {
+                st.fill_device_s += 1e-3 * fill_ms;
+                st.cipher_device_s += 1e-3 * cipher_ms;
+            }
             return 1;
+        }
         if (e == hipErrorNotReady)
             return 0;
         error = std::string("event query: ") + hipGetErrorString(e);
@@ -411,7 +427,11 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
             s.dev = loop.arena_base + L.arena + size_t(k) * L.slot_bytes;
             e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
             if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&s.event, hipEventDisableTiming);
+                e = hipEventCreate(&s.ev_start);
+            if (e == hipSuccess)
+                e = hipEventCreate(&s.ev_fill);
+            if (e == hipSuccess)
+                e = hipEventCreate(&s.event);
             if (e == hipSuccess)
                 e = hipHostMalloc(reinterpret_cast<void **>(&s.host), L.host_bytes, hipHostMallocDefault);
             if (e == hipSuccess)
@@ -434,6 +454,10 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
                 (void)hipHostFree(s.host);
             if (s.event)
                 (void)hipEventDestroy(s.event);
+            if (s.ev_fill)
+                (void)hipEventDestroy(s.ev_fill);
+            if (s.ev_start)
+                (void)hipEventDestroy(s.ev_start);
             if (s.stream)
                 (void)hipStreamDestroy(s.stream);
         }

@@ -61,3 +61,15 @@ def test_bench_line_fields():
     assert cpu["kind"] == "oracle" and cpu["value"] > 0 and cpu["cores"] >= 1 and cpu["sample"]
     lds = d["lds_gather"]
     assert lds["Tlookup/s"] > 0 and d["roofline_issue"]["measured_peak"] == lds["Tlookup/s"]
+
+
+def test_cpu_baseline_record():
+    # the oracle on a 1 MiB sample: all cores and one thread, one warm-up and
+    # the median of five runs each, with the host's CPU model
+    c = bench.cpu_baseline(1 << 20)
+    assert c["kind"] == "oracle" and c["unit"] == "GB/s" and c["value"] > 0
+    assert c["cores"] == len(os.sched_getaffinity(0))
+    assert c["cpu_model"] is None or len(c["cpu_model"]) > 3
+    assert "median of 5 runs" in c["sample"] and "warm-up" in c["sample"]
+    assert c["single_thread_GB/s"] > 0 and "median of 5 runs" in c["single_thread_sample"]
+    assert c["paper_style_GB/s"] > 0
