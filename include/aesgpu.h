@@ -373,6 +373,27 @@ int aes_batch_plan(const aes_msg_desc *d_desc, int nmsg, size_t *workspace_bytes
  * the aes_batch fields; descriptor contents are checked on the device. */
 int aes_batch_run(const aes_batch *b, void *stream);
 
+/*
+ * aes_batch_run for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The batch's workspace is not the caller's: it is a buffer the library
+ * holds in device memory for the life of the process, one per device
+ * (AES_BATCH_NOALLOC_MAX_MSGS messages' worth, about 8.8 MiB), set up with
+ * the device's other state on the first call.  The call allocates nothing;
+ * the caller still passes descriptors, keys, input and output as for
+ * aes_batch_run, with b->workspace NULL and b->workspace_bytes 0.
+ * Every call on a device shares that device's buffer and leaves its
+ * contents behind for the next (the batch sequence rewrites everything it
+ * reads, so nothing has to start cleared): calls whose batches may run at
+ * the same time on one device (different streams, or another thread's)
+ * race and give wrong results; calls queued on one stream do not.
+ * aes_batch_query does not apply (the counts live in the shared buffer).
+ * Errors: as aes_batch_run; AES_E_ARG if b->workspace or workspace_bytes is
+ * set, AES_E_LENGTH if b->max_msgs > AES_BATCH_NOALLOC_MAX_MSGS.
+ */
+#define AES_BATCH_NOALLOC_MAX_MSGS 16384
+int aes_batch_run_noalloc(const aes_batch *b, void *stream);
+
 /* After the stream has run the batch: messages planned (accepted into the
  * lists) and messages rejected by the device-side checks.  Synchronous
  * (waits for `stream`). */

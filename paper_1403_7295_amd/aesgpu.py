@@ -73,6 +73,7 @@ _SIGNATURES = {
     "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "aes_batch_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "aes_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "aes_batch_run_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "aes_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64)]),
@@ -425,6 +426,15 @@ def aes_batch_plan(nmsg, d_desc=None):
 
 def aes_batch_run(batch, stream=None):
     _check(lib.aes_batch_run(ctypes.byref(batch), _stream_handle(stream)))
+
+
+AES_BATCH_NOALLOC_MAX_MSGS = 16384
+
+
+def aes_batch_run_noalloc(batch, stream=None):
+    """aes_batch_run with the library's own workspace (batch.workspace must
+    be None and workspace_bytes 0); allocates nothing."""
+    _check(lib.aes_batch_run_noalloc(ctypes.byref(batch), _stream_handle(stream)))
 
 
 def aes_batch_query(batch, stream=None):

@@ -55,6 +55,8 @@ void init_device(int dev) {
     if (e == hipSuccess)
         e = upload_tables_batch(host_tables());
     if (e == hipSuccess)
+        e = init_batch_scratch(dev);
+    if (e == hipSuccess)
         e = upload_tables_xts(host_tables());
     if (e == hipSuccess)
         e = upload_tables_gcm(host_tables());
@@ -354,15 +356,6 @@ int gcm_crypt(int decrypt, const void *in, void *out, size_t nbytes, const void 
     return AES_OK;
 }
 
-// Workspace bytes for up to max_msgs messages: header, one key slot and one
-// list entry per message in each of the three lists, the plan's counters
-// per chunk of messages.
-size_t batch_layout(int max_msgs) {
-    const size_t chunks = (size_t(max_msgs) + kBatchChunk - 1) / kBatchChunk;
-    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(max_msgs) * sizeof(BatchItem) +
-           chunks * kBatchChunkCounters * sizeof(uint64_t);
-}
-
 // Cipher-kernel workgroups for a batch launch on this device.
 int batch_grid(const DeviceState &d) { return std::min(d.cus, kBatchMaxWaves / kBatchWavesPerGroup); }
 
@@ -596,6 +589,38 @@ int aes_batch_run(const aes_batch *b, void *stream) {
     // without a device-side count the host knows how many messages there are
     hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), 7u,
                                 a.d_nmsg ? a.max_msgs : a.nmsg);
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    return AES_OK;
+}
+
+int aes_batch_run_noalloc(const aes_batch *b, void *stream) {
+    if (!b)
+        return fail(AES_E_NULL, "batch must not be NULL");
+    if (b->workspace || b->workspace_bytes)
+        return fail(AES_E_ARG, "the no-allocation call uses the library's own workspace: "
+                               "workspace must be NULL and workspace_bytes 0");
+    if (b->max_msgs > AES_BATCH_NOALLOC_MAX_MSGS)
+        return fail(AES_E_LENGTH, "max_msgs is limited to " + std::to_string(AES_BATCH_NOALLOC_MAX_MSGS) +
+                                      " without a caller-supplied workspace");
+    int st;
+    const DeviceState *d = current_device(&st);
+    if (!d)
+        return st;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(AES_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    aes_batch w = *b;
+    w.workspace = batch_scratch(dev);   // the array's device address, looked up at set-up
+    w.workspace_bytes = kNoAllocScratchBytes;
+    if (!w.workspace)
+        return fail(AES_E_DEVICE, "the library's batch workspace has no address on this device");
+    BatchKArgs a;
+    st = batch_args(&w, &a);
+    if (st != AES_OK)
+        return st;
+    e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), 7u, a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     return AES_OK;

@@ -738,6 +738,30 @@ __global__ __launch_bounds__(256) void stage_kernel(const u32x4 *src, u32x4 *dst
 
 hipError_t upload_tables_batch(const HostTables &t) { return upload_base_tables(t); }
 
+// The workspace of aes_batch_run_noalloc, for callers that cannot allocate:
+// a file-scope device array, held by every device the library runs on until
+// the process ends.  Host code never passes the array's name to a kernel or
+// copy (in host code it is only a stand-in for the symbol): its device
+// address is looked up per device at the device's set-up and kept here.
+namespace {
+__device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+constexpr int kScratchDevices = 64;
+void *g_scratch_ptr[kScratchDevices];
+}  // namespace
+
+hipError_t init_batch_scratch(int dev) {
+    if (dev < 0 || dev >= kScratchDevices)
+        return hipErrorInvalidDevice;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess)
+        return e;
+    g_scratch_ptr[dev] = ptr;
+    return hipSuccess;
+}
+
+void *batch_scratch(int dev) { return dev >= 0 && dev < kScratchDevices ? g_scratch_ptr[dev] : nullptr; }
+
 hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStream_t stream) {
     const uint64_t n16 = nbytes / 16;
     const uint64_t grid = std::min<uint64_t>(std::max<uint64_t>((n16 + 255) / 256, 1), 64);

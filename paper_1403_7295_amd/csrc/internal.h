@@ -203,6 +203,22 @@ hipError_t launch_fill(const FillKArgs &a, int grid, hipStream_t stream);
 hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStream_t stream);
 
 hipError_t upload_tables_batch(const HostTables &t);
+
+// Workspace bytes for batches of up to max_msgs messages: header, one key
+// slot and one list entry per message in each of the three lists, the plan's
+// counters per chunk of messages.
+constexpr size_t batch_layout(int max_msgs) {
+    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(max_msgs) * sizeof(BatchItem) +
+           (size_t(max_msgs) + kBatchChunk - 1) / kBatchChunk * kBatchChunkCounters * sizeof(uint64_t);
+}
+// The library-held batch workspace of aes_batch_run_noalloc
+// (batch_kernels.hip): one per device, for batches of up to
+// AES_BATCH_NOALLOC_MAX_MSGS messages.  init_batch_scratch looks up its
+// address on the current device (once per device, at the device's set-up);
+// batch_scratch returns it (NULL before that).
+constexpr size_t kNoAllocScratchBytes = batch_layout(AES_BATCH_NOALLOC_MAX_MSGS);
+hipError_t init_batch_scratch(int dev);
+void *batch_scratch(int dev);
 // lists: bit k set if list k may hold messages (bit 0 forward, 1 inverse, 2
 // serial); a cipher kernel whose lists are all known to be empty is not
 // launched.  max_count: a bound on the message count known to the caller

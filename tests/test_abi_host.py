@@ -221,6 +221,24 @@ def test_batch_argument_checks(A):
     assert code(batch(tile_blocks=1025)) == A.AES_E_ARG
 
 
+def test_noalloc_batch_argument_checks(A):
+    ws = A.aes_batch_workspace_size(4)
+    f = dict(desc=0x100000, nmsg=4, d_nmsg=None, keys=0x200000, nkeys=4, in_base=0x300000, in_bytes=4096,
+             out_base=0x400000, out_bytes=4096, workspace=None, workspace_bytes=0, max_msgs=4, tile_blocks=0)
+
+    def code(**kw):
+        with pytest.raises(A.AESError) as e:
+            A.aes_batch_run_noalloc(A.aes_batch(**dict(f, **kw)), stream=0)
+        return e.value.code
+
+    assert code(workspace=0x500000, workspace_bytes=ws) == A.AES_E_ARG     # the library's workspace only
+    assert code(workspace_bytes=ws) == A.AES_E_ARG
+    assert code(max_msgs=A.AES_BATCH_NOALLOC_MAX_MSGS + 1) == A.AES_E_LENGTH
+    assert A.lib.aes_batch_run_noalloc(None, None) == A.AES_E_NULL
+    text = open(HEADER).read()
+    assert "#define AES_BATCH_NOALLOC_MAX_MSGS %d" % A.AES_BATCH_NOALLOC_MAX_MSGS in text
+
+
 def test_descriptor_layout(A):
     d = A.make_descs([16, 17, 0, 100], keybits=[128, 192, 256, 128], mode=["ecb", "ctr", "ctr", "ecb"],
                      decrypt=[0, 1, 0, 1])
