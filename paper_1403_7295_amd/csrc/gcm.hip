@@ -12,15 +12,22 @@
 // Evaluation order.  Number the sequence from its end, r = m - i, so that
 // S = H * sum_r X_r * H^r: r = 0 is the length block, r = 1 .. nC the
 // ciphertext blocks (block j at r = nC - j), then the additional data.
-// Positions are cut into chunks of 256 (64 lanes x 4 slots); wave w of NW
-// takes chunks w, w + NW, w + 2 NW, ... from the last to the first, so every
-// (lane, slot) stream is a Horner evaluation with the same multiplier
-// G = H^(256 NW):  W <- W * G + X.  At the end a stream at offset s in its
-// wave's first chunk needs the factor H^(s + 256 w); the streams are folded
-// with factors H^64 (slots), H^1 .. H^32 (lanes, a tree), H^256 .. H^2048
-// (the 16 waves of a workgroup) and H^(4096 b) (workgroups, in the last
-// kernel).  Every factor is a power H^(2^t), computed once by the first
-// kernel.
+// The first `head` = (nC + 1) mod 64 positions (the length block and the
+// last head - 1 ciphertext blocks) are left to the last kernel, so that the
+// bulk's positions start at r = head, where every group of 64 positions
+// covers 64 ciphertext blocks starting on a 1 KiB boundary: a wave's 16-byte
+// stores then write whole 128-byte lines, none shared with another wave.
+// The bulk's positions p = r - head are cut into chunks of 256 (64 lanes x
+// 4 slots); wave w of NW takes chunks w, w + NW, w + 2 NW, ... from the last
+// to the first, so every (lane, slot) stream is a Horner evaluation with the
+// same multiplier G = H^(256 NW):  W <- W * G + X.  At the end a stream at
+// offset s in its wave's first chunk needs the factor H^(s + 256 w); the
+// streams are folded with factors H^64 (slots), H^1 .. H^32 (lanes, a
+// tree), H^256 .. H^2048 (the 16 waves of a workgroup) and H^(4096 b)
+// (workgroups, in the last kernel), giving B = sum_(r >= head) X_r H^(r -
+// head).  The last kernel encrypts the head's blocks, adds them in, S = H *
+// (sum_(r < head) X_r H^r + H^head * B).  Every factor is a power H^(2^t),
+// computed once by the first kernel.
 //
 // Multiplication by a fixed element M uses 4-bit tables in LDS: for each of
 // the 32 nibble positions of a block, the 16 products (nibble value at that
@@ -259,7 +266,9 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
     const uint64_t nC = (a.nbytes + 15) >> 4, nA = (a.aad_bytes + 15) >> 4;
-    const uint64_t nchunks = (nC + nA + 1 + 255) >> 8;
+    // positions r < head belong to the last kernel (head <= nC + 1)
+    const uint64_t head = (nC + 1) & 63u;
+    const uint64_t nchunks = (nC + nA + 1 - head + 255) >> 8;
     const uint64_t cwhole = a.nbytes >> 4, awhole = a.aad_bytes >> 4;
     const uint32_t ctail = uint32_t(a.nbytes & 15u), atail = uint32_t(a.aad_bytes & 15u);
     const uint64_t wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -302,9 +311,10 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
         // all four slots' loads first, ahead of the per-slot branches below
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
-            // position r = 256q + 64i + lane is block j = nC - r; the slot's
-            // 64 blocks end at block nC - 256q - 64i
-            const uint64_t top = nC - 256 * q - 64u * uint32_t(i) - 63;
+            // position r = head + 256q + 64i + lane is block j = nC - r; the
+            // slot's 64 blocks start at block nC - head - 256q - 64i - 63, a
+            // multiple of 64
+            const uint64_t top = nC - head - 256 * q - 64u * uint32_t(i) - 63;
             const u32x4 v = load16(a.in + 16 * top + 16u * (63u - lane));
             x[i][0] = v.x;
             x[i][1] = v.y;
@@ -313,7 +323,7 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
-            const uint64_t top = nC - 256 * q - 64u * uint32_t(i) - 63;
+            const uint64_t top = nC - head - 256 * q - 64u * uint32_t(i) - 63;
             // rounds 1 and 2 (the counters of the slot are cs .. cs + 63)
             const uint32_t cs = c1 + uint32_t(top);
             const uint32_t v3 = __builtin_bswap32(cs + (63u - lane)) ^ a.rk[3];
@@ -347,7 +357,7 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
         rounds<NR, DIR_ENC, LAYOUT_T4X32, BPT>(s, aes, lc, a.rk, 3);
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
-            const uint64_t top = nC - 256 * q - 64u * uint32_t(i) - 63;
+            const uint64_t top = nC - head - 256 * q - 64u * uint32_t(i) - 63;
             const uint32_t o[4] = {x[i][0] ^ s[i][0], x[i][1] ^ s[i][1], x[i][2] ^ s[i][2], x[i][3] ^ s[i][3]};
             store16(a.out + 16 * top + 16u * (63u - lane), vec4(o[0], o[1], o[2], o[3]));
             uint32_t g[4];
@@ -366,8 +376,8 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
             // position r is additional-data block k = nC + nA - r; the slot's
-            // 64 blocks end at block nC + nA - 256q - 64i
-            const uint64_t top = nC + nA - 256 * q - 64u * uint32_t(i) - 63;
+            // 64 blocks end at block nC + nA - head - 256q - 64i
+            const uint64_t top = nC + nA - head - 256 * q - 64u * uint32_t(i) - 63;
             const u32x4 v = load16(a.aad + 16 * top + 16u * (63u - lane));
             uint32_t g[4];
             mul_tab(lds, kGTab, W[i], g);
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
     auto slow_chunk = [&](uint64_t q) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
-            const uint64_t r = 256 * q + 64u * uint32_t(i) + lane;
+            const uint64_t r = head + 256 * q + 64u * uint32_t(i) + lane;
             const bool is_c = r >= 1 && r <= nC;
             const uint64_t j = nC - r;
             u32x4 v = vec4(0, 0, 0, 0);
@@ -418,9 +428,12 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
     if (wave < nchunks) {
         uint64_t q = wave + nwaves * ((nchunks - 1 - wave) / nwaves);
         for (;;) {
-            if (q >= 1 && 256 * q + 255 <= nC)
+            // fast: all 256 positions whole ciphertext blocks (r >= 2 leaves
+            // out the length block and a partial last block)
+            const uint64_t rq = head + 256 * q;
+            if (rq >= 2 && rq + 255 <= nC)
                 fast_chunk(q);
-            else if (256 * q > nC && 256 * q + 255 <= nC + nA && nC + nA - 256 * q < awhole)
+            else if (rq > nC && rq + 255 <= nC + nA && nC + nA - rq < awhole)
                 aad_chunk(q);
             else
                 slow_chunk(q);
@@ -476,13 +489,18 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
 }
 
 // One workgroup: folds the workgroups' partial sums with the factors
-// H^(4096 b), multiplies by H and forms (or checks) the tag.
+// H^(4096 b) into B, then one wave encrypts the head's ciphertext blocks
+// (the last head - 1 blocks, r = 1 .. head - 1), adds the head's positions
+// as sum_(r < head) X_r H^r (a tree over lanes, lane r holding X_r) to
+// H^head * B, multiplies by H and forms (or checks) the tag.
+template <int NR, bool DEC>
 __global__ __launch_bounds__(1024) void gcm_final_kernel(const GcmArgs a) {
-    constexpr uint32_t kMaxTabs = 9, kParts = kMaxTabs * kTabBytes + kMaxTabs * kVecBytes;
+    constexpr uint32_t kMaxTabs = 14, kParts = kMaxTabs * kTabBytes + kMaxTabs * kVecBytes;
     __shared__ uint32_t lds[(kParts + kGcmMaxGrid * 16) / 4];
-    // tables 0 .. lg-1 hold H^4096 .. H^(4096 * 2^(lg-1)), table lg holds H
+    // tables 0 .. lg-1 hold H^4096 .. H^(4096 * 2^(lg-1)), tables lg .. lg+5
+    // hold H, H^2, .. H^32
     const int lg = int(a.grid_log2);
-    build_tables(lds, 0, uint32_t(lg + 1) * kTabBytes, a.ws, lg + 1, [lg](int k) { return k < lg ? 12 + k : 0; });
+    build_tables(lds, 0, uint32_t(lg + 6) * kTabBytes, a.ws, lg + 6, [lg](int k) { return k < lg ? 12 + k : k - lg; });
     const uint32_t t = threadIdx.x, grid = 1u << a.grid_log2;
     if (t < kGcmMaxGrid) {
         u32x4 p = vec4(0, 0, 0, 0);
@@ -501,14 +519,74 @@ __global__ __launch_bounds__(1024) void gcm_final_kernel(const GcmArgs a) {
         }
         __syncthreads();
     }
+    if (t >= 64)
+        return;
+    const uint32_t hpow = uint32_t(lg) * kTabBytes;   // table of H^(2^k) is hpow + k * kTabBytes
+    const uint64_t nC = (a.nbytes + 15) >> 4, cwhole = a.nbytes >> 4;
+    const uint32_t head = uint32_t((nC + 1) & 63u), ctail = uint32_t(a.nbytes & 15u);
+    // lane r < head holds X_r: r = 0 the length block, else ciphertext block
+    // j = nC - r, encrypted here with counter count(J0) + 1 + j
+    uint32_t x[4] = {0, 0, 0, 0};
+    if (t == 0 && head > 0) {
+        const uint64_t abits = 8 * a.aad_bytes, cbits = 8 * a.nbytes;
+        x[0] = __builtin_bswap32(uint32_t(abits >> 32));
+        x[1] = __builtin_bswap32(uint32_t(abits));
+        x[2] = __builtin_bswap32(uint32_t(cbits >> 32));
+        x[3] = __builtin_bswap32(uint32_t(cbits));
+    } else if (t < head) {
+        const uint64_t j = nC - t;
+        uint32_t ks[4] = {a.ws->j0[0], a.ws->j0[1], a.ws->j0[2],
+                          __builtin_bswap32(__builtin_bswap32(a.ws->j0[3]) + 1u + uint32_t(j))};
+        encrypt_global<NR>(a.rk, ks);
+        const bool whole = j < cwhole;
+        const u32x4 v = whole ? load16(a.in + 16 * j) : load_tail(a.in + 16 * j, ctail);
+        const u32x4 o = vec4(v.x ^ ks[0], v.y ^ ks[1], v.z ^ ks[2], v.w ^ ks[3]);
+        if (whole)
+            store16(a.out + 16 * j, o);
+        else
+            store_tail(a.out + 16 * j, o, ctail);
+        const u32x4 c = DEC ? v : o;
+        x[0] = c.x;
+        x[1] = c.y;
+        x[2] = c.z;
+        x[3] = c.w;
+        if (!whole) {
+            // only the tail's bytes enter GHASH
+#pragma unroll
+            for (int w = 0; w < 4; w++) {
+                const int keep = int(ctail) - 4 * w;
+                x[w] &= keep >= 4 ? ~0u : keep <= 0 ? 0u : (1u << (8 * keep)) - 1u;
+            }
+        }
+    }
+    // sum_r X_r H^r over the lanes: lane l adds lane l + 2^k's sum times H^(2^k)
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        uint32_t v[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            v[c] = uint32_t(__shfl_down(int(x[c]), 1u << k, 64));
+        mul_tab(lds, hpow + uint32_t(k) * kTabBytes, v, v);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            x[c] ^= v[c];
+    }
+    // B * H^head, then the sum times H
+    const u32x4 o = lds_load16(lds, kParts);
+    uint32_t sum[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+        if ((head >> k) & 1u)
+            mul_tab(lds, hpow + uint32_t(k) * kTabBytes, sum, sum);
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+        sum[c] ^= x[c];
+    mul_tab(lds, hpow, sum, sum);
     if (t == 0) {
-        const u32x4 o = lds_load16(lds, kParts);
-        uint32_t sum[4] = {o.x, o.y, o.z, o.w};
-        mul_tab(lds, uint32_t(lg) * kTabBytes, sum, sum);
         uint8_t tag[16];
         for (int b = 0; b < 16; b++)
             tag[b] = uint8_t((sum[b >> 2] ^ a.ws->ej0[b >> 2]) >> (8 * (b & 3)));
-        if (a.decrypt) {
+        if (DEC) {
             uint32_t diff = 0;
             for (uint32_t b = 0; b < a.tag_bytes; b++)
                 diff |= uint32_t(tag[b] ^ a.tag_in[b]);
@@ -541,7 +619,14 @@ hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream) {
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(gcm_final_kernel, dim3(1), dim3(1024), 0, stream, a);
+    void (*fin)(const GcmArgs);
+    if (a.decrypt)
+        fin = nr == 10 ? gcm_final_kernel<10, true> : nr == 12 ? gcm_final_kernel<12, true>
+                                                               : gcm_final_kernel<14, true>;
+    else
+        fin = nr == 10 ? gcm_final_kernel<10, false> : nr == 12 ? gcm_final_kernel<12, false>
+                                                                : gcm_final_kernel<14, false>;
+    hipLaunchKernelGGL(fin, dim3(1), dim3(1024), 0, stream, a);
     return hipGetLastError();
 }
 

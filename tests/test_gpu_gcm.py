@@ -91,6 +91,33 @@ def test_gcm_matches_oracle(A, O, ws, bits, nbytes, aad_bytes):
     assert_same(back, pt, what + " decrypt")
 
 
+def test_gcm_every_head_length(A, O, ws):
+    """The last (nC + 1) mod 64 hash positions (the length block and the
+    ragged end of the ciphertext) are finished apart from the bulk, so that
+    the bulk's slots start on 1 KiB boundaries: every such count 0 .. 63,
+    with and without a partial last block, in both directions, and once
+    with enough blocks for several chunks per wave."""
+    rk, nr = A.aes_expand_key(seedgen.key(59, 0, 128))
+    iv = seedgen.nonce(59, 0)[:12]
+    aad = seedgen.data_np(59, 1, 37)
+    heads = set()
+    for nblk in list(range(700, 764)) + [(1 << 16) + 5, (1 << 16) + 62]:
+        for tail in (0, 9):
+            nbytes = 16 * nblk - (16 - tail if tail else 0)
+            nC = (nbytes + 15) // 16
+            heads.add((nC + 1) % 64)
+            pt = seedgen.data_np(59, nbytes, nbytes)
+            want_ct, want_tag = O.gcm_encrypt(rk, nr, iv, aad, pt)
+            ct, tag = gpu_encrypt(A, ws, rk, nr, iv, aad, pt)
+            what = "%d bytes" % nbytes
+            assert_same(ct, want_ct, what + " ciphertext")
+            assert_same(tag, want_tag, what + " tag")
+            back, ok = gpu_decrypt(A, ws, rk, nr, iv, aad, ct, tag)
+            assert ok == 1, what
+            assert_same(back, pt, what + " decrypt")
+    assert heads == set(range(64))
+
+
 @pytest.mark.parametrize("ivlen", [1, 8, 13, 16, 17, 60, 256])
 def test_gcm_iv_lengths(A, O, ws, ivlen):
     rk, nr = A.aes_expand_key(seedgen.key(52, ivlen, 128))
