@@ -197,20 +197,29 @@ const char *aes_last_error(void);
  * Launch configuration of the buffer kernels (ECB and CTR).  Exposed so
  * that a tuner can sweep it and tests can show the result does not depend
  * on it.  All fields 0 mean "the library's choice".
- *   layout            0 = four round tables, 32 copies each, in LDS;
+ *   layout            0 = four round tables, 32 copies each, in LDS
+ *                         (128 KiB);
  *                     1 = two round tables, 64 copies each (the other two
- *                         are rotations of them);
+ *                         are rotations of them; 128 KiB);
  *                     2 = bitsliced: no tables, 32 blocks per lane as 128
  *                         bit-planes, S-box as a Boolean circuit (constant
  *                         time; encryption only: ECB decryption with this
- *                         layout returns AES_E_ARG).
+ *                         layout returns AES_E_ARG);
+ *                     3 = one round table, 64 copies (the other three are
+ *                         its rotations; 64 KiB, so two 1024-thread
+ *                         workgroups share a compute unit);
+ *                     4 = four round tables, one copy each (4 KiB, with
+ *                         LDS bank conflicts).
+ *                     Decryption adds a 32 KiB inverse S-box to each.
  *   blocks_per_thread 1, 2 or 4 16-byte blocks in flight per thread (table
  *                     layouts; the bitsliced layout always carries 32).
  *   wg_size           256, 512 or 1024 threads per workgroup (table layouts;
  *                     the bitsliced layout uses 256).
  *   grid              workgroups launched (each loops over the buffer); 0 =
- *                     one per compute unit (two for the bitsliced layout,
- *                     two waves per SIMD), fewer for small buffers.
+ *                     as many as fit on every compute unit at once (their
+ *                     LDS and registers; two per compute unit for the
+ *                     bitsliced layout, two waves per SIMD), fewer for small
+ *                     buffers.
  */
 typedef struct {
     int layout;

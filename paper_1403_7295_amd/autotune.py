@@ -7,11 +7,14 @@ workgroup size, or the bitsliced kernel) with HIP events on the current
 stream, keeps the fastest, and installs the result in the library with
 aes_set_tuned.  For batches it times the split granularity (the block
 multiple on which a wave's share of a message starts and ends) on a ragged
-multi-message workload.  Results are saved as JSON keyed
-by the GPU's architecture and compute-unit count; the binding installs the
-committed table for gfx950 when it is imported.
+multi-message workload.  Every candidate is timed per launch with HIP
+events and scored by its median launch.  The table (the winning entries
+and the batch split, keyed by the GPU's architecture and compute-unit
+count) is saved as JSON; the binding installs the committed table for
+gfx950 when it is imported.  The raw sweep goes to a separate file
+(--log), not into the table.
 
-    python -m paper_1403_7295_amd.autotune --out paper_1403_7295_amd/tuned_gfx950.json
+    python -m paper_1403_7295_amd.autotune --out paper_1403_7295_amd/tuned_gfx950.json --log sweep.json
 """
 import argparse
 import json
@@ -24,8 +27,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tuned_gfx950.json")
 
+# table layouts: 0 four tables x 32 copies, 1 two x 64, 3 one x 64 with
+# rotations (two workgroups per compute unit), 4 four unreplicated tables
 TABLE_CANDIDATES = [dict(layout=l, blocks_per_thread=b, wg_size=w, grid=0)
-                    for l in (0, 1) for b in (1, 2, 4) for w in (512, 1024)]
+                    for l in (0, 1, 3, 4) for b in (1, 2, 4) for w in (256, 512, 1024)]
 BITSLICED = dict(layout=2, blocks_per_thread=0, wg_size=0, grid=0)
 # (label, mode, decrypt)
 OPS = (("ecb_enc", "ecb", 0), ("ecb_dec", "ecb", 1), ("ctr", "ctr", 0))
@@ -35,17 +40,20 @@ SPLIT_CANDIDATES = (128, 256, 512, 1024)
 
 
 def _time(torch, fn, reps, warm=2):
+    """Median launch time in seconds over `reps` launches, each between its
+    own pair of HIP events (after `warm` untimed ones)."""
     s = torch.cuda.current_stream()
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(s)
-    for _ in range(reps):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(s)
         fn()
-    b.record(s)
+        b.record(s)
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps / 1e3
+    t = sorted(a.elapsed_time(b) / 1e3 for a, b in evs)
+    return t[len(t) // 2]
 
 
 def tune_plain(A, torch, nrs=(10, 12, 14), buckets=BUCKETS, verbose=False):
@@ -64,7 +72,7 @@ def tune_plain(A, torch, nrs=(10, 12, 14), buckets=BUCKETS, verbose=False):
                 fn = A.aes_decrypt if dec else A.aes_encrypt
                 cands = TABLE_CANDIDATES + ([] if (mode == "ecb" and dec) else [BITSLICED])
                 for size, min_bytes in buckets:
-                    reps = max(3, min(200, (1 << 28) // size))
+                    reps = max(7, min(200, (1 << 28) // size))
                     best = None
                     for cfg in cands:
                         A.aes_set_launch(cfg)
@@ -131,6 +139,7 @@ def apply(A, table):
 def main():
     ap = argparse.ArgumentParser(description="tune launch configurations on this GPU")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--log", default=None, help="where to write every measurement of the sweep")
     ap.add_argument("--nr", type=int, nargs="*", default=[10, 12, 14])
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
@@ -143,20 +152,25 @@ def main():
     t0 = time.time()
     if args.batch_only:
         table = load(DEFAULT_TABLE)
-        table["batch_tile_blocks"], table["batch_measurements"] = tune_batch(A, torch, verbose=True)
+        table["batch_tile_blocks"], blog = tune_batch(A, torch, verbose=True)
         save(args.out or DEFAULT_TABLE, table)
+        if args.log:
+            save(args.log, {"batch": blog})
         print("batch_tile_blocks", table["batch_tile_blocks"])
         return
     entries, log = tune_plain(A, torch, tuple(args.nr), verbose=True)
-    table = {"device": device_key(torch), "entries": entries, "measurements": log}
+    table = {"device": device_key(torch), "entries": entries}
+    sweep = {"plain": log}
     if not args.no_batch:
         split, blog = tune_batch(A, torch, verbose=True)
         table["batch_tile_blocks"] = split
-        table["batch_measurements"] = blog
+        sweep["batch"] = blog
     table["seconds"] = round(time.time() - t0, 1)
     if args.out:
         save(args.out, table)
-    print(json.dumps({k: v for k, v in table.items() if "measurements" not in k}, indent=1))
+    if args.log:
+        save(args.log, sweep)
+    print(json.dumps(table, indent=1))
 
 
 if __name__ == "__main__":

@@ -91,7 +91,8 @@ aes_launch g_launch = {0, 0, 0, 0};
 bool g_launch_set = false;
 
 bool valid_launch(const aes_launch &c) {
-    return (c.layout == 0 || c.layout == 1 || c.layout == LAYOUT_BITSLICED) &&
+    return (c.layout == LAYOUT_T4X32 || c.layout == LAYOUT_T2X64 || c.layout == LAYOUT_BITSLICED ||
+            c.layout == LAYOUT_T1X64 || c.layout == LAYOUT_T4X1) &&
            (c.blocks_per_thread == 0 || c.blocks_per_thread == 1 || c.blocks_per_thread == 2 ||
             c.blocks_per_thread == 4) &&
            (c.wg_size == 0 || c.wg_size == 256 || c.wg_size == 512 || c.wg_size == 1024) &&
@@ -100,7 +101,10 @@ bool valid_launch(const aes_launch &c) {
 
 std::vector<aes_tuned_entry> g_tuned;  // guarded by g_launch_mu
 
-LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes, int mode, int decrypt, int nr) {
+// mode and decrypt pick the tuned entry (AES_MODE_ECB or _CTR); kmode is the
+// kernel that will run (MODE_ECB, MODE_CTR or MODE_CBC), whose occupancy sets
+// the default grid.
+LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes, int mode, int decrypt, int nr, int kmode) {
     aes_launch o;
     bool set;
     {
@@ -135,10 +139,12 @@ LaunchCfg choose_launch(const DeviceState &d, uint64_t nbytes, int mode, int dec
         c.grid = int(grid < 1 ? 1 : grid > 0x7fffffff ? 0x7fffffff : grid);
         return c;
     }
-    // The round tables fill most of the LDS, so one workgroup runs per
-    // compute unit; a persistent grid of one workgroup per CU sweeps the
-    // buffer.  Small buffers get only as many workgroups as they can keep busy.
-    uint64_t grid = set && o.grid ? uint64_t(o.grid) : uint64_t(d.cus);
+    // A persistent grid of as many workgroups as fit on every compute unit
+    // at once (the 128 KiB table layouts: one; the 64 KiB one: two of 1024
+    // threads) sweeps the buffer.  Small buffers get only as many workgroups
+    // as they can keep busy.
+    const uint64_t per_cu = uint64_t(cipher_groups_per_cu(nr, kmode, decrypt ? DIR_DEC : DIR_ENC, c.layout, c.bpt, c.wg));
+    uint64_t grid = set && o.grid ? uint64_t(o.grid) : uint64_t(d.cus) * per_cu;
     const uint64_t nblk = (nbytes + 15) / 16;
     const uint64_t per_wg = uint64_t(c.wg) * c.bpt;
     const uint64_t useful = (nblk + per_wg - 1) / per_wg;
@@ -220,7 +226,8 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
         return AES_OK;
     }
     // CBC decryption has the shape of ECB decryption and shares its tuning
-    const LaunchCfg cfg = choose_launch(*d, nbytes, mode == AES_MODE_CBC ? AES_MODE_ECB : mode, dec_cipher, Nr);
+    const int kmode = mode == AES_MODE_CTR ? MODE_CTR : mode == AES_MODE_CBC ? MODE_CBC : MODE_ECB;
+    const LaunchCfg cfg = choose_launch(*d, nbytes, mode == AES_MODE_CBC ? AES_MODE_ECB : mode, dec_cipher, Nr, kmode);
     if (cfg.layout == LAYOUT_BITSLICED) {
         if (dec_cipher)
             return fail(AES_E_ARG, "the bitsliced kernel encrypts only (ECB encrypt, CTR)");
@@ -230,8 +237,7 @@ int crypt(int decrypt, const void *in, void *out, size_t nbytes, const uint8_t *
             return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
         return AES_OK;
     }
-    e = launch_cipher(Nr, mode == AES_MODE_CTR ? MODE_CTR : mode == AES_MODE_CBC ? MODE_CBC : MODE_ECB,
-                      dec_cipher ? DIR_DEC : DIR_ENC, cfg, a, static_cast<hipStream_t>(stream));
+    e = launch_cipher(Nr, kmode, dec_cipher ? DIR_DEC : DIR_ENC, cfg, a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     return AES_OK;
@@ -508,7 +514,8 @@ int aes_get_launch(size_t nbytes, int mode, int decrypt, int Nr, aes_launch *cfg
     const DeviceState *d = current_device(&st);
     if (!d)
         return st;
-    const LaunchCfg c = choose_launch(*d, nbytes, mode, decrypt && mode == AES_MODE_ECB, Nr);
+    const LaunchCfg c = choose_launch(*d, nbytes, mode, decrypt && mode == AES_MODE_ECB, Nr,
+                                      mode == AES_MODE_CTR ? MODE_CTR : MODE_ECB);
     cfg->layout = c.layout;
     cfg->blocks_per_thread = c.bpt;
     cfg->wg_size = c.wg;

@@ -2,12 +2,17 @@
 // CTR over one buffer, for Nr = 10, 12, 14, plus the plain copy kernel the
 // measurements are calibrated with.  The round code is in cipher_core.h.
 //
-// The grid is persistent: a fixed number of workgroups (one per compute
-// unit by default: the round tables fill most of the LDS) sweeps the buffer,
-// so the tables are staged into LDS once per workgroup, not once per tile.
+// The grid is persistent: a fixed number of workgroups (as many as fit on
+// every compute unit at once: one for the 128 KiB table layouts, two for the
+// 64 KiB one) sweeps the buffer, so the tables are staged into LDS once per
+// workgroup, not once per tile.
 // Lane l of a wave owns blocks base + 64*i + l, so every 16-byte load and
 // store instruction of a wave covers 1 KiB of contiguous memory.
 #include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "cipher_core.h"
 #include "internal.h"
@@ -17,7 +22,7 @@ namespace {
 
 template <int NR, int MODE, int DIR, int LAYOUT, int BPT>
 __global__ __launch_bounds__(1024) void cipher_kernel(const CipherArgs a) {
-    __shared__ uint32_t lds[lds_words<DIR>()];
+    __shared__ uint32_t lds[lds_words<DIR, LAYOUT>()];
     stage_tables<LAYOUT, DIR>(lds);
     __syncthreads();
 
@@ -78,7 +83,9 @@ KernelFn pick_bpt(int bi) {
 template <int NR, int MODE, int DIR>
 KernelFn pick_layout(int layout, int bi) {
     return layout == LAYOUT_T4X32 ? pick_bpt<NR, MODE, DIR, LAYOUT_T4X32>(bi)
-                                  : pick_bpt<NR, MODE, DIR, LAYOUT_T2X64>(bi);
+         : layout == LAYOUT_T2X64 ? pick_bpt<NR, MODE, DIR, LAYOUT_T2X64>(bi)
+         : layout == LAYOUT_T1X64 ? pick_bpt<NR, MODE, DIR, LAYOUT_T1X64>(bi)
+                                  : pick_bpt<NR, MODE, DIR, LAYOUT_T4X1>(bi);
 }
 
 template <int NR>
@@ -91,16 +98,37 @@ KernelFn pick_op(int mode, int dir, int layout, int bi) {
                           : pick_layout<NR, MODE_ECB, DIR_DEC>(layout, bi);
 }
 
+KernelFn cipher_fn(int nr, int mode, int dir, int layout, int bpt) {
+    const int bi = bpt == 1 ? 0 : bpt == 2 ? 1 : 2;
+    return nr == 10 ? pick_op<10>(mode, dir, layout, bi)
+         : nr == 12 ? pick_op<12>(mode, dir, layout, bi)
+                    : pick_op<14>(mode, dir, layout, bi);
+}
+
 }  // namespace
 
 hipError_t upload_tables(const HostTables &t) { return upload_base_tables(t); }
 
+int cipher_groups_per_cu(int nr, int mode, int dir, int layout, int bpt, int wg) {
+    // what the kernel's LDS array and registers allow, asked of the runtime
+    // once per kernel and workgroup size
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> known;
+    const void *fn = reinterpret_cast<const void *>(cipher_fn(nr, mode, dir, layout, bpt));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find({fn, wg});
+    if (it != known.end())
+        return it->second;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, wg, 0) != hipSuccess || n < 1)
+        n = 1;
+    known[{fn, wg}] = n;
+    return n;
+}
+
 hipError_t launch_cipher(int nr, int mode, int dir, const LaunchCfg &cfg, const CipherArgs &a,
                          hipStream_t stream) {
-    const int bi = cfg.bpt == 1 ? 0 : cfg.bpt == 2 ? 1 : 2;
-    KernelFn fn = nr == 10 ? pick_op<10>(mode, dir, cfg.layout, bi)
-                : nr == 12 ? pick_op<12>(mode, dir, cfg.layout, bi)
-                           : pick_op<14>(mode, dir, cfg.layout, bi);
+    KernelFn fn = cipher_fn(nr, mode, dir, cfg.layout, cfg.bpt);
     hipLaunchKernelGGL(fn, dim3(cfg.grid), dim3(cfg.wg), 0, stream, a);
     return hipGetLastError();
 }

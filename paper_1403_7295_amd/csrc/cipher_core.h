@@ -29,8 +29,17 @@
 //   layout T4X32: four tables, 32 copies;  addr = pair<<16 | x<<8 | (t&1)<<7 | (lane&31)<<2
 //   layout T2X64: two tables (T0, T1), 64 copies; addr = t<<16 | x<<8 | lane<<2,
 //                 and T2, T3 are T0, T1 rotated by 16 bits.
-// Both use 128 KiB.  Decryption adds the inverse S-box for the last round
-// (32 copies, 32 KiB at 0x20000), so a decryption workgroup uses all 160 KiB.
+//   layout T1X64: T0 alone, 64 copies;  addr = x<<8 | lane<<2, and T1, T2, T3
+//                 are T0 rotated by 8, 16, 24 bits (three rotations per
+//                 column): 64 KiB, so two 1024-thread workgroups fit on a
+//                 compute unit.
+//   layout T4X1:  four tables, one copy each (4 KiB, no replication):
+//                 addr = t<<10 | x<<2; lanes collide on banks whenever their
+//                 bytes agree modulo the bank count.
+// T4X32 and T2X64 use 128 KiB.  Decryption adds the inverse S-box for the
+// last round (32 copies, 32 KiB) after the round tables: at 0x20000 (a
+// decryption workgroup then uses all 160 KiB), 0x10000 for T1X64 and 0x1000
+// for T4X1.
 // The last encryption round reads S[x] out of the round tables (byte 2 of
 // T0[x] and byte 3 of T1[x] are S[x]) and assembles the column with two
 // v_perm_b32.
@@ -49,9 +58,15 @@ static __device__ uint32_t g_base[768];
 
 namespace {
 
-constexpr uint32_t kTableWords = 32768;       // 128 KiB of round tables
 constexpr uint32_t kInvSboxWords = 8192;      // 32 KiB: inverse S-box, 32 copies
-constexpr uint32_t kInvSboxAddr = 0x20000;
+
+// Words of round tables, and the byte address of the inverse S-box after them.
+template <int LAYOUT>
+constexpr uint32_t table_words() {
+    return LAYOUT == LAYOUT_T1X64 ? 16384u : LAYOUT == LAYOUT_T4X1 ? 1024u : 32768u;
+}
+template <int LAYOUT>
+constexpr uint32_t inv_sbox_addr() { return table_words<LAYOUT>() * 4u; }
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // a ^ b ^ c in one VALU op
@@ -87,13 +102,29 @@ __device__ __forceinline__ LaneConsts lane_consts(uint32_t lane) {
     if (LAYOUT == LAYOUT_T4X32) {
         for (int t = 0; t < 4; t++)
             c.t[t] = ((lane & 31u) << 2) | (uint32_t(t & 1) << 7) | (uint32_t(t >> 1) << 8);
-    } else {
+    } else if (LAYOUT == LAYOUT_T2X64) {
         for (int t = 0; t < 4; t++)
             c.t[t] = (lane << 2) | (uint32_t(t & 1) << 8);
+    } else if (LAYOUT == LAYOUT_T1X64) {
+        for (int t = 0; t < 4; t++)
+            c.t[t] = lane << 2;
+    } else {
+        for (int t = 0; t < 4; t++)
+            c.t[t] = uint32_t(t) << 10;   // the table's base address
     }
-    // (x<<8 | (lane&31)<<3 | 0x40000) >> 1 = 0x20000 | x<<7 | (lane&31)<<2
-    c.isb = ((lane & 31u) << 3) | (4u << 8);
+    // inverse S-box, 32 copies after the round tables: the address is built
+    // as (x<<8 | (lane&31)<<3 | base<<1) and halved, giving
+    // base | x<<7 | (lane&31)<<2 (base<<1 sits in byte 2 for the 64 and 128
+    // KiB layouts; for T4X1 the table's base is added after halving)
+    constexpr uint32_t base = inv_sbox_addr<LAYOUT>();
+    c.isb = ((lane & 31u) << 3) | (LAYOUT == LAYOUT_T4X1 ? 0u : (base >> 15) << 8);
     return c;
+}
+
+// Byte address of entry (byte K of w) of physical table T in the unreplicated layout.
+template <int K>
+__device__ __forceinline__ uint32_t flat_addr(uint32_t w, uint32_t table_base) {
+    return table_base | (((w >> (8 * K)) & 255u) << 2);
 }
 
 // Logical table T (0..3) looked up with byte K of w.
@@ -101,14 +132,31 @@ template <int LAYOUT, int T, int K>
 __device__ __forceinline__ uint32_t tl(const uint32_t *lds, const LaneConsts &lc, uint32_t w) {
     if (LAYOUT == LAYOUT_T4X32) {
         return lds_word(lds, entry_addr<K>(w, lc.t[T]));
-    } else {
+    } else if (LAYOUT == LAYOUT_T2X64) {
         uint32_t v = lds_word(lds, entry_addr<K>(w, lc.t[T & 1]));
         return (T >> 1) ? rotl(v, 16) : v;
+    } else if (LAYOUT == LAYOUT_T1X64) {
+        return rotl(lds_word(lds, entry_addr<K>(w, lc.t[0])), 8 * T);
+    } else {
+        return lds_word(lds, flat_addr<K>(w, lc.t[T]));
     }
 }
 
-template <int K>
+// The entry of the row-0 table (T0, or Td0 in the decryption layouts)
+// looked up with byte K of w, unrotated; T1 is its rotation by 8 bits.
+template <int LAYOUT, int K>
+__device__ __forceinline__ uint32_t t0_entry(const uint32_t *lds, const LaneConsts &lc, uint32_t w) {
+    return LAYOUT == LAYOUT_T4X1 ? lds_word(lds, flat_addr<K>(w, lc.t[0])) : lds_word(lds, entry_addr<K>(w, lc.t[0]));
+}
+template <int LAYOUT, int K>
+__device__ __forceinline__ uint32_t t1_entry(const uint32_t *lds, const LaneConsts &lc, uint32_t w) {
+    return LAYOUT == LAYOUT_T4X1 ? lds_word(lds, flat_addr<K>(w, lc.t[1])) : lds_word(lds, entry_addr<K>(w, lc.t[1]));
+}
+
+template <int LAYOUT, int K>
 __device__ __forceinline__ uint32_t inv_sbox_word(const uint32_t *lds, const LaneConsts &lc, uint32_t w) {
+    if (LAYOUT == LAYOUT_T4X1)
+        return lds_word(lds, inv_sbox_addr<LAYOUT>() + (entry_addr<K>(w, lc.isb) >> 1));
     return lds_word(lds, entry_addr<K>(w, lc.isb) >> 1);
 }
 
@@ -117,7 +165,7 @@ __device__ __forceinline__ uint32_t inv_sbox_word(const uint32_t *lds, const Lan
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t round_col(const uint32_t *lds, const LaneConsts &lc, uint32_t a,
                                               uint32_t b, uint32_t c, uint32_t d, uint32_t k) {
-    if (LAYOUT == LAYOUT_T4X32) {
+    if (LAYOUT == LAYOUT_T4X32 || LAYOUT == LAYOUT_T1X64 || LAYOUT == LAYOUT_T4X1) {
         return xor3(tl<LAYOUT, 0, 0>(lds, lc, a), tl<LAYOUT, 1, 1>(lds, lc, b),
                     xor3(tl<LAYOUT, 2, 2>(lds, lc, c), tl<LAYOUT, 3, 3>(lds, lc, d), k));
     } else {
@@ -131,22 +179,29 @@ __device__ __forceinline__ uint32_t round_col(const uint32_t *lds, const LaneCon
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t final_enc_col(const uint32_t *lds, const LaneConsts &lc, uint32_t a,
                                                   uint32_t b, uint32_t c, uint32_t d, uint32_t k) {
-    // physical tables 0 and 1 are T0 and T1 in both layouts
-    uint32_t ea = lds_word(lds, entry_addr<0>(a, lc.t[0]));
-    uint32_t eb = lds_word(lds, entry_addr<1>(b, lc.t[1]));
-    uint32_t ec = lds_word(lds, entry_addr<2>(c, lc.t[0]));
-    uint32_t ed = lds_word(lds, entry_addr<3>(d, lc.t[1]));
+    // physical tables 0 and 1 are T0 and T1 (T1X64: table 0 is T0 for all)
+    uint32_t ea = t0_entry<LAYOUT, 0>(lds, lc, a);
+    uint32_t eb = t1_entry<LAYOUT, 1>(lds, lc, b);
+    uint32_t ec = t0_entry<LAYOUT, 2>(lds, lc, c);
+    uint32_t ed = t1_entry<LAYOUT, 3>(lds, lc, d);
+    if (LAYOUT == LAYOUT_T1X64) {
+        // S from byte 2 of every T0 entry
+        uint32_t lo = __builtin_amdgcn_perm(ea, eb, 0x0C0C0206u);
+        uint32_t hi = __builtin_amdgcn_perm(ec, ed, 0x02060C0Cu);
+        return xor3(lo, hi, k);
+    }
     uint32_t lo = __builtin_amdgcn_perm(ea, eb, 0x0C0C0306u);  // S from byte 2 of T0, byte 3 of T1
     uint32_t hi = __builtin_amdgcn_perm(ec, ed, 0x03060C0Cu);
     return xor3(lo, hi, k);
 }
 
+template <int LAYOUT>
 __device__ __forceinline__ uint32_t final_dec_col(const uint32_t *lds, const LaneConsts &lc, uint32_t a,
                                                   uint32_t b, uint32_t c, uint32_t d, uint32_t k) {
-    uint32_t ea = inv_sbox_word<0>(lds, lc, a);
-    uint32_t eb = inv_sbox_word<1>(lds, lc, b);
-    uint32_t ec = inv_sbox_word<2>(lds, lc, c);
-    uint32_t ed = inv_sbox_word<3>(lds, lc, d);
+    uint32_t ea = inv_sbox_word<LAYOUT, 0>(lds, lc, a);
+    uint32_t eb = inv_sbox_word<LAYOUT, 1>(lds, lc, b);
+    uint32_t ec = inv_sbox_word<LAYOUT, 2>(lds, lc, c);
+    uint32_t ed = inv_sbox_word<LAYOUT, 3>(lds, lc, d);
     uint32_t lo = __builtin_amdgcn_perm(ea, eb, 0x0C0C0104u);
     uint32_t hi = __builtin_amdgcn_perm(ec, ed, 0x03060C0Cu);
     return xor3(lo, hi, k);
@@ -186,10 +241,10 @@ __device__ __forceinline__ void rounds(uint32_t (&s)[BPT][4], const uint32_t *ld
             s[i][2] = final_enc_col<LAYOUT>(lds, lc, a2, a3, a0, a1, k2);
             s[i][3] = final_enc_col<LAYOUT>(lds, lc, a3, a0, a1, a2, k3);
         } else {
-            s[i][0] = final_dec_col(lds, lc, a0, a3, a2, a1, k0);
-            s[i][1] = final_dec_col(lds, lc, a1, a0, a3, a2, k1);
-            s[i][2] = final_dec_col(lds, lc, a2, a1, a0, a3, k2);
-            s[i][3] = final_dec_col(lds, lc, a3, a2, a1, a0, k3);
+            s[i][0] = final_dec_col<LAYOUT>(lds, lc, a0, a3, a2, a1, k0);
+            s[i][1] = final_dec_col<LAYOUT>(lds, lc, a1, a0, a3, a2, k1);
+            s[i][2] = final_dec_col<LAYOUT>(lds, lc, a2, a1, a0, a3, k2);
+            s[i][3] = final_dec_col<LAYOUT>(lds, lc, a3, a2, a1, a0, k3);
         }
     }
 }
@@ -236,18 +291,27 @@ __device__ __forceinline__ u32x4 vec4(uint32_t a, uint32_t b, uint32_t c, uint32
 template <int LAYOUT, int DIR>
 __device__ __forceinline__ void stage_tables(uint32_t *lds) {
     const uint32_t *base = g_base + (DIR == DIR_ENC ? 0 : 256);
-    for (uint32_t i = 4 * threadIdx.x; i < kTableWords; i += 4 * blockDim.x) {
-        // word index i = table<<14 | x<<6 | copy (T2X64) or
-        //                pair<<14 | x<<6 | (t&1)<<5 | copy (T4X32)
-        const uint32_t x = (i >> 6) & 255u;
-        const uint32_t t = (LAYOUT == LAYOUT_T4X32) ? (((i >> 14) << 1) | ((i >> 5) & 1u)) : (i >> 14);
+    for (uint32_t i = 4 * threadIdx.x; i < table_words<LAYOUT>(); i += 4 * blockDim.x) {
+        // word index i = table<<14 | x<<6 | copy (T2X64),
+        //                pair<<14 | x<<6 | (t&1)<<5 | copy (T4X32),
+        //                x<<6 | copy (T1X64), table<<8 | x (T4X1)
+        uint32_t x, t;
+        if (LAYOUT == LAYOUT_T4X1) {
+            x = i & 255u;
+            t = i >> 8;
+            *reinterpret_cast<u32x4 *>(lds + i) = vec4(rotl(base[x], 8 * int(t)), rotl(base[x + 1], 8 * int(t)),
+                                                        rotl(base[x + 2], 8 * int(t)), rotl(base[x + 3], 8 * int(t)));
+            continue;
+        }
+        x = (i >> 6) & 255u;
+        t = LAYOUT == LAYOUT_T4X32 ? (((i >> 14) << 1) | ((i >> 5) & 1u)) : LAYOUT == LAYOUT_T2X64 ? (i >> 14) : 0u;
         const uint32_t v = rotl(base[x], 8 * int(t));
         *reinterpret_cast<u32x4 *>(lds + i) = vec4(v, v, v, v);
     }
     if (DIR == DIR_DEC) {
         for (uint32_t i = 4 * threadIdx.x; i < kInvSboxWords; i += 4 * blockDim.x) {
             const uint32_t v = g_base[512 + (i >> 5)];
-            *reinterpret_cast<u32x4 *>(lds + (kInvSboxAddr >> 2) + i) = vec4(v, v, v, v);
+            *reinterpret_cast<u32x4 *>(lds + (inv_sbox_addr<LAYOUT>() >> 2) + i) = vec4(v, v, v, v);
         }
     }
 }
@@ -471,9 +535,9 @@ __device__ __forceinline__ void cbc_encrypt_serial(const uint32_t *lds, const La
     }
 }
 
-template <int DIR>
+template <int DIR, int LAYOUT = LAYOUT_T4X32>
 constexpr uint32_t lds_words() {
-    return DIR == DIR_DEC ? kTableWords + kInvSboxWords : kTableWords;
+    return DIR == DIR_DEC ? table_words<LAYOUT>() + kInvSboxWords : table_words<LAYOUT>();
 }
 
 }  // namespace

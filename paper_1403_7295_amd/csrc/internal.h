@@ -34,7 +34,8 @@ constexpr uint64_t kCtrMaxBytes = uint64_t(1) << 36;
 // ---- kernels (aes_kernels.hip) --------------------------------------------
 enum Mode { MODE_ECB = 0, MODE_CTR = 1, MODE_CBC = 2 };
 enum Dir { DIR_ENC = 0, DIR_DEC = 1 };
-enum Layout { LAYOUT_T4X32 = 0, LAYOUT_T2X64 = 1 };
+// Table layouts in LDS (2 is the bitsliced kernel, which has no tables).
+enum Layout { LAYOUT_T4X32 = 0, LAYOUT_T2X64 = 1, LAYOUT_T1X64 = 3, LAYOUT_T4X1 = 4 };
 
 // Everything one launch of a buffer kernel needs; passed by value, so the
 // round keys and counter land in scalar registers.
@@ -59,6 +60,9 @@ hipError_t upload_tables(const HostTables &t);
 
 hipError_t launch_cipher(int nr, int mode, int dir, const LaunchCfg &cfg, const CipherArgs &a,
                          hipStream_t stream);
+// Workgroups of `wg` threads of that buffer kernel that fit on one compute
+// unit at once (its LDS array and registers), as the runtime reports it.
+int cipher_groups_per_cu(int nr, int mode, int dir, int layout, int bpt, int wg);
 hipError_t launch_copy(const void *in, void *out, uint64_t nbytes, int grid, hipStream_t stream);
 // The LDS gather calibration kernel (lds_gather.hip): grid workgroups of 16 waves.
 using LdsGatherStat = aes_lds_gather_stat;

@@ -157,11 +157,12 @@ def test_gcm_argument_checks(A):
 
 
 def test_launch_config_validation(A):
-    for bad in ({"layout": 3}, {"blocks_per_thread": 3}, {"wg_size": 100}, {"grid": -1}):
+    for bad in ({"layout": 5}, {"layout": -1}, {"blocks_per_thread": 3}, {"wg_size": 100}, {"grid": -1}):
         with pytest.raises(A.AESError) as e:
             A.aes_set_launch(bad)
         assert e.value.code == A.AES_E_ARG
-    A.aes_set_launch({"layout": 1, "blocks_per_thread": 4, "wg_size": 512, "grid": 3})
+    for layout in (0, 1, 2, 3, 4):
+        A.aes_set_launch({"layout": layout, "blocks_per_thread": 4, "wg_size": 512, "grid": 3})
     A.aes_set_launch(None)
 
 

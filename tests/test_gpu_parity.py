@@ -130,8 +130,12 @@ def test_ctr_counter_wraps_without_carry(A, O):
     assert_same(got, O.ctr(rk, nr, ctr0, x), "CTR across the 2^32 wrap")
 
 
+# every table layout (four tables x 32 copies, two x 64, one x 64 with
+# rotations, four unreplicated), blocks per thread, workgroup size, and the
+# default grid (as many workgroups as fit per compute unit), one workgroup,
+# or seven
 LAUNCHES = [dict(layout=l, blocks_per_thread=b, wg_size=w, grid=g)
-            for l in (0, 1) for b in (1, 2, 4) for w in (256, 1024) for g in (0, 1, 7)]
+            for l in (0, 1, 3, 4) for b in (1, 2, 4) for w in (256, 1024) for g in (0, 1, 7)]
 
 
 @pytest.fixture(scope="module")
