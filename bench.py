@@ -291,9 +291,10 @@ def bench_sector_batch(torch, A, dev, stream, nmsg=65536, size=4096, reps=5):
     ivs = rng.integers(0, 256, (nmsg, 16), dtype=np.uint8)
     total = nmsg * size
     x = seedgen.data_torch(6, 0, total, dev)
-    y = torch.empty_like(x)
+    y = torch.empty(total + 16 * nmsg, dtype=torch.uint8, device=dev)   # GCM tags after the data
     res = {"workload": "%d messages of %d B, per-message AES-128 key and IV (XTS: key pair, one %d-byte data "
-                       "unit per message)" % (nmsg, size, size), "bytes": total}
+                       "unit per message; GCM: 96-bit IV, no additional data, 16-byte tag)" % (nmsg, size, size),
+           "bytes": total}
     xts = np.stack([A.xts_ctr0(m, nmsg + m, size) for m in range(nmsg)])
     for name, mode, dec, ctr0 in (("cbc_encrypt", "cbc", 0, ivs), ("cbc_decrypt", "cbc", 1, ivs),
                                   ("xts_encrypt", "xts", 0, xts)):
@@ -303,6 +304,14 @@ def bench_sector_batch(torch, A, dev, stream, nmsg=65536, size=4096, reps=5):
         b.close()
         res[name + "_GB/s"] = r["GB/s"]
         res[name + "_launch_us"] = r["launch_us"]
+    gcm = np.zeros(nmsg, A.GCM_DESC_DTYPE)
+    gcm["tag_off"] = total + 16 * np.arange(nmsg)
+    descs = A.make_descs(np.full(nmsg, size), keybits=128, mode="gcm", ctr0=ivs)
+    b = A.Batch(descs, keys, x, y, gcm=gcm)
+    r = leg(torch, stream, lambda: b.launch_graph(stream), total, reps, 2)
+    b.close()
+    res["gcm_encrypt_GB/s"] = r["GB/s"]
+    res["gcm_encrypt_launch_us"] = r["launch_us"]
     del x, y
     torch.cuda.empty_cache()
     return res
@@ -363,6 +372,24 @@ def bench_served(torch, A, dev, plain_ctr_gbs, nreq, warm=1000,
                        "p50_admit_wait_ms": round(float(np.percentile(m["admit_s"], 50)) * 1e3, 3),
                        "launches": st["launches"], "max_inflight_reqs": st["max_inflight_reqs"],
                        "fill_share_of_device_time": fill_share(st)})
+    # the same requests in GCM (no additional data; tags after the data) at
+    # half the CTR capacity
+    r = base.copy()
+    r["mode"] = A.AES_MODE_GCM
+    rate = 0.5 * capacity_gbs * 1e9 / mean
+    r["arrival_s"] = base["arrival_s"] / rate
+    res, st = srv.run(r)
+    m, rm = res[warm:], r[warm:]
+    t_first = float(rm["arrival_s"][0])
+    t_last = float((rm["arrival_s"] + m["latency_s"]).max())
+    gcm_point = {"mode": "GCM", "offered_load_of_ctr_capacity": 0.5, "arrival_rate_per_s": round(rate, 1),
+                 "completed_GB/s": round(float(rm["nbytes"].sum()) / (t_last - t_first) / 1e9, 1),
+                 "p50_ms": round(float(np.percentile(m["latency_s"], 50)) * 1e3, 3),
+                 "p99_ms": round(float(np.percentile(m["latency_s"], 99)) * 1e3, 3),
+                 "launches": st["launches"],
+                 "encryptions_tagged": int((res["authentic"][r["decrypt"] == 0] == 1).sum()),
+                 "decryptions_rejected": int((res["authentic"][r["decrypt"] == 1] == 0).sum()),
+                 "note": "decryptions of the random payloads must all fail authentication"}
     # the loop's own ceiling: every request 64 bytes and already waiting, so
     # admission, planning and completion are all there is to do
     r = base.copy()
@@ -378,7 +405,7 @@ def bench_served(torch, A, dev, plain_ctr_gbs, nreq, warm=1000,
                         "AES-128/256 50/50, per-request key and nonce, 8 GiB HBM budget, 4 streams",
             "requests_per_point": nreq, "warmup_requests": warm, "tile_blocks": cfg.tile_blocks,
             "capacity_GB/s": round(capacity_gbs, 1), "capacity": capacity, "points": points,
-            "max_admitted": loop_rate}
+            "gcm": gcm_point, "max_admitted": loop_rate}
 
 
 def main():

@@ -55,10 +55,12 @@ typedef enum {
 /* ECB and CTR: every block independent.  CBC (SP 800-38A section 6.2, one of
  * the modes after the paper's): decryption is block-parallel (each block
  * needs the previous ciphertext block); encryption is serial by definition
- * and runs on one lane per message.  XTS (IEEE 1619) is a mode of batch
- * descriptors only; single buffers use aes_xts_encrypt / aes_xts_decrypt
- * (aes_encrypt with AES_MODE_XTS is AES_E_MODE). */
-typedef enum { AES_MODE_ECB = 0, AES_MODE_CTR = 1, AES_MODE_CBC = 2, AES_MODE_XTS = 3 } aes_mode;
+ * and runs on one lane per message.  XTS (IEEE 1619) and GCM (SP 800-38D)
+ * are modes of batch descriptors (GCM also of served requests); single
+ * buffers use aes_xts_* / aes_gcm_* (aes_encrypt with AES_MODE_XTS or
+ * AES_MODE_GCM is AES_E_MODE). */
+typedef enum { AES_MODE_ECB = 0, AES_MODE_CTR = 1, AES_MODE_CBC = 2, AES_MODE_XTS = 3,
+               AES_MODE_GCM = 4 } aes_mode;
 
 /*
  * Key Expansion (FIPS-197 section 5.2; the paper's first step,
@@ -308,7 +310,10 @@ int aes_lds_gather(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int *
  * aes_xts_encrypt) use key_idx for the data key and ctr0 for the rest, all
  * little-endian: bytes 0..7 the tweak value of the message's first data
  * unit, 8..11 the key slot of the tweak key (same key size), 12..15 the
- * data-unit size in bytes (a power of two, 16 .. 4096).
+ * data-unit size in bytes (a power of two, 16 .. 4096).  GCM messages
+ * (any length up to 2^36 - 32 bytes) carry their 96-bit IV in ctr0[0..11]
+ * (J0 = IV || 0^31 || 1; ctr0[12..15] are ignored) and the rest in the
+ * batch's aes_gcm_desc array.
  */
 typedef struct {
     uint64_t in_off;
@@ -321,6 +326,33 @@ typedef struct {
     uint8_t reserved;
     uint8_t ctr0[16];
 } aes_msg_desc;
+
+/*
+ * The GCM part of batch message m (SP 800-38D): element m of an array
+ * parallel to the descriptors, 32 bytes each, device memory owned by the
+ * caller.  Entries of messages of other modes are not read.
+ *   aad_off, aad_bytes  the additional authenticated data: aad_bytes (up to
+ *                       2^36) at in_base + aad_off, a multiple of 16; it
+ *                       must not overlap the message's output.
+ *   tag_off             encryption: the 16-byte tag is written at
+ *                       out_base + tag_off; decryption: the expected tag is
+ *                       read from in_base + tag_off.  Inside the buffer, and
+ *                       not overlapping the message's output.
+ *   tag_bytes           decryption: how many leading tag bytes to compare
+ *                       (4, 8 or 12 .. 16); encryption: ignored.
+ *   ok                  written by the device after the batch: encryption 1;
+ *                       decryption 1 if the tag matches, else 0; 0 for a
+ *                       refused descriptor.  A decryption writes the
+ *                       plaintext whatever the verdict: a caller must not
+ *                       release it unless ok is 1.
+ */
+typedef struct {
+    uint64_t aad_off;
+    uint64_t aad_bytes;
+    uint64_t tag_off;
+    uint32_t tag_bytes;
+    int32_t ok;
+} aes_gcm_desc;
 
 /*
  * A batch.  Every pointer is a device pointer owned by the caller.
@@ -338,6 +370,10 @@ typedef struct {
  *                    message starts and ends on a multiple of this many
  *                    16-byte blocks (XTS: of whole data units), or at the
  *                    message's end; 0 = library choice (512).
+ *   gcm              the GCM fields of the messages (aes_gcm_desc, one per
+ *                    message slot, at least max_msgs of them), or NULL if
+ *                    the batch has no GCM message (a GCM descriptor is then
+ *                    refused).
  * The sequence is: on-device Key Expansion for every message (FIPS-197
  * section 5.2; the decryption schedule of section 5.3.5 where needed) and a
  * plan that puts the messages in three lists (encryption tables, inverse
@@ -345,7 +381,11 @@ typedef struct {
  * shares of work, one per wave, by cost (blocks times rounds): the paper's
  * chunking into one piece per processor, Section IV-A, across messages; then
  * persistent kernels, one workgroup per compute unit, in which every wave
- * runs its share.  A message with an invalid descriptor (bad key code or
+ * runs its share.  GCM messages run their CTR part (from J0 + 1) in the
+ * forward list; then their GHASH (section 6.4) over the additional data,
+ * the ciphertext and the lengths is cut into pieces of up to 16,384 blocks,
+ * one wave per piece (the pieces' sums are added by linearity), and a last
+ * kernel forms or checks each tag.  A message with an invalid descriptor (bad key code or
  * mode, ECB length not a multiple of 16, misaligned offset, outside the
  * buffers, input and output partly overlapping, key_idx >= nkeys) is
  * skipped and counted (aes_batch_query).
@@ -364,6 +404,7 @@ typedef struct {
     size_t workspace_bytes;
     int max_msgs;
     int tile_blocks;
+    aes_gcm_desc *gcm;
 } aes_batch;
 
 /* Workspace bytes for batches of up to max_msgs messages (any lengths).
@@ -426,7 +467,12 @@ int aes_batch_graph_destroy(void *graph);
  * (word i = mix64(seed + (i+1) * 0x9E3779B97F4A7C15), bytes little-endian),
  * written on the device when the request is launched: the synthetic stand-in
  * for data arriving over the network.  Key, mode, direction and counter are
- * as in aes_msg_desc.
+ * as in aes_msg_desc (modes ECB, CTR, CBC and GCM).  A GCM request (96-bit
+ * IV in ctr0[0..11], no additional data) has 16 more payload bytes (the
+ * next 16 of its stream, after the data rounded up to 16 bytes): the
+ * expected tag when decrypting; when encrypting, its tag is written at the
+ * same place after its output.  Each GCM buffer counts 16 more bytes
+ * against the budget.
  */
 typedef struct {
     double arrival_s;
@@ -478,7 +524,8 @@ typedef struct {
                            arena memory that overlaps this request's output
                            (its bytes at out_off are then no longer its
                            result), else 0 */
-    int reserved;
+    int authentic;      /* GCM: 1 if the tag was written (encryption) or
+                           matched (decryption), else 0; other modes: -1 */
 } aes_request_result;
 
 typedef struct {

@@ -32,8 +32,10 @@ AES_MODE_ECB = 0
 AES_MODE_CTR = 1
 AES_MODE_CBC = 2
 AES_MODE_XTS = 3      # batch descriptors only
+AES_MODE_GCM = 4      # batch descriptors and served requests only
 
-MODES = {"ecb": AES_MODE_ECB, "ctr": AES_MODE_CTR, "cbc": AES_MODE_CBC, "xts": AES_MODE_XTS}
+MODES = {"ecb": AES_MODE_ECB, "ctr": AES_MODE_CTR, "cbc": AES_MODE_CBC, "xts": AES_MODE_XTS,
+         "gcm": AES_MODE_GCM}
 
 # every function the header declares, with its ctypes signature
 _SIGNATURES = {
@@ -109,13 +111,19 @@ MSG_DESC_DTYPE = np.dtype([("in_off", "<u8"), ("out_off", "<u8"), ("nbytes", "<u
 assert MSG_DESC_DTYPE.itemsize == 48
 
 
+# aes_gcm_desc: the GCM fields of a batch message
+GCM_DESC_DTYPE = np.dtype([("aad_off", "<u8"), ("aad_bytes", "<u8"), ("tag_off", "<u8"),
+                           ("tag_bytes", "<u4"), ("ok", "<i4")])
+assert GCM_DESC_DTYPE.itemsize == 32
+
+
 class aes_batch(ctypes.Structure):
     _fields_ = [("desc", ctypes.c_void_p), ("nmsg", ctypes.c_int), ("d_nmsg", ctypes.c_void_p),
                 ("keys", ctypes.c_void_p), ("nkeys", ctypes.c_int),
                 ("in_base", ctypes.c_void_p), ("in_bytes", ctypes.c_uint64),
                 ("out_base", ctypes.c_void_p), ("out_bytes", ctypes.c_uint64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("max_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int)]
+                ("max_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int), ("gcm", ctypes.c_void_p)]
 
 
 # aes_request and aes_request_result, as numpy records
@@ -124,7 +132,7 @@ REQUEST_DTYPE = np.dtype([("arrival_s", "<f8"), ("nbytes", "<u8"), ("payload_see
                           ("decrypt", "u1"), ("reserved", "u1"), ("ctr0", "u1", (16,))])
 RESULT_DTYPE = np.dtype([("latency_s", "<f8"), ("admit_s", "<f8"), ("in_off", "<u8"),
                          ("out_off", "<u8"), ("status", "<i4"), ("launch", "<i4"),
-                         ("overwritten", "<i4"), ("reserved", "<i4")])
+                         ("overwritten", "<i4"), ("authentic", "<i4")])
 assert REQUEST_DTYPE.itemsize == 48 and RESULT_DTYPE.itemsize == 48
 
 
@@ -499,9 +507,11 @@ class Batch:
     descs      numpy MSG_DESC_DTYPE array (see make_descs)
     keys       numpy uint8 array (nkeys, 32): one key per 32-byte slot
     inp, out   device tensors the descriptors' offsets point into
+    gcm        numpy GCM_DESC_DTYPE array, one entry per message (GCM
+               messages' additional data and tags), or None
     """
 
-    def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None, device=None):
+    def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None, device=None, gcm=None):
         import torch
         self.device = device or inp.device
         _dev((inp, 0, "inp"), (out, 0, "out"))
@@ -523,15 +533,27 @@ class Batch:
                            out_base=out.data_ptr(), out_bytes=out.numel() * out.element_size(),
                            workspace=aligned, workspace_bytes=ws, max_msgs=self.max_msgs,
                            tile_blocks=self.tile_blocks)
+        self.d_gcm = None
+        if gcm is not None:
+            self.d_gcm = torch.zeros(self.max_msgs * GCM_DESC_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+            self.c.gcm = self.d_gcm.data_ptr()
         self.graph = None
-        self.set_descs(descs)
+        self.set_descs(descs, gcm=gcm)
 
-    def set_descs(self, descs, keys=None, stream=None):
-        """Rewrite the descriptors (and optionally the keys) in place."""
+    def set_descs(self, descs, keys=None, stream=None, gcm=None):
+        """Rewrite the descriptors (and optionally the keys and GCM fields) in place."""
         import torch
         descs = np.ascontiguousarray(descs, dtype=MSG_DESC_DTYPE)
         if len(descs) > self.max_msgs:
             raise ValueError("batch holds at most %d messages" % self.max_msgs)
+        if gcm is not None:
+            if self.d_gcm is None:
+                raise ValueError("this batch was made without GCM fields")
+            g = np.ascontiguousarray(gcm, dtype=GCM_DESC_DTYPE)
+            if len(g) != len(descs):
+                raise ValueError("one GCM entry per message")
+            graw = torch.from_numpy(g.view(np.uint8).reshape(-1).copy())
+            self.d_gcm[:graw.numel()].copy_(graw)
         raw = torch.from_numpy(descs.view(np.uint8).reshape(-1).copy())
         self.d_desc[:raw.numel()].copy_(raw)
         self.d_nmsg.fill_(len(descs))
@@ -542,6 +564,11 @@ class Batch:
 
     def run(self, stream=None):
         aes_batch_run(self.c, stream)
+
+    def gcm_results(self, n):
+        """The GCM fields of the first n messages as the device left them
+        (after the stream has run the batch): ok holds each verdict."""
+        return self.d_gcm[:n * GCM_DESC_DTYPE.itemsize].cpu().numpy().view(GCM_DESC_DTYPE).copy()
 
     def query(self, stream=None):
         return aes_batch_query(self.c, stream)
@@ -629,6 +656,11 @@ class Server:
         """The output bytes of one finished request (a view into the arena)."""
         o = int(result["out_off"])
         return self.scratch[o:o + int(nbytes)]
+
+    def tag(self, result, nbytes):
+        """The tag an encrypting GCM request wrote after its output."""
+        o = int(result["out_off"]) + (int(nbytes) + 15) // 16 * 16
+        return self.scratch[o:o + 16]
 
 
 def _install_tuned():

@@ -395,9 +395,13 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
     a->header = reinterpret_cast<BatchHeader *>(ws);
     a->keytab = reinterpret_cast<uint32_t *>(ws + sizeof(BatchHeader));
     a->items = reinterpret_cast<BatchItem *>(ws + items_off);
-    a->chunk_totals = reinterpret_cast<uint64_t *>(ws + items_off + 3 * size_t(b->max_msgs) * sizeof(BatchItem));
+    a->chunk_totals =
+        reinterpret_cast<uint64_t *>(ws + items_off + size_t(kBatchLists) * size_t(b->max_msgs) * sizeof(BatchItem));
     a->split_blocks = uint32_t(b->tile_blocks ? b->tile_blocks : kDefaultSplitBlocks);
     a->reject_flags = nullptr;
+    a->gcm = b->gcm;
+    if (reinterpret_cast<uintptr_t>(b->gcm) & 7u)
+        return fail(AES_E_ALIGN, "gcm must be 8-byte aligned");
     return AES_OK;
 }
 
@@ -594,7 +598,8 @@ int aes_batch_run(const aes_batch *b, void *stream) {
     if (!d)
         return st;
     // without a device-side count the host knows how many messages there are
-    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), 7u,
+    // the GHASH and tag kernels only if the batch can hold GCM messages
+    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 15u : 7u,
                                 a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -627,7 +632,8 @@ int aes_batch_run_noalloc(const aes_batch *b, void *stream) {
     st = batch_args(&w, &a);
     if (st != AES_OK)
         return st;
-    e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), 7u, a.d_nmsg ? a.max_msgs : a.nmsg);
+    e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 15u : 7u,
+                     a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     return AES_OK;
@@ -668,7 +674,8 @@ int aes_batch_graph_create(const aes_batch *b, void **graph) {
     if (e == hipSuccess)
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_batch(a, batch_grid(*d), s, 7u, a.max_msgs);   // the count may change per replay
+        // the count may change per replay
+        hipError_t le = launch_batch(a, batch_grid(*d), s, a.gcm ? 15u : 7u, a.max_msgs);
         e = hipStreamEndCapture(s, &g);
         if (le != hipSuccess)
             e = le;

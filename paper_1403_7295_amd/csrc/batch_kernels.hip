@@ -19,6 +19,14 @@
 //                   long lists, the second half of them taken off a counter)
 //                   with every message's round keys in scalar registers and
 //                   the same block loop as the single-buffer kernels.
+//   ghash_kernel    GCM messages only: GHASH (SP 800-38D section 6.4) over
+//                   each message's additional data, ciphertext and lengths,
+//                   cut into pieces of kGhashPiece positions, one wave per
+//                   piece with its own multiplier table in LDS; a piece's
+//                   sum, times the power of H its position calls for, is
+//                   XORed into the message's sum (GHASH is linear).
+//   gcm_tag_kernel  one lane per GCM message: the tag Cipher_K(J0) XOR the
+//                   sum, written (encryption) or compared (decryption).
 //
 // This is the paper's method (cut the data into one chunk per processor and
 // process the chunks in parallel, Section IV) applied across messages, with
@@ -29,6 +37,7 @@
 
 #include "aesgpu.h"
 #include "cipher_core.h"
+#include "ghash_core.h"
 #include "internal.h"
 #include "xts_core.h"
 
@@ -58,11 +67,40 @@ __device__ __forceinline__ uint32_t xts_unit_shift(const aes_msg_desc &d) {
     return 31u - __builtin_clz(xts_unit_bytes(d) >> 4);   // log2 of the blocks per unit
 }
 
+__device__ __forceinline__ bool ranges_overlap(uintptr_t a, uint64_t na, uintptr_t b, uint64_t nb) {
+    return na && nb && a < b + nb && b < a + na;
+}
+
+// The GCM fields of message m (SP 800-38D limits; every range inside its
+// buffer; the additional data and the tag clear of the message's output,
+// which is written before they are read).
+__device__ __forceinline__ bool gcm_valid(const aes_msg_desc &d, uint32_t m, const BatchKArgs &a) {
+    if (!a.gcm)
+        return false;
+    const aes_gcm_desc g = a.gcm[m];
+    if (d.nbytes > (uint64_t(1) << 36) - 32 || g.aad_bytes > (uint64_t(1) << 36) || (g.aad_off & 15u))
+        return false;
+    if (g.aad_bytes > a.in_bytes || g.aad_off > a.in_bytes - g.aad_bytes)
+        return false;
+    const uint64_t tb = d.decrypt ? g.tag_bytes : 16u;
+    if (d.decrypt && !(tb == 4 || tb == 8 || (tb >= 12 && tb <= 16)))
+        return false;
+    const uint64_t tbuf = d.decrypt ? a.in_bytes : a.out_bytes;
+    if (tb > tbuf || g.tag_off > tbuf - tb)
+        return false;
+    const uintptr_t out = reinterpret_cast<uintptr_t>(a.out_base) + d.out_off;
+    const uintptr_t aad = reinterpret_cast<uintptr_t>(a.in_base) + g.aad_off;
+    const uintptr_t tag = reinterpret_cast<uintptr_t>(d.decrypt ? a.in_base : a.out_base) + g.tag_off;
+    return !ranges_overlap(aad, g.aad_bytes, out, d.nbytes) && !ranges_overlap(tag, tb, out, d.nbytes);
+}
+
 // Same test as the host applies to a single-buffer call, plus bounds.
-__device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKArgs &a) {
-    if (d.keybits_code > 2 || d.mode > AES_MODE_XTS || d.decrypt > 1)
+__device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, uint32_t m, const BatchKArgs &a) {
+    if (d.keybits_code > 2 || d.mode > AES_MODE_GCM || d.decrypt > 1)
         return false;
     if ((d.mode == AES_MODE_ECB || d.mode == AES_MODE_CBC || d.mode == AES_MODE_XTS) && (d.nbytes & 15u))
+        return false;
+    if (d.mode == AES_MODE_GCM && !gcm_valid(d, m, a))
         return false;
     if (d.mode == AES_MODE_XTS) {
         const uint32_t u = xts_unit_bytes(d);
@@ -94,9 +132,9 @@ __device__ __forceinline__ bool desc_valid(const aes_msg_desc &d, const BatchKAr
     return true;
 }
 
-// Forward list (encryption tables): ECB encrypt, CTR, XTS encrypt.  Inverse
-// list (decryption tables): ECB, CBC and XTS decrypt.  Serial list: CBC
-// encrypt.
+// Forward list (encryption tables): ECB encrypt, CTR, XTS encrypt, GCM (its
+// CTR part, either direction).  Inverse list (decryption tables): ECB, CBC
+// and XTS decrypt.  Serial list: CBC encrypt.
 __device__ __forceinline__ int desc_class(const aes_msg_desc &d) {
     if (d.mode == AES_MODE_CBC)
         return d.decrypt ? 1 : 2;
@@ -208,6 +246,18 @@ __device__ __forceinline__ void expand_message_keys(const BatchKArgs &a, const a
         expand_key<NK>(a.keys + size_t(xts_key2(d)) * 32, tab, [&](int i, uint32_t v) { w2[i] = v; });
         store_schedule<NK>(slot + (d.decrypt ? 0 : kKeySlotWords / 2), w2);
     }
+    if (d.mode == AES_MODE_GCM) {
+        // H = Cipher_K(0^128); J0 = IV || 0^31 || 1 (a 96-bit IV) and
+        // Cipher_K(J0); the message's GHASH sum starts at zero
+        uint32_t h[4] = {0, 0, 0, 0};
+        encrypt_one<NR>(tab, w, h);
+        uint32_t e[4] = {le32(d.ctr0), le32(d.ctr0 + 4), le32(d.ctr0 + 8), 0x01000000u};
+        encrypt_one<NR>(tab, w, e);
+        u32x4 *g = reinterpret_cast<u32x4 *>(slot);
+        g[kGcmSlotH / 4] = vec4(h[0], h[1], h[2], h[3]);
+        g[kGcmSlotEJ0 / 4] = vec4(e[0], e[1], e[2], e[3]);
+        g[kGcmSlotSum / 4] = vec4(0, 0, 0, 0);
+    }
 }
 
 // Exclusive prefix sums over the workgroup's kPlanThreads threads of N
@@ -255,7 +305,14 @@ __device__ __forceinline__ void block_exclusive_scan(uint64_t (&v)[N], uint64_t 
     }
 }
 
-constexpr int kPlanCounters = kBatchChunkCounters;   // items in lists 0, 1, 2; cost of lists 0, 1; rejected
+// items in lists 0, 1, 2; cost of lists 0, 1; rejected; GCM messages; their GHASH pieces
+constexpr int kPlanCounters = kBatchChunkCounters;
+
+// GHASH positions of a GCM message: its additional data, its ciphertext
+// and the length block, 16 bytes each.
+__device__ __forceinline__ uint64_t ghash_positions(const aes_msg_desc &d, const aes_gcm_desc &g) {
+    return ((g.aad_bytes + 15) >> 4) + ((d.nbytes + 15) >> 4) + 1;
+}
 
 // floor(a b / c) without overflow (messages may overlap, so a list's cost is
 // not bounded by the memory size).
@@ -274,7 +331,7 @@ __device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, 
     if (m >= n)
         return;
     const aes_msg_desc d = a.desc[m];
-    if (!desc_valid(d, a)) {
+    if (!desc_valid(d, m, a)) {
         c[5] = 1;
         return;
     }
@@ -287,6 +344,24 @@ __device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, 
     c[2] = k == 2 ? 1 : 0;
     c[3] = k == 0 ? cost : 0;
     c[4] = k == 1 ? cost : 0;
+    if (d.mode == AES_MODE_GCM) {
+        c[6] = 1;
+        c[7] = (ghash_positions(d, a.gcm[m]) + kGhashPiece - 1) / kGhashPiece;
+    }
+}
+
+// The GHASH list's item of GCM message m: its pieces, and the pieces of the
+// GCM messages before it (c: the message's exclusive prefix of the counters).
+__device__ __forceinline__ void gcm_item(const BatchKArgs &a, uint32_t m, const uint64_t (&before)[kPlanCounters],
+                                         const uint64_t (&c)[kPlanCounters]) {
+    const aes_msg_desc d = a.desc[m];
+    if (d.mode != AES_MODE_GCM)
+        return;
+    BatchItem it;
+    it.msg = m;
+    it.count = uint32_t((ghash_positions(d, a.gcm[m]) + kGhashPiece - 1) / kGhashPiece);
+    it.start = before[7] + c[7];
+    a.items[size_t(3) * a.max_msgs + before[6] + c[6]] = it;
 }
 
 // The first launch of a batch, one message per thread, kPlanThreads messages
@@ -348,6 +423,8 @@ __global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArg
         h->cost[0] = total[3];
         h->cost[1] = total[4];
         h->rejected = uint32_t(total[5]);
+        h->ngcm = uint32_t(total[6]);
+        h->gcm_pieces = total[7];
     }
     if (!valid)
         return;
@@ -357,6 +434,8 @@ __global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArg
     it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;
     it.start = k == 0 ? c[3] : k == 1 ? c[4] : 0;
     a.items[size_t(k) * a.max_msgs + (k == 0 ? c[0] : k == 1 ? c[1] : c[2])] = it;
+    const uint64_t zero[kPlanCounters] = {0, 0, 0, 0, 0, 0, 0, 0};
+    gcm_item(a, m, zero, c);
     uint32_t *slot = a.keytab + size_t(m) * kKeySlotWords;
     if (d.keybits_code == 0)
         expand_message_keys<4>(a, d, slot, tab);
@@ -405,6 +484,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
         it.start = k == 0 ? base[3] + c[3] : k == 1 ? base[4] + c[4] : 0;
         const uint64_t i = k == 0 ? base[0] + c[0] : k == 1 ? base[1] + c[1] : base[2] + c[2];
         a.items[size_t(k) * a.max_msgs + i] = it;
+        gcm_item(a, m, base, c);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         BatchHeader *h = a.header;
@@ -415,6 +495,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
         h->cost[0] = sum_all[3];
         h->cost[1] = sum_all[4];
         h->rejected = uint32_t(sum_all[5]);
+        h->ngcm = uint32_t(sum_all[6]);
+        h->gcm_pieces = sum_all[7];
     }
 }
 
@@ -453,8 +535,10 @@ __device__ __forceinline__ void run_range(const uint32_t *lds, const LaneConsts 
     if (MODE == MODE_CTR) {
         for (int i = 0; i < 3; i++)
             ctr[i] = le32(d.ctr0 + 4 * i);
-        ctr[3] = (uint32_t(d.ctr0[12]) << 24) | (uint32_t(d.ctr0[13]) << 16) | (uint32_t(d.ctr0[14]) << 8) |
-                 uint32_t(d.ctr0[15]);
+        // GCM: the first data block's counter is J0 + 1 = IV || 0^31 || 2
+        ctr[3] = d.mode == AES_MODE_GCM ? 2u
+                                        : (uint32_t(d.ctr0[12]) << 24) | (uint32_t(d.ctr0[13]) << 16) |
+                                              (uint32_t(d.ctr0[14]) << 8) | uint32_t(d.ctr0[15]);
     }
     const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
     uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
@@ -690,6 +774,168 @@ __global__ __launch_bounds__(kBatchWavesPerGroup * 64) void batch_kernel(const B
         run_shares<CLASS, BPT>(lds, lc, a, n, wave, nwaves);
 }
 
+// ---- GCM: GHASH pieces and tags ----------------------------------------------
+// LDS of the GHASH kernel: per wave, one multiplier's table and the scratch
+// for building it (16 waves x 10 KiB = the whole 160 KiB).
+constexpr uint32_t kGhashWaveBytes = kTabBytes + kVecBytes;
+
+__device__ __forceinline__ u32x4 load16_masked(const uint8_t *p, bool whole, uint32_t tail) {
+    return whole ? load16(p) : load_tail(p, tail);
+}
+
+// GHASH position r of a GCM message, numbered from the end of the hashed
+// sequence (so that the sum is H * sum_r X_r H^r): r = 0 the length block,
+// 1 .. nC ciphertext block nC - r, nC + 1 .. nC + nA additional-data block
+// nC + nA - r; partial blocks zero-padded.  `ct` points at the ciphertext
+// (the input when decrypting, the output when encrypting).
+__device__ __forceinline__ u32x4 ghash_block(uint64_t r, uint64_t nC, uint64_t nA, const uint8_t *ct, uint64_t cbytes,
+                                             const uint8_t *aad, uint64_t abytes) {
+    if (r == 0) {
+        const uint64_t abits = 8 * abytes, cbits = 8 * cbytes;
+        return vec4(__builtin_bswap32(uint32_t(abits >> 32)), __builtin_bswap32(uint32_t(abits)),
+                    __builtin_bswap32(uint32_t(cbits >> 32)), __builtin_bswap32(uint32_t(cbits)));
+    }
+    if (r <= nC) {
+        const uint64_t j = nC - r;
+        return load16_masked(ct + 16 * j, j < (cbytes >> 4), uint32_t(cbytes & 15u));
+    }
+    const uint64_t k = nC + nA - r;
+    return load16_masked(aad + 16 * k, k < (abytes >> 4), uint32_t(abytes & 15u));
+}
+
+// One wave: piece `piece` of GCM message `msg`, positions [p_lo, p_hi), as
+// sum_(r in piece) X_r H^(r + 1), XORed into the message's sum.  Lane l
+// takes positions p_lo + 64q + l, Horner over q from the top with the
+// multiplier G = H^64 (one table); the lanes are folded with H, H^2, ..,
+// H^32 (a tree, each level's table built in the same space); the result is
+// multiplied by H^(p_lo + 1) (square and multiply, by the whole wave).
+__device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, uint32_t vec, const BatchKArgs &a,
+                                            uint32_t msg, uint64_t piece) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const aes_msg_desc d = a.desc[msg];
+    const aes_gcm_desc g = a.gcm[msg];
+    const uint64_t nC = (d.nbytes + 15) >> 4, nA = (g.aad_bytes + 15) >> 4;
+    const uint64_t npos = nC + nA + 1;
+    const uint64_t p_lo = piece * kGhashPiece;
+    const uint64_t p_hi = min(npos, p_lo + kGhashPiece);
+    const uint8_t *ct = d.decrypt ? static_cast<const uint8_t *>(a.in_base) + d.in_off
+                                  : static_cast<const uint8_t *>(a.out_base) + d.out_off;
+    const uint8_t *aad = static_cast<const uint8_t *>(a.in_base) + g.aad_off;
+    uint32_t *slot = a.keytab + size_t(msg) * kKeySlotWords;
+    const uint32_t h[4] = {uniform32(slot[kGcmSlotH]), uniform32(slot[kGcmSlotH + 1]), uniform32(slot[kGcmSlotH + 2]),
+                           uniform32(slot[kGcmSlotH + 3])};
+    uint64_t hlo, hhi;
+    to_poly(h, hlo, hhi);
+    uint64_t glo = hlo, ghi = hhi;
+    for (int t = 0; t < 6; t++)
+        gf_square(glo, ghi);
+    uint32_t gw[4];
+    from_poly(glo, ghi, gw);
+    build_table_wave(lds, tab, vec, gw);
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (uint64_t q = (p_hi - p_lo + 63) >> 6; q-- > 0;) {
+        const uint64_t r = p_lo + 64 * q + lane;
+        u32x4 x = vec4(0, 0, 0, 0);
+        if (r < p_hi)
+            x = ghash_block(r, nC, nA, ct, d.nbytes, aad, g.aad_bytes);
+        uint32_t t[4];
+        mul_tab(lds, tab, w, t);
+        w[0] = t[0] ^ x.x;
+        w[1] = t[1] ^ x.y;
+        w[2] = t[2] ^ x.z;
+        w[3] = t[3] ^ x.w;
+    }
+    // sum_l w_l H^l over the lanes
+    uint64_t plo = hlo, phi = hhi;
+    for (int k = 0; k < 6; k++) {
+        uint32_t pw[4];
+        from_poly(plo, phi, pw);
+        build_table_wave(lds, tab, vec, pw);
+        uint32_t v[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            v[c] = uint32_t(__shfl_down(int(w[c]), 1u << k, 64));
+        mul_tab(lds, tab, v, v);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            w[c] ^= v[c];
+        gf_square(plo, phi);
+    }
+    // times H^(p_lo + 1): lane 0's sum, the same in every lane
+    const uint32_t s0[4] = {uniform32(w[0]), uniform32(w[1]), uniform32(w[2]), uniform32(w[3])};
+    uint64_t rlo, rhi, blo = hlo, bhi = hhi;
+    to_poly(s0, rlo, rhi);
+    for (uint64_t e = p_lo + 1; e; e >>= 1) {
+        if (e & 1)
+            mul_wave(rlo, rhi, blo, bhi, rlo, rhi);
+        if (e > 1)
+            gf_square(blo, bhi);
+    }
+    uint32_t res[4];
+    from_poly(rlo, rhi, res);
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            atomicXor(slot + kGcmSlotSum + c, res[c]);
+    }
+}
+
+// Persistent: wave w of NW takes pieces w, w + NW, w + 2 NW, ... of the
+// GHASH list (every GCM message's pieces, in message order).
+__global__ __launch_bounds__(kBatchWavesPerGroup * 64) void ghash_kernel(const BatchKArgs a) {
+    const uint32_t n = a.header->ngcm;
+    const uint64_t npieces = a.header->gcm_pieces;
+    if (n == 0)
+        return;
+    __shared__ uint32_t lds[kBatchWavesPerGroup * kGhashWaveBytes / 4];
+    const uint32_t wv = uniform32(threadIdx.x >> 6);
+    const uint32_t tab = wv * kGhashWaveBytes, vec = tab + kTabBytes;
+    const uint64_t wave = uint64_t(blockIdx.x) * kBatchWavesPerGroup + wv;
+    const uint64_t nwaves = uint64_t(gridDim.x) * kBatchWavesPerGroup;
+    const BatchItem *list = a.items + size_t(3) * a.max_msgs;
+    for (uint64_t p = wave; p < npieces; p += nwaves) {
+        const uint32_t i = uniform32(find_item(list, n, p));
+        const uint32_t msg = uniform32(list[i].msg);
+        ghash_piece(lds, tab, vec, a, msg, p - uniform64(list[i].start));
+    }
+}
+
+// One lane per message: every GCM message's tag, Cipher_K(J0) XOR its GHASH
+// sum, written after its output (encryption) or compared with the expected
+// one (decryption); the verdict goes to the message's aes_gcm_desc.
+__global__ __launch_bounds__(256) void gcm_tag_kernel(const BatchKArgs a) {
+    const uint32_t n = batch_count(a);
+    const uint32_t m = blockIdx.x * 256u + threadIdx.x;
+    if (m >= n || !a.gcm)
+        return;
+    const aes_msg_desc d = a.desc[m];
+    if (d.mode != AES_MODE_GCM)
+        return;
+    if (!desc_valid(d, m, a)) {
+        a.gcm[m].ok = 0;
+        return;
+    }
+    const aes_gcm_desc g = a.gcm[m];
+    const uint32_t *slot = a.keytab + size_t(m) * kKeySlotWords;
+    uint8_t tag[16];
+#pragma unroll
+    for (int b = 0; b < 16; b++)
+        tag[b] = uint8_t((slot[kGcmSlotSum + b / 4] ^ slot[kGcmSlotEJ0 + b / 4]) >> (8 * (b & 3)));
+    if (!d.decrypt) {
+        uint8_t *t = static_cast<uint8_t *>(a.out_base) + g.tag_off;
+#pragma unroll
+        for (int b = 0; b < 16; b++)
+            t[b] = tag[b];
+        a.gcm[m].ok = 1;
+    } else {
+        const uint8_t *t = static_cast<const uint8_t *>(a.in_base) + g.tag_off;
+        uint32_t diff = 0;
+        for (uint32_t b = 0; b < g.tag_bytes; b++)
+            diff |= uint32_t(tag[b] ^ t[b]);
+        a.gcm[m].ok = diff == 0 ? 1 : 0;
+    }
+}
+
 // ---- synthetic payloads for the request loop ------------------------------
 // The payload of a request is the SplitMix64 stream of its seed: word i =
 // mix64(seed + (i + 1) * 0x9E3779B97F4A7C15), stored little-endian (Steele,
@@ -786,7 +1032,7 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
             e = hipGetLastError();
         }
     }
-    if (e != hipSuccess || !(lists & 7u))
+    if (e != hipSuccess || !(lists & 15u))
         return e;
     // the forward kernel also runs the serial list
     if (lists & 5u) {
@@ -797,6 +1043,18 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
     }
     if (lists & 2u) {
         hipLaunchKernelGGL((batch_kernel<1, 4>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    // GCM: the hash reads the ciphertext the forward kernel has written
+    if (lists & 8u) {
+        hipLaunchKernelGGL(ghash_kernel, dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        const int groups = (std::max(max_count, 1) + 255) / 256;
+        hipLaunchKernelGGL(gcm_tag_kernel, dim3(groups), dim3(256), 0, stream, a);
         e = hipGetLastError();
     }
     return e;

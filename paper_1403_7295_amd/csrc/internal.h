@@ -127,19 +127,23 @@ hipError_t launch_gcm(int nr, const GcmArgs &a, hipStream_t stream);
 // Workspace = header | key schedules (max_msgs slots) | items[3][max_msgs] |
 // chunk totals (the plan's counters per chunk of messages).
 struct BatchHeader {
-    uint32_t nitems[3];   // messages in the forward list (ECB encrypt, CTR, XTS encrypt),
-                          // the inverse list (ECB, CBC and XTS decrypt) and the serial
-                          // list (CBC encrypt)
+    uint32_t nitems[3];   // messages in the forward list (ECB encrypt, CTR, XTS encrypt,
+                          // GCM), the inverse list (ECB, CBC and XTS decrypt) and the
+                          // serial list (CBC encrypt)
     uint32_t rejected;    // messages whose descriptor failed the checks
     uint64_t next[3];     // forward and inverse lists: next share handed out from the
                           // counter; serial list: next message
     uint64_t cost[2];     // work of the forward and inverse lists, in cost units
-    uint32_t pad[50];
+    uint32_t ngcm;        // GCM messages (the GHASH list)
+    uint32_t pad0;
+    uint64_t gcm_pieces;  // GHASH pieces of all of them
+    uint32_t pad[46];
 };
 static_assert(sizeof(BatchHeader) == 256, "header is one 256-byte line");
 
 // One message in a list.  Forward and inverse lists: start = the cost units of
 // the messages before it in the list.  Serial list: count = its blocks.
+// GHASH list: start = the pieces of the messages before it, count = its own.
 struct BatchItem {
     uint32_t msg;     // message index
     uint32_t count;
@@ -147,8 +151,13 @@ struct BatchItem {
 };
 
 // encryption schedule at 0, decryption schedule at 64; an XTS message keeps
-// its tweak key's encryption schedule in the half its direction leaves free
+// its tweak key's encryption schedule in the half its direction leaves free;
+// a GCM message keeps H = Cipher_K(0), Cipher_K(J0) and its GHASH sum there
 constexpr int kKeySlotWords = 128;
+constexpr int kGcmSlotH = 64, kGcmSlotEJ0 = 68, kGcmSlotSum = 72;
+// GHASH positions (16-byte blocks of additional data, ciphertext and the
+// length block) per piece: one wave hashes one piece
+constexpr uint64_t kGhashPiece = 16384;
 // A wave's share of a message starts and ends on a multiple of this many
 // blocks by default (four steps of the block loop, 64 lanes x 2 blocks; the
 // best of 128 .. 1024 over batch sizes from one message to gigabytes).  The
@@ -161,7 +170,8 @@ constexpr int kBatchWavesPerGroup = 16;
 // Messages per chunk of the plan (one workgroup of the prep and plan
 // kernels), and the plan's counters per chunk.
 constexpr int kBatchChunk = 256;
-constexpr int kBatchChunkCounters = 6;
+constexpr int kBatchChunkCounters = 8;
+constexpr int kBatchLists = 4;   // forward, inverse, serial, GHASH
 
 struct BatchKArgs {
     const aes_msg_desc *desc;
@@ -176,13 +186,14 @@ struct BatchKArgs {
     uint64_t out_bytes;
     BatchHeader *header;
     uint32_t *keytab;
-    BatchItem *items;        // three lists of max_msgs entries
+    BatchItem *items;        // kBatchLists lists of max_msgs entries
     uint64_t *chunk_totals;  // the plan's counters per chunk of messages
     uint32_t split_blocks;   // a share starts and ends on a multiple of this
     uint8_t *reject_flags;   // NULL, or one byte per message, set to 1 for each
                              // message the descriptor check refuses (the
                              // caller clears them; the request loop points
                              // this at pinned host memory)
+    aes_gcm_desc *gcm;       // NULL, or the GCM fields per message
 };
 
 // Synthetic payloads of the request loop (batch_kernels.hip).
@@ -209,10 +220,11 @@ hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStr
 hipError_t upload_tables_batch(const HostTables &t);
 
 // Workspace bytes for batches of up to max_msgs messages: header, one key
-// slot and one list entry per message in each of the three lists, the plan's
+// slot and one list entry per message in each of the lists, the plan's
 // counters per chunk of messages.
 constexpr size_t batch_layout(int max_msgs) {
-    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 + 3 * size_t(max_msgs) * sizeof(BatchItem) +
+    return sizeof(BatchHeader) + size_t(max_msgs) * kKeySlotWords * 4 +
+           size_t(kBatchLists) * size_t(max_msgs) * sizeof(BatchItem) +
            (size_t(max_msgs) + kBatchChunk - 1) / kBatchChunk * kBatchChunkCounters * sizeof(uint64_t);
 }
 // The library-held batch workspace of aes_batch_run_noalloc
@@ -224,8 +236,8 @@ constexpr size_t kNoAllocScratchBytes = batch_layout(AES_BATCH_NOALLOC_MAX_MSGS)
 hipError_t init_batch_scratch(int dev);
 void *batch_scratch(int dev);
 // lists: bit k set if list k may hold messages (bit 0 forward, 1 inverse, 2
-// serial); a cipher kernel whose lists are all known to be empty is not
-// launched.  max_count: a bound on the message count known to the caller
+// serial, 3 GCM: the GHASH and tag kernels); a kernel whose lists are all
+// known to be empty is not launched.  max_count: a bound on the message count known to the caller
 // (at most max_msgs); up to one chunk, Key Expansion and the plan run as one
 // launch.  Key Expansion and the plan always run.
 hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists, int max_count);

@@ -55,7 +55,9 @@ static_assert(sizeof(SlotHeader) == kAlign, "slot header is 256 bytes");
 struct ServeLayout {
     size_t arena;
     size_t desc_off, fill_off, ws_off, ws_bytes, slot_bytes, staged_bytes;
-    size_t flags_off, host_bytes;   // pinned memory: staged part, then one reject flag per message
+    // pinned memory: the staged part, then one reject flag per message, then
+    // the GCM fields per message (read and written by the device in place)
+    size_t flags_off, gcm_off, host_bytes;
     size_t total;
 };
 
@@ -71,7 +73,8 @@ bool make_layout(const aes_serve_cfg &c, ServeLayout *L) {
     L->ws_bytes = serve_batch_layout(c.max_batch_msgs);
     L->slot_bytes = L->ws_off + round_up(L->ws_bytes, kAlign);
     L->flags_off = L->staged_bytes;
-    L->host_bytes = L->flags_off + round_up(size_t(c.max_batch_msgs), kAlign);
+    L->gcm_off = L->flags_off + round_up(size_t(c.max_batch_msgs), kAlign);
+    L->host_bytes = L->gcm_off + round_up(size_t(c.max_batch_msgs) * sizeof(aes_gcm_desc), kAlign);
     L->total = L->arena + size_t(c.streams) * L->slot_bytes;
     return true;
 }
@@ -109,7 +112,11 @@ struct Loop {
     Loop(const aes_request *r, int n, const aes_serve_cfg &c, const ServeLayout &l, aes_request_result *o)
         : reqs(r), nreq(n), cfg(c), L(l), res(o), sim(c.simulate_gbps > 0) {}
 
-    uint64_t footprint(int i) const { return 2 * round_up(reqs[i].nbytes, kAlign); }
+    // a GCM request's input and output each carry 16 more bytes: the
+    // expected tag after the ciphertext (decryption), the tag after the
+    // ciphertext (encryption)
+    uint64_t payload(int i) const { return reqs[i].nbytes + (reqs[i].mode == AES_MODE_GCM ? 16u : 0u); }
+    uint64_t footprint(int i) const { return 2 * round_up(payload(i), kAlign); }
 
     int launch(Slot &s, double now) {
         const int n = int(s.reqs.size());
@@ -125,6 +132,7 @@ struct Loop {
         SlotHeader *h = reinterpret_cast<SlotHeader *>(s.host);
         aes_msg_desc *d = reinterpret_cast<aes_msg_desc *>(s.host + L.desc_off);
         FillDesc *f = reinterpret_cast<FillDesc *>(s.host + L.fill_off);
+        aes_gcm_desc *g = reinterpret_cast<aes_gcm_desc *>(s.host + L.gcm_off);
         uint64_t chunks = 0;
         unsigned lists = 0;   // the batch kernel's lists this batch uses
         for (int k = 0; k < n; k++) {
@@ -140,13 +148,23 @@ struct Loop {
             d[k].reserved = 0;
             std::memcpy(d[k].ctr0, q.ctr0, 16);
             f[k].off = r.in_off;
-            f[k].nbytes = q.nbytes;
+            f[k].nbytes = payload(s.reqs[k]);
             f[k].seed = q.payload_seed;
             f[k].chunk_first = chunks;
-            chunks += (q.nbytes + kFillChunk - 1) / kFillChunk;
+            chunks += (f[k].nbytes + kFillChunk - 1) / kFillChunk;
             const bool inverse = q.decrypt && (q.mode == AES_MODE_ECB || q.mode == AES_MODE_CBC);
             const bool serial = !q.decrypt && q.mode == AES_MODE_CBC;
             lists |= serial ? 4u : inverse ? 2u : 1u;
+            if (q.mode == AES_MODE_GCM) {
+                // no additional data; the tag 16-byte aligned after the data
+                const uint64_t tag_at = (q.nbytes + 15) / 16 * 16;
+                g[k].aad_off = r.in_off;
+                g[k].aad_bytes = 0;
+                g[k].tag_off = (q.decrypt ? r.in_off : r.out_off) + tag_at;
+                g[k].tag_bytes = 16;
+                g[k].ok = -1;
+                lists |= 8u;
+            }
         }
         h->nmsg = n;
         h->nchunks = chunks;
@@ -184,6 +202,8 @@ struct Loop {
             b.workspace_bytes = L.ws_bytes;
             b.max_msgs = cfg.max_batch_msgs;
             b.tile_blocks = cfg.tile_blocks;
+            b.gcm = (lists & 8u) ? reinterpret_cast<aes_gcm_desc *>(static_cast<uint8_t *>(s.host_dev) + L.gcm_off)
+                                 : nullptr;
             BatchKArgs ka;
             int st = serve_batch_args(&b, &ka);
             if (st != AES_OK)
@@ -269,10 +289,13 @@ struct Loop {
                     continue;
                 const double t = sim ? s.done_at : now;
                 const uint8_t *flags = sim ? nullptr : s.host + L.flags_off;
+                const aes_gcm_desc *g = sim ? nullptr : reinterpret_cast<const aes_gcm_desc *>(s.host + L.gcm_off);
                 for (size_t k = 0; k < s.reqs.size(); k++) {
                     const int i = s.reqs[k];
                     res[i].latency_s = t - reqs[i].arrival_s;
                     res[i].status = flags && flags[k] ? AES_E_ARG : AES_OK;
+                    if (reqs[i].mode == AES_MODE_GCM)
+                        res[i].authentic = g ? g[k].ok : (reqs[i].decrypt ? 0 : 1);
                     const uint64_t fp = footprint(i);
                     if (fp) {
                         arena.release(res[i].in_off, fp);
@@ -392,9 +415,12 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
         const aes_request &q = reqs[i];
         if (i && q.arrival_s < reqs[i - 1].arrival_s)
             return serve_fail(AES_E_ARG, "requests must be sorted by arrival_s");
-        if (q.keybits_code > 2 || q.mode > AES_MODE_CBC || q.decrypt > 1 || q.key_idx >= uint32_t(nkeys))
+        if (q.keybits_code > 2 || (q.mode > AES_MODE_CBC && q.mode != AES_MODE_GCM) || q.decrypt > 1 ||
+            q.key_idx >= uint32_t(nkeys))
             return serve_fail(AES_E_ARG, "request " + std::to_string(i) + ": bad key, mode or direction");
-        if (q.mode != AES_MODE_CTR && q.nbytes % 16)
+        if (q.mode == AES_MODE_GCM && q.nbytes > (uint64_t(1) << 36) - 32)
+            return serve_fail(AES_E_LENGTH, "request " + std::to_string(i) + ": GCM longer than 2^36 - 32 bytes");
+        if ((q.mode == AES_MODE_ECB || q.mode == AES_MODE_CBC) && q.nbytes % 16)
             return serve_fail(AES_E_LENGTH, "request " + std::to_string(i) + ": ECB/CBC length not whole blocks");
         if (q.mode == AES_MODE_CTR && q.nbytes > kCtrMaxBytes)
             return serve_fail(AES_E_LENGTH, "request " + std::to_string(i) + ": CTR longer than 2^36 bytes");
@@ -405,6 +431,7 @@ int aes_serve_run(const aes_request *reqs, int nreq, const uint8_t *d_keys, int 
         results[i] = aes_request_result{};
         results[i].status = AES_E_ARG;
         results[i].launch = -1;
+        results[i].authentic = -1;
     }
     loop.keys = d_keys;
     loop.nkeys = nkeys;

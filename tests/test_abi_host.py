@@ -167,11 +167,12 @@ def test_launch_config_validation(A):
 
 
 def test_batch_workspace_size(A):
-    # header + key slots of 512 bytes + three lists of 16-byte items + the
-    # plan's six 8-byte counters per chunk of 256 messages
-    assert A.aes_batch_workspace_size(10) == 256 + 10 * 512 + 3 * 10 * 16 + 48
-    assert A.aes_batch_workspace_size(1) == 256 + 512 + 3 * 16 + 48
-    assert A.aes_batch_workspace_size(257) == 256 + 257 * 512 + 3 * 257 * 16 + 2 * 48
+    # header + key slots of 512 bytes + four lists of 16-byte items (forward,
+    # inverse, serial, GHASH) + the plan's eight 8-byte counters per chunk of
+    # 256 messages
+    assert A.aes_batch_workspace_size(10) == 256 + 10 * 512 + 4 * 10 * 16 + 64
+    assert A.aes_batch_workspace_size(1) == 256 + 512 + 4 * 16 + 64
+    assert A.aes_batch_workspace_size(257) == 256 + 257 * 512 + 4 * 257 * 16 + 2 * 64
     for bad in (0, -3):
         with pytest.raises(A.AESError) as e:
             A.aes_batch_workspace_size(bad)
@@ -220,6 +221,18 @@ def test_batch_argument_checks(A):
     assert code(batch(workspace_bytes=ws - 1)) == A.AES_E_LENGTH
     assert code(batch(tile_blocks=-1)) == A.AES_E_ARG
     assert code(batch(tile_blocks=1025)) == A.AES_E_ARG
+    assert code(batch(gcm=0x600004)) == A.AES_E_ALIGN
+
+
+def test_gcm_batch_layout(A):
+    import ctypes
+    assert A.GCM_DESC_DTYPE.itemsize == 32
+    # the gcm pointer follows tile_blocks at the end of aes_batch
+    assert A.aes_batch.gcm.offset == A.aes_batch.tile_blocks.offset + 4 == 96
+    assert ctypes.sizeof(A.aes_batch) == 104
+    assert A.AES_MODE_GCM == 4 and A.MODES["gcm"] == 4
+    text = open(HEADER).read()
+    assert "AES_MODE_GCM = 4" in text
 
 
 def test_noalloc_batch_argument_checks(A):

@@ -389,3 +389,144 @@ def test_sector_batch_full_size_sampled(A, O):
     ws = w.view(nmsg, size)[rows].cpu().numpy()
     for j, m in enumerate(idx):
         assert np.array_equal(ws[j], oracle_message(O, xd[m], keys, xs[j])), ("XTS encrypt", m)
+
+
+# --- GCM messages in a batch -------------------------------------------------
+def gcm_batch(A, O, n, seed, max_len=1 << 16, big=(), n_other=0):
+    """n GCM messages (and n_other CTR/ECB ones), 128/192/256-bit keys,
+    lengths log-uniform up to max_len plus the lengths in `big`, additional
+    data of 0 .. 1000 bytes (larger for the big ones), half encryptions and
+    half decryptions of the oracle's ciphertexts, a quarter of those with a
+    changed tag.  Input buffer: the messages, then their additional data,
+    then the expected tags; output buffer: the same size (tags of the
+    encryptions at the same offsets as the expected tags)."""
+    rng = np.random.default_rng(seed)
+    lens = list(seedgen.log_uniform_lengths(rng, n, 1, max_len)) + list(big)
+    n = len(lens)
+    lens[0] = 0
+    keybits = rng.choice([128, 192, 256], n + n_other)
+    dec = rng.integers(0, 2, n)
+    aadl = rng.integers(0, 1001, n)
+    aadl[1] = 0
+    for i in range(len(big)):
+        aadl[n - 1 - i] = 100000 + 7 * i
+    keys = np.zeros((n + n_other, 32), np.uint8)
+    for m in range(n + n_other):
+        keys[m, :keybits[m] // 8] = seedgen.key(seed, m, int(keybits[m]))
+    ivs = [seedgen.nonce(seed, m)[:12] for m in range(n)]
+    olens = seedgen.log_uniform_lengths(rng, n_other, 16, max_len, 16) if n_other else np.zeros(0, np.int64)
+    pad = lambda v: (int(v) + 15) // 16 * 16  # noqa: E731
+    off, msg_off = 0, []
+    for L in list(lens) + list(olens):
+        msg_off.append(off)
+        off += pad(L)
+    aad_off = []
+    for L in aadl:
+        aad_off.append(off)
+        off += pad(L)
+    tag_off = []
+    for _ in range(n):
+        tag_off.append(off)
+        off += 16
+    total = off + 16
+    x = np.zeros(total, np.uint8)
+    want = {}
+    forged = np.zeros(n, bool)
+    for m in range(n):
+        bits = int(keybits[m])
+        rk, nr = O.expand_key(keys[m][:bits // 8])
+        pt = seedgen.data_np(seed, 1000 + m, int(lens[m]))
+        aad = seedgen.data_np(seed, 5000 + m, int(aadl[m]))
+        ct, tag = O.gcm_encrypt(rk, nr, ivs[m], aad, pt)
+        x[aad_off[m]:aad_off[m] + aad.size] = aad
+        if dec[m]:
+            x[msg_off[m]:msg_off[m] + ct.size] = ct
+            t = tag.copy()
+            if m % 4 == 1:
+                t[m % 16] ^= 0x40
+                forged[m] = True
+            x[tag_off[m]:tag_off[m] + 16] = t
+            want[m] = (pt, None, not forged[m])
+        else:
+            x[msg_off[m]:msg_off[m] + pt.size] = pt
+            want[m] = (ct, tag, True)
+    for k in range(n_other):
+        m = n + k
+        x[msg_off[m]:msg_off[m] + int(olens[k])] = seedgen.data_np(seed, 9000 + k, int(olens[k]))
+    modes = [A.AES_MODE_GCM] * n + [int(v) for v in rng.choice([0, 1], n_other)]
+    ctr0 = np.zeros((n + n_other, 16), np.uint8)
+    for m in range(n):
+        ctr0[m, :12] = ivs[m]
+    for k in range(n_other):
+        ctr0[n + k] = seedgen.nonce(seed, n + k)
+    descs = A.make_descs(list(lens) + list(olens), in_off=msg_off, keybits=keybits, mode=modes,
+                         decrypt=list(dec) + [0] * n_other, ctr0=ctr0)
+    g = np.zeros(n + n_other, A.GCM_DESC_DTYPE)
+    g["aad_off"][:n] = aad_off
+    g["aad_bytes"][:n] = aadl
+    g["tag_off"][:n] = tag_off
+    g["tag_bytes"][:n] = 16
+    g["ok"] = -7
+    return descs, keys, g, x, want, n
+
+
+def check_gcm_batch(A, O, b, descs, keys, x, y, want, n, g_out):
+    for m in range(n):
+        d = descs[m]
+        o, L = int(d["out_off"]), int(d["nbytes"])
+        data, tag, ok = want[m]
+        assert np.array_equal(y[o:o + L], data), "GCM message %d (%s) output" % (m, d)
+        if tag is not None:
+            t = int(g_out["tag_off"][m])
+            assert np.array_equal(y[t:t + 16], tag), "GCM message %d tag" % m
+        assert g_out["ok"][m] == (1 if ok else 0), "GCM message %d verdict" % m
+    # the other messages, against the oracle
+    for m in range(n, len(descs)):
+        d = descs[m]
+        i, L = int(d["in_off"]), int(d["nbytes"])
+        want_o = oracle_message(O, d, keys, x[i:i + L])
+        assert np.array_equal(y[int(d["out_off"]):int(d["out_off"]) + L], want_o), "message %d" % m
+
+
+def test_gcm_batch_matches_oracle(A, O):
+    descs, keys, g, x, want, n = gcm_batch(A, O, 200, 71, big=((1 << 20) + 5, 600 * 1024 + 3), n_other=40)
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.zeros_like(xd)
+    b = A.Batch(descs, keys, xd, yd, gcm=g)
+    b.run()
+    planned, rejected = b.query()
+    assert rejected == 0 and planned == len(descs)
+    check_gcm_batch(A, O, b, descs, keys, x, yd.cpu().numpy(), want, n, b.gcm_results(len(descs)))
+    # graph replays recompute everything from the descriptors (the sums start over)
+    yd.zero_()
+    b.launch_graph()
+    b.launch_graph()
+    torch.cuda.synchronize()
+    check_gcm_batch(A, O, b, descs, keys, x, yd.cpu().numpy(), want, n, b.gcm_results(len(descs)))
+    b.close()
+
+
+def test_gcm_batch_refuses_bad_fields(A, O):
+    descs, keys, g, x, want, n = gcm_batch(A, O, 8, 72)
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.zeros_like(xd)
+    bad = g.copy()
+    bad["aad_off"][2] += 8                                      # not 16-byte aligned
+    bad["aad_bytes"][3] = xd.numel()                            # past the input buffer
+    bad["tag_off"][4] = xd.numel() - 8                          # the tag past the buffer's end
+    if descs["decrypt"][5]:
+        bad["tag_bytes"][5] = 7                                 # a tag length the standard does not allow
+    else:
+        bad["tag_off"][5] = int(descs["out_off"][5])            # the tag over the message's own output
+    b = A.Batch(descs, keys, xd, yd, gcm=bad)
+    b.run()
+    _, rejected = b.query()
+    assert rejected == 4
+    r = b.gcm_results(len(descs))
+    assert list(r["ok"][2:6]) == [0, 0, 0, 0]
+    check_gcm_batch(A, O, b, descs[6:], keys[6:], x, yd.cpu().numpy(), {i - 6: want[i] for i in range(6, n)},
+                    n - 6, r[6:])
+    # without GCM fields every GCM descriptor is refused
+    b2 = A.Batch(descs, keys, xd, yd)
+    b2.run()
+    assert b2.query()[1] == n

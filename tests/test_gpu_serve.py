@@ -188,3 +188,37 @@ def test_mixed_modes_same_alone_and_in_the_mix(A):
         n = int(q["nbytes"])
         payload = seedgen.bytes_np(int(q["payload_seed"]), n)
         assert torch.equal(srv.output(res[i], n), alone(A, q, keys[i], payload)), "request %d (%s)" % (i, q)
+
+
+def test_served_gcm_requests_match_the_oracle(A):
+    """GCM requests through the loop (no additional data, the tag after the
+    data in the arena): encryptions equal the oracle's ciphertext and tag;
+    decryptions of the random payloads equal the oracle's plaintext, and
+    both reject the random 'tag' that follows them."""
+    r, keys = requests(A, 150, rate=1e5, seed=57, lo=64, hi=1 << 22)
+    r["mode"] = A.AES_MODE_GCM
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 16 + 255) // 256 * 256)
+    cfg = A.serve_cfg(streams=3, budget_bytes=int(fp.sum()) + (1 << 20), max_batch_msgs=32)
+    srv = A.Server(keys, cfg)
+    res, st = srv.run(r)
+    torch.cuda.synchronize()
+    assert st["completed"] == len(r) and st["launches"] > 2
+    assert (res["status"] == A.AES_OK).all() and not res["overwritten"].any()
+    o = ref.default()
+    for i, q in enumerate(r):
+        n = int(q["nbytes"])
+        bits = 128 + 64 * int(q["keybits_code"])
+        rk, nr = o.expand_key(keys[i][:bits // 8])
+        iv = q["ctr0"][:12]
+        payload = seedgen.bytes_np(int(q["payload_seed"]), n)
+        got = srv.output(res[i], n).cpu().numpy()
+        if q["decrypt"]:
+            tag = seedgen.bytes_np(int(q["payload_seed"]), 16, offset=(n + 15) // 16 * 16)
+            pt, ok = o.gcm_decrypt(rk, nr, iv, b"", payload, tag)
+            assert np.array_equal(got, pt), "request %d plaintext" % i
+            assert res["authentic"][i] == int(ok) == 0, "request %d verdict" % i
+        else:
+            ct, tag = o.gcm_encrypt(rk, nr, iv, b"", payload)
+            assert np.array_equal(got, ct), "request %d ciphertext" % i
+            assert np.array_equal(srv.tag(res[i], n).cpu().numpy(), tag), "request %d tag" % i
+            assert res["authentic"][i] == 1

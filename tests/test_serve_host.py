@@ -179,3 +179,37 @@ def test_nothing_is_overwritten_with_room_for_everything(A):
     cfg = A.serve_cfg(streams=3, budget_bytes=int(fp.sum()), max_batch_msgs=16, simulate_gbps=50.0)
     res, _ = A.aes_serve_run(r, cfg)
     assert not res["overwritten"].any()
+
+
+def test_gcm_requests_take_16_more_bytes(A):
+    # a GCM request's input and output each carry a 16-byte tag after the
+    # data, counted against the budget; the simulated loop reports encryption
+    # tags as written and decryptions (no device to check them) as not
+    r, _ = requests(A, 300, rate=50000.0, hi=1 << 16)
+    r["mode"] = A.AES_MODE_GCM
+    budget = 1 << 22
+    cfg = A.serve_cfg(streams=2, budget_bytes=budget, max_batch_msgs=16, simulate_gbps=40.0)
+    res, st = A.aes_serve_run(r, cfg)
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 16 + 255) // 256 * 256)
+    assert st["completed"] == 300 and st["max_inflight_bytes"] <= budget
+    gap = res["out_off"].astype(np.int64) - res["in_off"].astype(np.int64)
+    assert np.array_equal(gap, fp // 2)
+    assert (res["authentic"] == np.where(r["decrypt"] == 1, 0, 1)).all()
+    other, _ = requests(A, 50, rate=50000.0, hi=1 << 16)
+    res2, _ = A.aes_serve_run(other, cfg)
+    assert (res2["authentic"] == -1).all()
+
+
+def test_gcm_request_checks(A):
+    r, _ = requests(A, 10, rate=1000.0)
+    bad = r.copy()
+    bad["mode"][4] = A.AES_MODE_XTS          # not a served mode
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, A.serve_cfg(simulate_gbps=10.0))
+    assert e.value.code == A.AES_E_ARG
+    bad = r.copy()
+    bad["mode"][4] = A.AES_MODE_GCM
+    bad["nbytes"][4] = (1 << 36) - 16        # over GCM's 2^36 - 32
+    with pytest.raises(A.AESError) as e:
+        A.aes_serve_run(bad, A.serve_cfg(budget_bytes=1 << 40, simulate_gbps=10.0))
+    assert e.value.code == A.AES_E_LENGTH
