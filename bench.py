@@ -192,17 +192,20 @@ def leg(torch, stream, launch, nbytes, reps=10, warmup=None):
     return {"GB/s": round(nbytes / (st["median"] * 1e-6) / 1e9, 1), "launch_us": st}
 
 
-def bench_lds_gather(torch, A, dev, stream, rounds=LDS_GATHER_ROUNDS, steps=20, warmup=3):
+def bench_lds_gather(torch, A, dev, stream, rounds=LDS_GATHER_ROUNDS, steps=20, warmup=3, layout=0):
     """The LDS calibration kernel in the cipher's launch shape: the 32-bit,
     own-bank lookups per second the LDS accepts with no global memory traffic
     and the cipher's VALU cost per lookup, and the rate of the cycle counter
-    its waves read (s_memtime over the constant-rate s_memrealtime)."""
-    waves = torch.cuda.get_device_properties(dev).multi_processor_count * 16
+    its waves read (s_memtime over the constant-rate s_memrealtime).  Layout
+    0: the cipher's four tables x 32 copies, one workgroup per compute unit;
+    layout 3: one table x 64 copies, two."""
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    waves = cus * 16 * 2     # room for two workgroups of 16 waves per compute unit
     rec = torch.zeros(waves * 3, dtype=torch.int64, device=dev)
     got = {}
 
     def launch():
-        got["waves"], got["khz"] = A.aes_lds_gather(rec, rounds, stream=stream)
+        got["waves"], got["khz"] = A.aes_lds_gather(rec, rounds, stream=stream, layout=layout)
 
     _, k = timed_launches(torch, stream, launch, steps, warmup)
     w = got["waves"]
@@ -214,9 +217,9 @@ def bench_lds_gather(torch, A, dev, stream, rounds=LDS_GATHER_ROUNDS, steps=20, 
         clock = None    # the cycle counter does not count engine clocks here
     rate = lookups / k / 1e12
     out = {"Tlookup/s": round(rate, 3), "kernel_us": round(k * 1e6, 1), "lookups_per_launch": lookups,
-           "waves": w, "counter_clock_GHz": round(clock, 3) if clock else None}
+           "waves": w, "layout": layout, "counter_clock_GHz": round(clock, 3) if clock else None}
     if clock:
-        out["lookups_per_counter_clk_per_cu"] = round(rate * 1e12 / (w / 16) / (clock * 1e9), 2)
+        out["lookups_per_counter_clk_per_cu"] = round(rate * 1e12 / cus / (clock * 1e9), 2)
     return out
 
 
@@ -557,11 +560,28 @@ def main():
             plain = 2.0 / (1.0 / a + 1.0 / b)     # half the bytes at each key size
         out["served"] = bench_served(torch, A, dev, plain, args.served_requests)
 
+    # every table layout on the headline workload, each at its best blocks per
+    # thread and workgroup size of the 1 GiB sweep (four tables x 32 copies,
+    # two x 64, one x 64 with two workgroups per compute unit, four x 1)
+    if not args.no_secondary:
+        rk, nr = A.aes_expand_key(key128)
+        lay = {}
+        for layout, bpt in ((0, 4), (1, 4), (3, 2), (4, 4)):
+            A.aes_set_launch(layout=layout, blocks_per_thread=bpt, wg_size=1024)
+            try:
+                cfg = A.aes_get_launch(n, A.AES_MODE_ECB, False, nr)
+                lay["layout%d" % layout] = dict(leg(torch, stream, lambda: A.aes_encrypt(
+                    x, y, n, rk, nr, A.AES_MODE_ECB, stream=stream), n), launch=cfg)
+            finally:
+                A.aes_set_launch(None)
+        out["layouts"] = lay
+
     # the lookup rate the LDS accepts on this device, measured last: the
     # calibration kernel runs at a high clock and power, and measurements
     # taken right after it came out slowed
     lds = bench_lds_gather(torch, A, dev, stream)
     out["lds_gather"] = lds
+    out["lds_gather_one_table"] = bench_lds_gather(torch, A, dev, stream, layout=3)
     roof_issue["measured_peak"] = lds["Tlookup/s"]
     roof_issue["frac_of_measured"] = round(issue_achieved / lds["Tlookup/s"], 4)
     roof_issue["measured_peak_note"] = ("the LDS calibration kernel in the same run: the cipher's lookup "

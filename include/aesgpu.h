@@ -291,6 +291,14 @@ typedef struct {
 int aes_lds_gather(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int *waves, int *tick_khz,
                    void *stream);
 
+/* The same calibration over another table layout, in its launch shape:
+ * layout 0 as aes_lds_gather; layout 3 (one table x 64 copies, 64 KiB) with
+ * as many workgroups per compute unit as fit (two), each lane reading copy
+ * `lane` of the one table.  *waves = workgroups x 16.  Errors as
+ * aes_lds_gather, and AES_E_ARG for another layout. */
+int aes_lds_gather_layout(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int layout, int *waves,
+                          int *tick_khz, void *stream);
+
 
 /* ---------------------------------------------------------------------- */
 /* Batches: many independent messages, each with its own key, length and  */
@@ -374,6 +382,9 @@ typedef struct {
  *                    message slot, at least max_msgs of them), or NULL if
  *                    the batch has no GCM message (a GCM descriptor is then
  *                    refused).
+ *   blocks_per_thread  16-byte blocks each lane carries through the rounds
+ *                    at once in the parallel lists, 2 or 4; 0 = library
+ *                    choice (4).  (XTS pieces always carry 2.)
  * The sequence is: on-device Key Expansion for every message (FIPS-197
  * section 5.2; the decryption schedule of section 5.3.5 where needed) and a
  * plan that puts the messages in three lists (encryption tables, inverse
@@ -405,6 +416,7 @@ typedef struct {
     int max_msgs;
     int tile_blocks;
     aes_gcm_desc *gcm;
+    int blocks_per_thread;
 } aes_batch;
 
 /* Workspace bytes for batches of up to max_msgs messages (any lengths).
@@ -495,6 +507,7 @@ typedef struct {
  *                  exceeds it is rejected (status AES_E_BUDGET), never queued.
  * max_batch_msgs   requests per launch (1..65536).
  * tile_blocks      as for aes_batch (0 = library choice).
+ * blocks_per_thread  as for aes_batch (0 = library choice).
  * timeout_s        the run fails with AES_E_DEVICE if nothing completes for
  *                  this long while work is in flight (0 = 60 s).
  * simulate_gbps    > 0: no device is touched; every launch is taken to finish
@@ -507,6 +520,7 @@ typedef struct {
     uint64_t budget_bytes;
     int max_batch_msgs;
     int tile_blocks;
+    int blocks_per_thread;
     double timeout_s;
     double simulate_gbps;
 } aes_serve_cfg;

@@ -72,6 +72,9 @@ _SIGNATURES = {
     "aes_lds_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_void_p]),
+    "aes_lds_gather_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                             ctypes.c_void_p]),
     "aes_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "aes_batch_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "aes_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -123,7 +126,8 @@ class aes_batch(ctypes.Structure):
                 ("in_base", ctypes.c_void_p), ("in_bytes", ctypes.c_uint64),
                 ("out_base", ctypes.c_void_p), ("out_bytes", ctypes.c_uint64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("max_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int), ("gcm", ctypes.c_void_p)]
+                ("max_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int), ("gcm", ctypes.c_void_p),
+                ("blocks_per_thread", ctypes.c_int)]
 
 
 # aes_request and aes_request_result, as numpy records
@@ -139,6 +143,7 @@ assert REQUEST_DTYPE.itemsize == 48 and RESULT_DTYPE.itemsize == 48
 class aes_serve_cfg(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int), ("budget_bytes", ctypes.c_uint64),
                 ("max_batch_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int),
+                ("blocks_per_thread", ctypes.c_int),
                 ("timeout_s", ctypes.c_double), ("simulate_gbps", ctypes.c_double)]
 
 
@@ -167,7 +172,8 @@ def _load():
 
 lib = _load()
 TUNED_TABLE = os.path.join(HERE, "tuned_gfx950.json")
-TUNED_TILE_BLOCKS = 0      # batch tile size picked by the autotuner (0 = library default)
+TUNED_TILE_BLOCKS = 0      # batch split step picked by the autotuner (0 = library default)
+TUNED_BATCH_BPT = 0        # batch blocks per thread picked by the autotuner (0 = library default)
 
 
 def _check(status):
@@ -395,12 +401,15 @@ def aes_copy(inp, out, nbytes=None, stream=None):
 LDS_GATHER_RECORD_BYTES = 24   # aes_lds_gather_stat: cycles, ticks (uint64), fold, pad (uint32)
 
 
-def aes_lds_gather(out, rounds, stream=None):
-    """Runs the LDS gather calibration kernel; `out` is a device tensor holding
-    one 24-byte record per wave.  Returns (waves, constant-rate clock in kHz)."""
+def aes_lds_gather(out, rounds, stream=None, layout=0):
+    """Runs the LDS gather calibration kernel over table layout 0 (four
+    tables x 32 copies) or 3 (one table x 64 copies, two workgroups per
+    compute unit); `out` is a device tensor holding one 24-byte record per
+    wave.  Returns (waves, constant-rate clock in kHz)."""
     waves, khz = ctypes.c_int(0), ctypes.c_int(0)
-    _check(lib.aes_lds_gather(_dev((out, 0, "out")), out.numel() * out.element_size(), int(rounds),
-                              ctypes.byref(waves), ctypes.byref(khz), _stream_handle(stream, out)))
+    _check(lib.aes_lds_gather_layout(_dev((out, 0, "out")), out.numel() * out.element_size(), int(rounds),
+                                     int(layout), ctypes.byref(waves), ctypes.byref(khz),
+                                     _stream_handle(stream, out)))
     return waves.value, khz.value
 
 
@@ -511,7 +520,8 @@ class Batch:
                messages' additional data and tags), or None
     """
 
-    def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None, device=None, gcm=None):
+    def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None, device=None, gcm=None,
+                 blocks_per_thread=0):
         import torch
         self.device = device or inp.device
         _dev((inp, 0, "inp"), (out, 0, "out"))
@@ -532,7 +542,8 @@ class Batch:
                            in_base=inp.data_ptr(), in_bytes=inp.numel() * inp.element_size(),
                            out_base=out.data_ptr(), out_bytes=out.numel() * out.element_size(),
                            workspace=aligned, workspace_bytes=ws, max_msgs=self.max_msgs,
-                           tile_blocks=self.tile_blocks)
+                           tile_blocks=self.tile_blocks,
+                           blocks_per_thread=int(blocks_per_thread or TUNED_BATCH_BPT))
         self.d_gcm = None
         if gcm is not None:
             self.d_gcm = torch.zeros(self.max_msgs * GCM_DESC_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
@@ -600,13 +611,16 @@ class Batch:
 
 # --- serving ----------------------------------------------------------------
 def serve_cfg(streams=4, budget_bytes=8 << 30, max_batch_msgs=4096, tile_blocks=None,
-              timeout_s=0.0, simulate_gbps=0.0):
-    """A request-loop configuration; tile_blocks None takes the autotuner's
-    split step, the one Batch uses too."""
+              timeout_s=0.0, simulate_gbps=0.0, blocks_per_thread=None):
+    """A request-loop configuration; tile_blocks and blocks_per_thread None
+    take the autotuner's choices, the ones Batch uses too."""
     if tile_blocks is None:
         tile_blocks = TUNED_TILE_BLOCKS
+    if blocks_per_thread is None:
+        blocks_per_thread = TUNED_BATCH_BPT
     return aes_serve_cfg(streams=streams, budget_bytes=budget_bytes,
                          max_batch_msgs=max_batch_msgs, tile_blocks=tile_blocks,
+                         blocks_per_thread=blocks_per_thread,
                          timeout_s=timeout_s, simulate_gbps=simulate_gbps)
 
 
@@ -666,7 +680,7 @@ class Server:
 def _install_tuned():
     """Install the autotuner's committed launch table for gfx950 (the only
     device the library runs on); host-side only, no device is touched."""
-    global TUNED_TILE_BLOCKS
+    global TUNED_TILE_BLOCKS, TUNED_BATCH_BPT
     if not os.path.exists(TUNED_TABLE):
         return
     with open(TUNED_TABLE) as f:
@@ -674,6 +688,7 @@ def _install_tuned():
     aes_set_tuned([dict(mode=e["mode"], decrypt=e["decrypt"], Nr=e["Nr"], min_bytes=e["min_bytes"],
                         cfg=e["cfg"]) for e in table.get("entries", [])])
     TUNED_TILE_BLOCKS = int(table.get("batch_tile_blocks", 0))
+    TUNED_BATCH_BPT = int(table.get("batch_blocks_per_thread", 0))
 
 
 _install_tuned()

@@ -37,6 +37,7 @@ OPS = (("ecb_enc", "ecb", 0), ("ecb_dec", "ecb", 1), ("ctr", "ctr", 0))
 # size buckets: the size tuned at, and the smallest size the result applies to
 BUCKETS = ((1 << 16, 0), (1 << 20, 1 << 18), (1 << 24, 1 << 22), (1 << 30, 1 << 27))
 SPLIT_CANDIDATES = (128, 256, 512, 1024)
+BATCH_BPT_CANDIDATES = (2, 4)
 
 
 def _time(torch, fn, reps, warm=2):
@@ -94,24 +95,36 @@ def tune_plain(A, torch, nrs=(10, 12, 14), buckets=BUCKETS, verbose=False):
 
 
 def tune_batch(A, torch, nmsg=2000, verbose=False):
-    """Best split granularity for the ragged multi-message workload (a
-    2,000-message slice of it)."""
+    """Best split granularity and blocks per thread of the batch kernels
+    (their table layout is the buffer kernels' four tables x 32 copies,
+    which the plain sweep finds fastest for every operation) on the ragged
+    multi-message workload (a 2,000-message slice of it) and on 4 KiB
+    sectors (8,192 messages), scored by the sum of the two times."""
     import seedgen
     lens, keybits, keys, _ = seedgen.ragged_batch(4, nmsg)
-    descs = A.make_descs(lens, keybits=keybits, mode="ecb")
-    total = int(lens.sum())
-    x = seedgen.data_torch(4, 0, total, "cuda")
+    work = [(A.make_descs(lens, keybits=keybits, mode="ecb"), keys, int(lens.sum()))]
+    nsec = 8192
+    skeys = np.zeros((nsec, 32), np.uint8)
+    skeys[:, :16] = np.random.default_rng(6).integers(0, 256, (nsec, 16), dtype=np.uint8)
+    work.append((A.make_descs(np.full(nsec, 4096), keybits=128, mode="ctr", ctr0=np.zeros(16, np.uint8)), skeys,
+                 nsec * 4096))
+    x = seedgen.data_torch(4, 0, max(t for _, _, t in work), "cuda")
     y = torch.empty_like(x)
     results = []
-    for split in SPLIT_CANDIDATES:
-        b = A.Batch(descs, keys, x, y, tile_blocks=split)
-        t = _time(torch, lambda: b.launch_graph(), 5)
-        b.close()
-        results.append(dict(tile_blocks=split, seconds=t, GBps=total / t / 1e9))
-        if verbose:
-            print("batch split %6d: %.1f GB/s" % (split, total / t / 1e9), flush=True)
+    for bpt in BATCH_BPT_CANDIDATES:
+        for split in SPLIT_CANDIDATES:
+            secs = []
+            for descs, k, total in work:
+                b = A.Batch(descs, k, x, y, tile_blocks=split, blocks_per_thread=bpt)
+                secs.append(_time(torch, lambda: b.launch_graph(), 7))
+                b.close()
+            results.append(dict(tile_blocks=split, blocks_per_thread=bpt, seconds=sum(secs),
+                                ragged_GBps=work[0][2] / secs[0] / 1e9, sectors_GBps=work[1][2] / secs[1] / 1e9))
+            if verbose:
+                print("batch split %5d bpt %d: ragged %.1f GB/s, 4 KiB sectors %.1f GB/s"
+                      % (split, bpt, results[-1]["ragged_GBps"], results[-1]["sectors_GBps"]), flush=True)
     best = min(results, key=lambda r: r["seconds"])
-    return best["tile_blocks"], results
+    return best["tile_blocks"], best["blocks_per_thread"], results
 
 
 def device_key(torch):
@@ -152,18 +165,20 @@ def main():
     t0 = time.time()
     if args.batch_only:
         table = load(DEFAULT_TABLE)
-        table["batch_tile_blocks"], blog = tune_batch(A, torch, verbose=True)
+        table["batch_tile_blocks"], table["batch_blocks_per_thread"], blog = tune_batch(A, torch, verbose=True)
         save(args.out or DEFAULT_TABLE, table)
         if args.log:
             save(args.log, {"batch": blog})
-        print("batch_tile_blocks", table["batch_tile_blocks"])
+        print("batch_tile_blocks", table["batch_tile_blocks"], "batch_blocks_per_thread",
+              table["batch_blocks_per_thread"])
         return
     entries, log = tune_plain(A, torch, tuple(args.nr), verbose=True)
     table = {"device": device_key(torch), "entries": entries}
     sweep = {"plain": log}
     if not args.no_batch:
-        split, blog = tune_batch(A, torch, verbose=True)
+        split, bpt, blog = tune_batch(A, torch, verbose=True)
         table["batch_tile_blocks"] = split
+        table["batch_blocks_per_thread"] = bpt
         sweep["batch"] = blog
     table["seconds"] = round(time.time() - t0, 1)
     if args.out:

@@ -374,6 +374,8 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
         return fail(AES_E_ARG, "need 1 <= max_msgs, 0 <= nmsg <= max_msgs and nkeys >= 1");
     if (b->tile_blocks < 0 || b->tile_blocks > kMaxSplitBlocks)
         return fail(AES_E_ARG, "tile_blocks must be 0 .. " + std::to_string(kMaxSplitBlocks));
+    if (b->blocks_per_thread != 0 && b->blocks_per_thread != 2 && b->blocks_per_thread != 4)
+        return fail(AES_E_ARG, "blocks_per_thread must be 0, 2 or 4");
     if ((reinterpret_cast<uintptr_t>(b->in_base) | reinterpret_cast<uintptr_t>(b->out_base)) & 15u)
         return fail(AES_E_ALIGN, "in_base and out_base must be 16-byte aligned");
     if (reinterpret_cast<uintptr_t>(b->workspace) & 255u)
@@ -398,6 +400,7 @@ int batch_args(const aes_batch *b, BatchKArgs *a) {
     a->chunk_totals =
         reinterpret_cast<uint64_t *>(ws + items_off + size_t(kBatchLists) * size_t(b->max_msgs) * sizeof(BatchItem));
     a->split_blocks = uint32_t(b->tile_blocks ? b->tile_blocks : kDefaultSplitBlocks);
+    a->bpt = uint32_t(b->blocks_per_thread ? b->blocks_per_thread : 4);
     a->reject_flags = nullptr;
     a->gcm = b->gcm;
     if (reinterpret_cast<uintptr_t>(b->gcm) & 7u)
@@ -546,10 +549,17 @@ int aes_copy(const void *in, void *out, size_t nbytes, void *stream) {
 
 int aes_lds_gather(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int *waves, int *tick_khz,
                    void *stream) {
+    return aes_lds_gather_layout(out, out_bytes, rounds, LAYOUT_T4X32, waves, tick_khz, stream);
+}
+
+int aes_lds_gather_layout(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int layout, int *waves,
+                          int *tick_khz, void *stream) {
     if (!out || !waves || !tick_khz)
         return fail(AES_E_NULL, "out, waves and tick_khz must not be NULL");
     if (rounds < 1)
         return fail(AES_E_ARG, "need rounds >= 1");
+    if (layout != LAYOUT_T4X32 && layout != LAYOUT_T1X64)
+        return fail(AES_E_ARG, "layout must be 0 (four tables x 32 copies) or 3 (one table x 64 copies)");
     int st = AES_OK;
     const DeviceState *d = current_device(&st);
     if (!d)
@@ -560,11 +570,12 @@ int aes_lds_gather(aes_lds_gather_stat *out, size_t out_bytes, int rounds, int *
         a = hipDeviceGetAttribute(tick_khz, hipDeviceAttributeWallClockRate, dev);
     if (a != hipSuccess)
         return fail(AES_E_DEVICE, std::string("wall clock rate: ") + hipGetErrorString(a));
-    const int nw = d->cus * kLdsGatherWavesPerGroup;
+    const int grid = d->cus * lds_gather_groups_per_cu(layout);
+    const int nw = grid * kLdsGatherWavesPerGroup;
     *waves = nw;
     if (out_bytes < size_t(nw) * sizeof(aes_lds_gather_stat))
         return fail(AES_E_LENGTH, "out must hold one record per wave (" + std::to_string(nw) + " waves)");
-    hipError_t e = launch_lds_gather(out, uint32_t(rounds), d->cus, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_lds_gather(out, uint32_t(rounds), layout, grid, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     return AES_OK;

@@ -1034,15 +1034,18 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
     }
     if (e != hipSuccess || !(lists & 15u))
         return e;
+    using BatchFn = void (*)(const BatchKArgs);
     // the forward kernel also runs the serial list
     if (lists & 5u) {
-        hipLaunchKernelGGL((batch_kernel<0, 4>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        BatchFn fwd = a.bpt == 2 ? batch_kernel<0, 2> : batch_kernel<0, 4>;
+        hipLaunchKernelGGL(fwd, dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
     if (lists & 2u) {
-        hipLaunchKernelGGL((batch_kernel<1, 4>), dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        BatchFn inv = a.bpt == 2 ? batch_kernel<1, 2> : batch_kernel<1, 4>;
+        hipLaunchKernelGGL(inv, dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -68,7 +68,9 @@ hipError_t launch_copy(const void *in, void *out, uint64_t nbytes, int grid, hip
 using LdsGatherStat = aes_lds_gather_stat;
 constexpr int kLdsGatherWavesPerGroup = 16;
 uint32_t lds_gather_reads_per_round();
-hipError_t launch_lds_gather(LdsGatherStat *out, uint32_t rounds, int grid, hipStream_t stream);
+// layout: LAYOUT_T4X32 or LAYOUT_T1X64; grid = compute units x lds_gather_groups_per_cu(layout)
+int lds_gather_groups_per_cu(int layout);
+hipError_t launch_lds_gather(LdsGatherStat *out, uint32_t rounds, int layout, int grid, hipStream_t stream);
 // CBC encryption is serial: one lane walks the whole buffer.
 hipError_t launch_cbc_encrypt(int nr, const CipherArgs &a, hipStream_t stream);
 // The bitsliced comparison kernel (bitslice.hip): encryption only.
@@ -189,6 +191,7 @@ struct BatchKArgs {
     BatchItem *items;        // kBatchLists lists of max_msgs entries
     uint64_t *chunk_totals;  // the plan's counters per chunk of messages
     uint32_t split_blocks;   // a share starts and ends on a multiple of this
+    uint32_t bpt;            // blocks per lane in the parallel lists: 2 or 4
     uint8_t *reject_flags;   // NULL, or one byte per message, set to 1 for each
                              // message the descriptor check refuses (the
                              // caller clears them; the request loop points

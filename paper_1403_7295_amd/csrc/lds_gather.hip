@@ -4,13 +4,15 @@
 // traffic and almost no VALU work, and so measures the lookup rate the
 // cipher's issue roofline is compared with on the device at hand.
 //
-// Launch shape as the cipher: one 1024-thread workgroup per compute unit, 16
-// waves, a 128 KiB LDS array laid out as the cipher's four round tables (256
-// entries of 32 copies each, copy = lane & 31, so every lane reads its own
-// bank).  Per round each lane takes four words, one per column as the cipher
-// has, and looks byte K of each up in table K: 16 reads, each address built
-// by one v_perm_b32 from the word and a per-lane constant, the 16 words
-// folded by three-input XORs.  That is the cipher's lookup instruction
+// Launch shape as the cipher: 1024-thread workgroups, 16 waves each, as many
+// per compute unit as fit.  The LDS array is laid out as one of the cipher's
+// table layouts: four round tables of 256 entries x 32 copies (copy = lane &
+// 31, 128 KiB, one workgroup per CU), or one table x 64 copies at a 256-byte
+// stride (copy = lane, 64 KiB, two workgroups per CU).  Per round each lane
+// takes four words, one per column as the cipher has, and looks byte K of
+// each up in table K (or in the one table): 16 reads, each address built by
+// one v_perm_b32 from the word and a per-lane constant, the 16 words folded
+// by three-input XORs.  That is the cipher's lookup instruction
 // stream; what it leaves out is global memory, the round keys, and the
 // dependence of a round's addresses on the previous round's reads: the
 // words advance by a constant each round instead, so the loop measures what
@@ -26,26 +28,31 @@
 namespace aesgpu {
 namespace {
 
-constexpr uint32_t kGatherWords = 32768;   // 128 KiB, the size of the round tables
 constexpr uint32_t kGatherReads = 16;      // reads per lane per round
+
+// words of the LDS array: 128 KiB (four tables x 32 copies) or 64 KiB (one table x 64 copies)
+template <int LAYOUT>
+constexpr uint32_t gather_words() { return LAYOUT == LAYOUT_T1X64 ? 16384u : 32768u; }
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+template <int LAYOUT>
 __global__ __launch_bounds__(1024) void lds_gather_kernel(LdsGatherStat *out, uint32_t rounds) {
-    __shared__ uint32_t lds[kGatherWords];
-    for (uint32_t i = threadIdx.x; i < kGatherWords; i += blockDim.x)
+    __shared__ uint32_t lds[gather_words<LAYOUT>()];
+    for (uint32_t i = threadIdx.x; i < gather_words<LAYOUT>(); i += blockDim.x)
         lds[i] = i * 0x9E3779B1u;
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63u;
     const char *bytes = reinterpret_cast<const char *>(lds);
-    // byte 0: copy (lane & 31) and table bit 0; byte 1: table bit 1 (to address bit 16)
+    // four tables: byte 0 the copy (lane & 31) and table bit 0, byte 1 table
+    // bit 1 (to address bit 16); one table: byte 0 the copy (lane)
     uint32_t lc[4];
 #pragma unroll
     for (uint32_t t = 0; t < 4; t++)
-        lc[t] = ((lane & 31u) << 2) | ((t & 1u) << 7) | ((t >> 1) << 8);
+        lc[t] = LAYOUT == LAYOUT_T1X64 ? (lane << 2) : ((lane & 31u) << 2) | ((t & 1u) << 7) | ((t >> 1) << 8);
     uint32_t w[4];
 #pragma unroll
     for (uint32_t c = 0; c < 4; c++)
@@ -92,8 +99,20 @@ __global__ __launch_bounds__(1024) void lds_gather_kernel(LdsGatherStat *out, ui
 
 uint32_t lds_gather_reads_per_round() { return kGatherReads; }
 
-hipError_t launch_lds_gather(LdsGatherStat *out, uint32_t rounds, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL(lds_gather_kernel, dim3(grid), dim3(1024), 0, stream, out, rounds);
+int lds_gather_groups_per_cu(int layout) {
+    int n = 0;
+    const void *fn = layout == LAYOUT_T1X64 ? reinterpret_cast<const void *>(lds_gather_kernel<LAYOUT_T1X64>)
+                                            : reinterpret_cast<const void *>(lds_gather_kernel<LAYOUT_T4X32>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 1024, 0) != hipSuccess || n < 1)
+        n = 1;
+    return n;
+}
+
+hipError_t launch_lds_gather(LdsGatherStat *out, uint32_t rounds, int layout, int grid, hipStream_t stream) {
+    if (layout == LAYOUT_T1X64)
+        hipLaunchKernelGGL(lds_gather_kernel<LAYOUT_T1X64>, dim3(grid), dim3(1024), 0, stream, out, rounds);
+    else
+        hipLaunchKernelGGL(lds_gather_kernel<LAYOUT_T4X32>, dim3(grid), dim3(1024), 0, stream, out, rounds);
     return hipGetLastError();
 }
 

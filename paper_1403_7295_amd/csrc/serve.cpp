@@ -63,7 +63,8 @@ struct ServeLayout {
 
 bool make_layout(const aes_serve_cfg &c, ServeLayout *L) {
     if (c.streams < 1 || c.streams > kMaxStreams || c.max_batch_msgs < 1 || c.max_batch_msgs > 65536 ||
-        c.budget_bytes < kAlign || c.tile_blocks < 0 || c.tile_blocks > kMaxSplitBlocks)
+        c.budget_bytes < kAlign || c.tile_blocks < 0 || c.tile_blocks > kMaxSplitBlocks ||
+        (c.blocks_per_thread != 0 && c.blocks_per_thread != 2 && c.blocks_per_thread != 4))
         return false;
     L->arena = c.budget_bytes / kAlign * kAlign;
     L->desc_off = sizeof(SlotHeader);
@@ -202,6 +203,7 @@ struct Loop {
             b.workspace_bytes = L.ws_bytes;
             b.max_msgs = cfg.max_batch_msgs;
             b.tile_blocks = cfg.tile_blocks;
+            b.blocks_per_thread = cfg.blocks_per_thread;
             b.gcm = (lists & 8u) ? reinterpret_cast<aes_gcm_desc *>(static_cast<uint8_t *>(s.host_dev) + L.gcm_off)
                                  : nullptr;
             BatchKArgs ka;
@@ -394,7 +396,7 @@ int aes_serve_scratch_size(const aes_serve_cfg *cfg, size_t *bytes) {
     ServeLayout L;
     if (!make_layout(*cfg, &L))
         return serve_fail(AES_E_ARG, "streams 1..16, max_batch_msgs 1..65536, budget_bytes >= 256, "
-                                     "tile_blocks 0 .. 1024");
+                                     "tile_blocks 0 .. 1024, blocks_per_thread 0, 2 or 4");
     *bytes = L.total;
     return AES_OK;
 }

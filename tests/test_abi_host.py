@@ -222,6 +222,8 @@ def test_batch_argument_checks(A):
     assert code(batch(tile_blocks=-1)) == A.AES_E_ARG
     assert code(batch(tile_blocks=1025)) == A.AES_E_ARG
     assert code(batch(gcm=0x600004)) == A.AES_E_ALIGN
+    for bpt in (1, 3, 8, -2):
+        assert code(batch(blocks_per_thread=bpt)) == A.AES_E_ARG
 
 
 def test_gcm_batch_layout(A):
@@ -229,7 +231,7 @@ def test_gcm_batch_layout(A):
     assert A.GCM_DESC_DTYPE.itemsize == 32
     # the gcm pointer follows tile_blocks at the end of aes_batch
     assert A.aes_batch.gcm.offset == A.aes_batch.tile_blocks.offset + 4 == 96
-    assert ctypes.sizeof(A.aes_batch) == 104
+    assert A.aes_batch.blocks_per_thread.offset == 104 and ctypes.sizeof(A.aes_batch) == 112
     assert A.AES_MODE_GCM == 4 and A.MODES["gcm"] == 4
     text = open(HEADER).read()
     assert "AES_MODE_GCM = 4" in text

@@ -115,6 +115,18 @@ def test_split_granularity_and_order_do_not_matter(A, tile_blocks):
     assert torch.equal(y0, y1)
 
 
+@pytest.mark.parametrize("bpt", [2, 4])
+def test_blocks_per_thread_matches_oracle(A, O, bpt):
+    # both block-loop widths the autotuner chooses between, every mode
+    descs, keys = mixed_messages(A, 150, 46, max_len=1 << 18)
+    x, xd, yd = buffers(descs, 46)
+    b = A.Batch(descs, keys, xd, yd, blocks_per_thread=bpt)
+    assert b.c.blocks_per_thread == bpt
+    b.run()
+    assert b.query()[1] == 0
+    check_against_oracle(O, descs, keys, x, yd.cpu().numpy())
+
+
 def test_in_place(A, O):
     descs, keys = mixed_messages(A, 50, 43, modes=2)   # CBC decryption cannot run in place
     x, xd, _ = buffers(descs, 43)

@@ -191,18 +191,22 @@ def test_copy_helper(A):
     assert torch.equal(x, y)
 
 
-def lds_gather_folds(blocks, rounds):
+def lds_gather_folds(blocks, rounds, layout=0):
     """What each workgroup of the LDS calibration kernel must report: word i
     of the LDS holds i * 0x9E3779B1; lane l of workgroup b starts column word
     c at (l + 64 c + 1) * 0x9E3779B1 ^ b, adds 0x3B5D7F91 + c per round and
-    reads, in table K, entry byte K of that word, copy l & 31; the wave's
-    fold is the XOR of every word read and of the lane numbers."""
+    reads, in table K, entry byte K of that word, copy l & 31 (layout 0), or
+    that entry of the one table, copy l (layout 3); the wave's fold is the
+    XOR of every word read and of the lane numbers."""
     m = np.uint64(0xFFFFFFFF)
     phi = np.uint64(0x9E3779B1)
     lane = np.arange(64, dtype=np.uint64)[None, :]
     b = np.arange(blocks, dtype=np.uint64)[:, None]
-    lc = [((lane & np.uint64(31)) << np.uint64(2)) | np.uint64((t & 1) << 7) | np.uint64((t >> 1) << 16)
-          for t in range(4)]
+    if layout == 3:
+        lc = [lane << np.uint64(2) for t in range(4)]
+    else:
+        lc = [((lane & np.uint64(31)) << np.uint64(2)) | np.uint64((t & 1) << 7) | np.uint64((t >> 1) << 16)
+              for t in range(4)]
     w = [(((lane + np.uint64(64 * c + 1)) * phi) & m) ^ b for c in range(4)]
     acc = np.zeros((blocks, 64), np.uint64)
     for _ in range(rounds):
@@ -235,6 +239,16 @@ def test_lds_gather_helper(A):
     assert e.value.code == A.AES_E_LENGTH
     with pytest.raises(A.AESError) as e:
         A.aes_lds_gather(rec, 0)
+    assert e.value.code == A.AES_E_ARG
+    # the one-table layout: two workgroups per compute unit, copy = lane
+    rec2 = torch.full((2 * waves * 3,), -1, dtype=torch.int64, device="cuda")
+    w2, _ = A.aes_lds_gather(rec2, rounds, layout=3)
+    torch.cuda.synchronize()
+    assert w2 == 2 * waves
+    fold2 = rec2.view(-1, 3).cpu().numpy()[:, 2].astype(np.uint64)
+    assert np.array_equal(fold2, np.repeat(lds_gather_folds(2 * cus, rounds, layout=3), 16))
+    with pytest.raises(A.AESError) as e:
+        A.aes_lds_gather(rec2, rounds, layout=1)
     assert e.value.code == A.AES_E_ARG
 
 

@@ -113,7 +113,8 @@ def test_argument_checks(A):
     with pytest.raises(A.AESError) as e:
         A.aes_serve_run(bad, A.serve_cfg(budget_bytes=1 << 40, simulate_gbps=10.0))
     assert e.value.code == A.AES_E_LENGTH
-    for kw in ({"streams": 0}, {"streams": 17}, {"max_batch_msgs": 0}, {"budget_bytes": 100}):
+    for kw in ({"streams": 0}, {"streams": 17}, {"max_batch_msgs": 0}, {"budget_bytes": 100},
+               {"blocks_per_thread": 3}):
         with pytest.raises(A.AESError) as e:
             A.aes_serve_scratch_size(A.serve_cfg(**kw))
         assert e.value.code == A.AES_E_ARG
