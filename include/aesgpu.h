@@ -394,7 +394,7 @@ typedef struct {
  * persistent kernels, one workgroup per compute unit, in which every wave
  * runs its share.  GCM messages run their CTR part (from J0 + 1) in the
  * forward list; then their GHASH (section 6.4) over the additional data,
- * the ciphertext and the lengths is cut into pieces of up to 16,384 blocks,
+ * the ciphertext and the lengths is cut into pieces of up to 4,096 blocks,
  * one wave per piece (the pieces' sums are added by linearity), and a last
  * kernel forms or checks each tag.  A message with an invalid descriptor (bad key code or
  * mode, ECB length not a multiple of 16, misaligned offset, outside the

@@ -36,17 +36,25 @@ __global__ __launch_bounds__(1024) void cipher_kernel(const CipherArgs a) {
                                                wave * 64u * BPT, nblk, sweep);
 }
 
-// CBC encryption of one buffer: inherently serial, so lane 0 of the first
-// wave does all of it after the workgroup has staged the tables.
+// CBC encryption of one buffer: inherently serial, so the first quad of
+// lanes does all of it (one column of the state each) after the workgroup
+// has staged the tables.
 template <int NR>
 __global__ __launch_bounds__(256) void cbc_encrypt_kernel(const CipherArgs a) {
     __shared__ uint32_t lds[lds_words<DIR_ENC>()];
     stage_tables<LAYOUT_T4X32, DIR_ENC>(lds);
     __syncthreads();
-    if (threadIdx.x != 0)
+    if (threadIdx.x >= 4)
         return;
-    const LaneConsts lc = lane_consts<LAYOUT_T4X32>(0);
-    cbc_encrypt_serial<NR, LAYOUT_T4X32>(lds, lc, a.rk, a.ctr, a.in, a.out, a.nbytes >> 4);
+    const uint32_t j = threadIdx.x;
+    const LaneConsts lc = lane_consts<LAYOUT_T4X32>(j);
+    // this lane's column of every round key, and of the IV
+    uint32_t rk[NR + 1];
+#pragma unroll
+    for (int r = 0; r <= NR; r++)
+        rk[r] = j == 0 ? a.rk[4 * r] : j == 1 ? a.rk[4 * r + 1] : j == 2 ? a.rk[4 * r + 2] : a.rk[4 * r + 3];
+    const uint32_t iv = j == 0 ? a.ctr[0] : j == 1 ? a.ctr[1] : j == 2 ? a.ctr[2] : a.ctr[3];
+    cbc_encrypt_quad<NR, LAYOUT_T4X32>(lds, lc, rk, iv, a.in, a.out, a.nbytes >> 4);
 }
 
 template <int BPT>

@@ -257,6 +257,17 @@ __device__ __forceinline__ void expand_message_keys(const BatchKArgs &a, const a
         g[kGcmSlotH / 4] = vec4(h[0], h[1], h[2], h[3]);
         g[kGcmSlotEJ0 / 4] = vec4(e[0], e[1], e[2], e[3]);
         g[kGcmSlotSum / 4] = vec4(0, 0, 0, 0);
+        // H^(kGhashPiece * 2^t): the factors of the GHASH pieces' positions
+        uint64_t lo, hi;
+        to_poly(h, lo, hi);
+        for (int t = 0; t < kGhashPieceLog2; t++)
+            gf_square(lo, hi);
+        for (int t = 0; t < kGcmSlotPowers; t++) {
+            uint32_t pw[4];
+            from_poly(lo, hi, pw);
+            g[kGcmSlotPow / 4 + t] = vec4(pw[0], pw[1], pw[2], pw[3]);
+            gf_square(lo, hi);
+        }
     }
 }
 
@@ -566,53 +577,54 @@ __device__ __forceinline__ void run_xts_range(const uint32_t *lds, const LaneCon
                                 first_unit + (gb0 >> ushift), ushift);
 }
 
-// The serial list (CBC encryption): one message per lane, each lane
-// encrypting its message block after block with its own round keys.  Wave w
-// takes messages 64w .. 64w+63 first; only when there are more than 64 per
-// wave are the rest handed out 64 at a time from a counter.  These run
-// before the wave's parallel share, so the long serial chains start early.
+// The serial list (CBC encryption): one message per quad of four lanes,
+// each lane carrying one column of the state (cbc_encrypt_quad), each
+// message with its own round keys (a lane holds its column of every round
+// key).  Wave w takes messages 16w .. 16w+15 first; only when there are
+// more than 16 per wave are the rest handed out 16 at a time from a
+// counter.  These run before the wave's parallel share, so the long serial
+// chains start early.
+template <int NR>
+__device__ __forceinline__ void serial_message(const uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a,
+                                               const BatchItem &item) {
+    const uint32_t j = threadIdx.x & 3u;
+    const aes_msg_desc d = a.desc[item.msg];
+    const uint32_t *rkp = a.keytab + size_t(item.msg) * kKeySlotWords;
+    uint32_t rk[NR + 1];
+#pragma unroll
+    for (int r = 0; r <= NR; r++)
+        rk[r] = rkp[4 * r + j];
+    const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
+    uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
+    cbc_encrypt_quad<NR, LAYOUT_T4X32>(lds, lc, rk, le32(d.ctr0 + 4 * j), in, out, item.count);
+}
+
 __device__ __forceinline__ void run_serial(const uint32_t *lds, const BatchKArgs &a, uint32_t n, uint32_t wave,
                                            uint32_t nwaves) {
     const uint32_t lane = threadIdx.x & 63u;
     const BatchItem *list = a.items + size_t(2) * a.max_msgs;
     const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
-    const uint64_t statics = uint64_t(nwaves) * 64u;
-    uint64_t t0 = uint64_t(wave) * 64u;
+    constexpr uint32_t kPerWave = 16;   // quads per wave
+    const uint64_t statics = uint64_t(nwaves) * kPerWave;
+    uint64_t t0 = uint64_t(wave) * kPerWave;
     while (t0 < n) {
-        const uint64_t t = t0 + lane;
+        const uint64_t t = t0 + (lane >> 2);
+        // the four lanes of a quad take the same message, so they are active together
         if (t < n) {
             const BatchItem item = list[t];
-            const aes_msg_desc d = a.desc[item.msg];
-            const uint32_t *rkp = a.keytab + size_t(item.msg) * kKeySlotWords;
-            uint32_t iv[4];
-            for (int i = 0; i < 4; i++)
-                iv[i] = le32(d.ctr0 + 4 * i);
-            const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
-            uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
-            const int nr = desc_nr(d);
-            uint32_t rk[60];
-            if (nr == 10) {
-#pragma unroll
-                for (int i = 0; i < 44; i++)
-                    rk[i] = rkp[i];
-                cbc_encrypt_serial<10, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, item.count);
-            } else if (nr == 12) {
-#pragma unroll
-                for (int i = 0; i < 52; i++)
-                    rk[i] = rkp[i];
-                cbc_encrypt_serial<12, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, item.count);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 60; i++)
-                    rk[i] = rkp[i];
-                cbc_encrypt_serial<14, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, item.count);
-            }
+            const int nr = desc_nr(a.desc[item.msg]);
+            if (nr == 10)
+                serial_message<10>(lds, lc, a, item);
+            else if (nr == 12)
+                serial_message<12>(lds, lc, a, item);
+            else
+                serial_message<14>(lds, lc, a, item);
         }
         if (n <= statics)
             break;
         uint64_t c = 0;
         if (lane == 0)
-            c = atomicAdd(reinterpret_cast<unsigned long long *>(&a.header->next[2]), 64ull);
+            c = atomicAdd(reinterpret_cast<unsigned long long *>(&a.header->next[2]), uint64_t(kPerWave));
         t0 = statics + uniform64(c);
     }
 }
@@ -808,7 +820,9 @@ __device__ __forceinline__ u32x4 ghash_block(uint64_t r, uint64_t nC, uint64_t n
 // takes positions p_lo + 64q + l, Horner over q from the top with the
 // multiplier G = H^64 (one table); the lanes are folded with H, H^2, ..,
 // H^32 (a tree, each level's table built in the same space); the result is
-// multiplied by H^(p_lo + 1) (square and multiply, by the whole wave).
+// multiplied by H and by H^(p_lo) = product of the stored powers
+// H^(kGhashPiece 2^t) over the set bits t of the piece index (products by
+// the whole wave).
 __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, uint32_t vec, const BatchKArgs &a,
                                             uint32_t msg, uint64_t piece) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -863,13 +877,19 @@ __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, uint32_
     }
     // times H^(p_lo + 1): lane 0's sum, the same in every lane
     const uint32_t s0[4] = {uniform32(w[0]), uniform32(w[1]), uniform32(w[2]), uniform32(w[3])};
-    uint64_t rlo, rhi, blo = hlo, bhi = hhi;
+    uint64_t rlo, rhi, blo = 0, bhi = 0;
     to_poly(s0, rlo, rhi);
-    for (uint64_t e = p_lo + 1; e; e >>= 1) {
-        if (e & 1)
+    mul_wave(rlo, rhi, hlo, hhi, rlo, rhi);
+    for (int t = 0; (piece >> t) != 0; t++) {
+        if (t < kGcmSlotPowers) {
+            const uint32_t pw[4] = {uniform32(slot[kGcmSlotPow + 4 * t]), uniform32(slot[kGcmSlotPow + 4 * t + 1]),
+                                    uniform32(slot[kGcmSlotPow + 4 * t + 2]), uniform32(slot[kGcmSlotPow + 4 * t + 3])};
+            to_poly(pw, blo, bhi);
+        } else {
+            gf_square(blo, bhi);   // beyond the stored powers (messages over 2^(12+13) blocks)
+        }
+        if ((piece >> t) & 1)
             mul_wave(rlo, rhi, blo, bhi, rlo, rhi);
-        if (e > 1)
-            gf_square(blo, bhi);
     }
     uint32_t res[4];
     from_poly(rlo, rhi, res);

@@ -491,42 +491,67 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
     }
 }
 
-// CBC encryption of one whole message by one lane (each block depends on the
-// previous ciphertext, SP 800-38A section 6.2).  rk holds this lane's round
-// keys (registers), iv the initial chaining value.  The chain is serial but
+// CBC encryption (SP 800-38A section 6.2): each block depends on the
+// previous ciphertext, so a message is one chain.  The chain is serial but
 // the plaintext is not: blocks are read a group of kCbcGroup ahead, so a
 // group's loads are in flight while the previous group is enciphered and
 // neither the read latency nor the completion of the last store stalls a
 // block.
 constexpr int kCbcGroup = 4;
 
+// CBC encryption of one message by a quad of four lanes (lanes 4q .. 4q+3
+// of a wave, all four active together): lane j of the quad holds column j
+// of the state, looks up the four bytes of its own column (byte r in table
+// r) and the round's output column i gathers table r's entry from lane
+// i + r of the quad, a quad permute inside the XOR (DPP), so the sixteen
+// lookups of a round are spread over four lanes instead of waiting in one.
+// rk_col[r] is round key word 4r + j (this lane's column of round key r);
+// iv_col is word j of the IV.  Plaintext words are read a group of
+// kCbcGroup blocks ahead, as in the one-lane form.
+// quad_perm controls: lane i of every quad reads lane i + 1, i + 2, i + 3 (mod 4)
+constexpr int kQuadNext1 = 0x39, kQuadNext2 = 0x4E, kQuadNext3 = 0x93;
+template <int QUAD_PERM>
+__device__ __forceinline__ uint32_t quad_from(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_mov_dpp(int(v), QUAD_PERM, 0xF, 0xF, false));
+}
+
 template <int NR, int LAYOUT>
-__device__ __forceinline__ void cbc_encrypt_serial(const uint32_t *lds, const LaneConsts &lc,
-                                                   const uint32_t *rk, const uint32_t *iv,
-                                                   const uint8_t *in, uint8_t *out, uint64_t nblocks) {
-    uint32_t c0 = iv[0], c1 = iv[1], c2 = iv[2], c3 = iv[3];
-    u32x4 cur[kCbcGroup];
+__device__ __forceinline__ void cbc_encrypt_quad(const uint32_t *lds, const LaneConsts &lc,
+                                                 const uint32_t (&rk_col)[NR + 1], uint32_t iv_col,
+                                                 const uint8_t *in, uint8_t *out, uint64_t nblocks) {
+    const uint32_t j = threadIdx.x & 3u;
+    uint32_t c = iv_col;
+    uint32_t cur[kCbcGroup];
 #pragma unroll
     for (int i = 0; i < kCbcGroup; i++)
-        cur[i] = uint64_t(i) < nblocks ? *reinterpret_cast<const u32x4 *>(in + 16 * i) : vec4(0, 0, 0, 0);
+        cur[i] = uint64_t(i) < nblocks ? *reinterpret_cast<const uint32_t *>(in + 16 * i + 4 * j) : 0u;
     for (uint64_t g = 0; g < nblocks; g += kCbcGroup) {
-        u32x4 nxt[kCbcGroup];
+        uint32_t nxt[kCbcGroup];
 #pragma unroll
         for (int i = 0; i < kCbcGroup; i++) {
-            const uint64_t j = g + kCbcGroup + i;
-            nxt[i] = j < nblocks ? *reinterpret_cast<const u32x4 *>(in + 16 * j) : vec4(0, 0, 0, 0);
+            const uint64_t b = g + kCbcGroup + i;
+            nxt[i] = b < nblocks ? *reinterpret_cast<const uint32_t *>(in + 16 * b + 4 * j) : 0u;
         }
 #pragma unroll
         for (int i = 0; i < kCbcGroup; i++) {
             if (g + i < nblocks) {
-                const u32x4 x = cur[i];
-                uint32_t st[1][4] = {{x.x ^ c0 ^ rk[0], x.y ^ c1 ^ rk[1], x.z ^ c2 ^ rk[2], x.w ^ c3 ^ rk[3]}};
-                rounds<NR, DIR_ENC, LAYOUT, 1>(st, lds, lc, rk, 1);
-                c0 = st[0][0];
-                c1 = st[0][1];
-                c2 = st[0][2];
-                c3 = st[0][3];
-                *reinterpret_cast<u32x4 *>(out + 16 * (g + i)) = vec4(c0, c1, c2, c3);
+                uint32_t s = cur[i] ^ c ^ rk_col[0];
+#pragma unroll
+                for (int r = 1; r < NR; r++) {
+                    const uint32_t u0 = tl<LAYOUT, 0, 0>(lds, lc, s), u1 = tl<LAYOUT, 1, 1>(lds, lc, s);
+                    const uint32_t u2 = tl<LAYOUT, 2, 2>(lds, lc, s), u3 = tl<LAYOUT, 3, 3>(lds, lc, s);
+                    s = (((u0 ^ rk_col[r]) ^ quad_from<kQuadNext1>(u1)) ^ quad_from<kQuadNext2>(u2)) ^
+                        quad_from<kQuadNext3>(u3);
+                }
+                // last round: S of byte r in byte r of the output column (T3
+                // holds S in byte 0, T0 in bytes 1 and 2, T1 in byte 3)
+                const uint32_t f0 = tl<LAYOUT, 3, 0>(lds, lc, s) & 0x000000FFu;
+                const uint32_t f1 = tl<LAYOUT, 0, 1>(lds, lc, s) & 0x0000FF00u;
+                const uint32_t f2 = tl<LAYOUT, 0, 2>(lds, lc, s) & 0x00FF0000u;
+                const uint32_t f3 = tl<LAYOUT, 1, 3>(lds, lc, s) & 0xFF000000u;
+                c = (((f0 ^ rk_col[NR]) ^ quad_from<kQuadNext1>(f1)) ^ quad_from<kQuadNext2>(f2)) ^
+                    quad_from<kQuadNext3>(f3);
+                *reinterpret_cast<uint32_t *>(out + 16 * (g + i) + 4 * j) = c;
             }
         }
 #pragma unroll

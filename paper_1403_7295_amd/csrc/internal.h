@@ -154,12 +154,15 @@ struct BatchItem {
 
 // encryption schedule at 0, decryption schedule at 64; an XTS message keeps
 // its tweak key's encryption schedule in the half its direction leaves free;
-// a GCM message keeps H = Cipher_K(0), Cipher_K(J0) and its GHASH sum there
+// a GCM message keeps H = Cipher_K(0), Cipher_K(J0), its GHASH sum and the
+// powers H^(kGhashPiece * 2^t), t < kGcmSlotPowers, there
 constexpr int kKeySlotWords = 128;
-constexpr int kGcmSlotH = 64, kGcmSlotEJ0 = 68, kGcmSlotSum = 72;
+constexpr int kGcmSlotH = 64, kGcmSlotEJ0 = 68, kGcmSlotSum = 72, kGcmSlotPow = 76, kGcmSlotPowers = 13;
+static_assert(kGcmSlotPow + 4 * kGcmSlotPowers <= kKeySlotWords, "GCM powers fit the key slot");
 // GHASH positions (16-byte blocks of additional data, ciphertext and the
 // length block) per piece: one wave hashes one piece
-constexpr uint64_t kGhashPiece = 16384;
+constexpr int kGhashPieceLog2 = 12;
+constexpr uint64_t kGhashPiece = uint64_t(1) << kGhashPieceLog2;
 // A wave's share of a message starts and ends on a multiple of this many
 // blocks by default (four steps of the block loop, 64 lanes x 2 blocks; the
 // best of 128 .. 1024 over batch sizes from one message to gigabytes).  The

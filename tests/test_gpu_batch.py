@@ -542,3 +542,35 @@ def test_gcm_batch_refuses_bad_fields(A, O):
     b2 = A.Batch(descs, keys, xd, yd)
     b2.run()
     assert b2.query()[1] == n
+
+
+def test_gcm_batch_message_beyond_the_stored_powers(A):
+    """One GCM message of 512 MiB + 80 KiB: its GHASH pieces run past the
+    13 powers H^(4096 * 2^t) kept per message, so the last ones square on.
+    It equals the single-buffer GCM kernels' ciphertext and tag (a separate
+    implementation, checked against the oracle elsewhere, at 1 GiB through
+    GHASH's linearity)."""
+    n = (512 << 20) + 80 * 1024 + 7
+    key = np.zeros((1, 32), np.uint8)
+    key[0, :16] = seedgen.key(73, 0, 128)
+    iv = seedgen.nonce(73, 0)[:12]
+    x = seedgen.data_torch(73, 0, n + 64, "cuda")
+    y = torch.zeros_like(x)
+    aad_off = (n + 15) // 16 * 16                      # 48 bytes of additional data after the message
+    descs = A.make_descs([n], in_off=[0], keybits=128, mode="gcm", ctr0=np.concatenate([iv, np.zeros(4, np.uint8)]))
+    g = np.zeros(1, A.GCM_DESC_DTYPE)
+    g["aad_off"], g["aad_bytes"], g["tag_off"], g["tag_bytes"] = aad_off, 48, aad_off, 16
+    b = A.Batch(descs, key, x, y, gcm=g)
+    b.run()
+    assert b.query() == (1, 0)
+    assert b.gcm_results(1)["ok"][0] == 1
+    rk, nr = A.aes_expand_key(key[0, :16])
+    ws = torch.zeros(A.aes_gcm_workspace_size(), dtype=torch.uint8, device="cuda")
+    ref_out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    tag = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    A.aes_gcm_encrypt(x[:n], ref_out, n, x[aad_off:aad_off + 48], 48, rk, nr, iv, tag, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(y[:n], ref_out)
+    assert torch.equal(y[aad_off:aad_off + 16], tag)
+    del x, y, ref_out
+    torch.cuda.empty_cache()
