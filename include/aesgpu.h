@@ -440,7 +440,7 @@ int aes_batch_run(const aes_batch *b, void *stream);
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * The batch's workspace is not the caller's: it is a buffer the library
  * holds in device memory for the life of the process, one per device
- * (AES_BATCH_NOALLOC_MAX_MSGS messages' worth, about 8.8 MiB), set up with
+ * (AES_BATCH_NOALLOC_MAX_MSGS messages' worth, about 9.0 MiB), set up with
  * the device's other state on the first call.  The call allocates nothing;
  * the caller still passes descriptors, keys, input and output as for
  * aes_batch_run, with b->workspace NULL and b->workspace_bytes 0.

@@ -316,7 +316,9 @@ __device__ __forceinline__ void block_exclusive_scan(uint64_t (&v)[N], uint64_t 
     }
 }
 
-// items in lists 0, 1, 2; cost of lists 0, 1; rejected; GCM messages; their GHASH pieces
+// items in lists 0, 1, 2; cost of lists 0, 1; rejected; GCM messages; their
+// GHASH pieces; the short ones among them (at most kLaneGhashMaxPositions
+// positions: one piece each)
 constexpr int kPlanCounters = kBatchChunkCounters;
 
 // GHASH positions of a GCM message: its additional data, its ciphertext
@@ -356,23 +358,52 @@ __device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, 
     c[3] = k == 0 ? cost : 0;
     c[4] = k == 1 ? cost : 0;
     if (d.mode == AES_MODE_GCM) {
+        const uint64_t npos = ghash_positions(d, a.gcm[m]);
         c[6] = 1;
-        c[7] = (ghash_positions(d, a.gcm[m]) + kGhashPiece - 1) / kGhashPiece;
+        c[7] = (npos + kGhashPiece - 1) / kGhashPiece;
+        c[8] = npos <= kLaneGhashMaxPositions ? 1 : 0;
     }
 }
 
+// Whether the batch hashes its short GCM messages one per lane: when there
+// are enough of them that a wave per message would cost more (each wave
+// builds seven multiplier tables and folds its lanes for a few Horner steps)
+// than one pass of the longest allowed message through a lane.
+__device__ __forceinline__ bool lane_ghash(const uint64_t (&total)[kPlanCounters]) {
+    return total[8] >= kLaneGhashMinMessages;
+}
+
+// The GHASH counts of the header: messages and pieces hashed by waves, and
+// messages hashed by lanes.
+__device__ __forceinline__ void gcm_header(BatchHeader *h, const uint64_t (&total)[kPlanCounters]) {
+    const uint64_t short_msgs = lane_ghash(total) ? total[8] : 0;
+    h->ngcm = uint32_t(total[6] - short_msgs);
+    h->gcm_pieces = total[7] - short_msgs;
+    h->nlane = uint32_t(short_msgs);
+}
+
 // The GHASH list's item of GCM message m: its pieces, and the pieces of the
-// GCM messages before it (c: the message's exclusive prefix of the counters).
+// GCM messages before it (c: the message's exclusive prefix of the counters),
+// or, for a short message when the batch hashes those per lane, its place at
+// the back of the list.
 __device__ __forceinline__ void gcm_item(const BatchKArgs &a, uint32_t m, const uint64_t (&before)[kPlanCounters],
-                                         const uint64_t (&c)[kPlanCounters]) {
+                                         const uint64_t (&c)[kPlanCounters], bool lanes) {
     const aes_msg_desc d = a.desc[m];
     if (d.mode != AES_MODE_GCM)
         return;
+    const uint64_t npos = ghash_positions(d, a.gcm[m]);
+    const uint64_t short_before = lanes ? before[8] + c[8] : 0;
     BatchItem it;
     it.msg = m;
-    it.count = uint32_t((ghash_positions(d, a.gcm[m]) + kGhashPiece - 1) / kGhashPiece);
-    it.start = before[7] + c[7];
-    a.items[size_t(3) * a.max_msgs + before[6] + c[6]] = it;
+    if (lanes && npos <= kLaneGhashMaxPositions) {
+        it.count = 1;
+        it.start = 0;
+        a.items[size_t(3) * a.max_msgs + (size_t(a.max_msgs) - 1 - short_before)] = it;
+        return;
+    }
+    it.count = uint32_t((npos + kGhashPiece - 1) / kGhashPiece);
+    it.start = before[7] + c[7] - short_before;   // a short message is one piece
+    a.items[size_t(3) * a.max_msgs + (before[6] + c[6] - short_before)] = it;
 }
 
 // The first launch of a batch, one message per thread, kPlanThreads messages
@@ -434,8 +465,7 @@ __global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArg
         h->cost[0] = total[3];
         h->cost[1] = total[4];
         h->rejected = uint32_t(total[5]);
-        h->ngcm = uint32_t(total[6]);
-        h->gcm_pieces = total[7];
+        gcm_header(h, total);
     }
     if (!valid)
         return;
@@ -445,8 +475,8 @@ __global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArg
     it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;
     it.start = k == 0 ? c[3] : k == 1 ? c[4] : 0;
     a.items[size_t(k) * a.max_msgs + (k == 0 ? c[0] : k == 1 ? c[1] : c[2])] = it;
-    const uint64_t zero[kPlanCounters] = {0, 0, 0, 0, 0, 0, 0, 0};
-    gcm_item(a, m, zero, c);
+    const uint64_t zero[kPlanCounters] = {};
+    gcm_item(a, m, zero, c, lane_ghash(total));
     uint32_t *slot = a.keytab + size_t(m) * kKeySlotWords;
     if (d.keybits_code == 0)
         expand_message_keys<4>(a, d, slot, tab);
@@ -495,7 +525,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
         it.start = k == 0 ? base[3] + c[3] : k == 1 ? base[4] + c[4] : 0;
         const uint64_t i = k == 0 ? base[0] + c[0] : k == 1 ? base[1] + c[1] : base[2] + c[2];
         a.items[size_t(k) * a.max_msgs + i] = it;
-        gcm_item(a, m, base, c);
+        gcm_item(a, m, base, c, lane_ghash(sum_all));
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         BatchHeader *h = a.header;
@@ -506,8 +536,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
         h->cost[0] = sum_all[3];
         h->cost[1] = sum_all[4];
         h->rejected = uint32_t(sum_all[5]);
-        h->ngcm = uint32_t(sum_all[6]);
-        h->gcm_pieces = sum_all[7];
+        gcm_header(h, sum_all);
     }
 }
 
@@ -596,7 +625,10 @@ __device__ __forceinline__ void serial_message(const uint32_t *lds, const LaneCo
         rk[r] = rkp[4 * r + j];
     const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + d.in_off;
     uint8_t *out = static_cast<uint8_t *>(a.out_base) + d.out_off;
-    cbc_encrypt_quad<NR, LAYOUT_T4X32>(lds, lc, rk, le32(d.ctr0 + 4 * j), in, out, item.count);
+    // word j of the IV, read from the descriptor in memory (indexing the
+    // local copy by the lane's column would put that copy in scratch)
+    const uint32_t iv = le32(a.desc[item.msg].ctr0 + 4 * j);
+    cbc_encrypt_quad<NR, LAYOUT_T4X32>(lds, lc, rk, iv, in, out, item.count);
 }
 
 __device__ __forceinline__ void run_serial(const uint32_t *lds, const BatchKArgs &a, uint32_t n, uint32_t wave,
@@ -920,6 +952,240 @@ __global__ __launch_bounds__(kBatchWavesPerGroup * 64) void ghash_kernel(const B
     }
 }
 
+// ---- GHASH of short messages, four lanes per message -----------------------
+// For batches of many short GCM messages (lane_ghash) the four lanes of a
+// quad hash one message whole, in four interleaved Horner chains: lane p of
+// the quad takes the positions r = 4s + p, Z_p <- Z_p G ^ X_(4s+p) for s from
+// the top down, with G = H^4, so that Z_p = sum_s X_(4s+p) G^s; the sum over
+// all r of X_r H^(r+1) is then H (Z_0 ^ H (Z_1 ^ H (Z_2 ^ H Z_3))), which every
+// lane of the quad forms from the four Z_p (the first one writes it).
+// Products go through 4-bit tables of the lane's own copy of the multiplier M
+// in arithmetic form (gf128.h): T[v] = v M for the 16 nibble values v, 256
+// bytes per lane, 16 KiB per wave, so that ten waves fit on a compute unit
+// and cover each other's latencies.  Entry v of lane l sits at byte
+// v * 1024 + l * 16, so the 16-byte reads of any 16 neighbouring lanes fall
+// on 16 different bank groups, whatever entries they read.  A product Y M is
+// the sum over the 32 nibbles of Y, nibble 8q + c (bits 4c .. 4c+3 of word
+// q), of T[nibble] x^(32q + 4c): the word shift is where the entry is added
+// (an accumulator per nibble position c, seven words long), the shifts by 4c
+// are applied once per product, and the 256-bit sum is reduced modulo
+// x^128 + x^7 + x^2 + x + 1.
+constexpr uint32_t kLaneEntryStride = 64u * 16u;             // one entry of every lane
+constexpr uint32_t kLaneTabBytes = 16u * kLaneEntryStride;   // 16 KiB per wave
+constexpr uint32_t kLaneMsgsPerWave = 16;                    // a quad of lanes each
+
+// The lane's table of the multiplier (lo, hi), at byte offset `base` =
+// 16 * lane.
+__device__ __forceinline__ void lane_build(uint32_t *lds, uint32_t base, uint64_t lo, uint64_t hi) {
+    uint32_t p[4][4];   // M x^t for t < 4
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        p[t][0] = uint32_t(lo);
+        p[t][1] = uint32_t(lo >> 32);
+        p[t][2] = uint32_t(hi);
+        p[t][3] = uint32_t(hi >> 32);
+        mulx_small(lo, hi, 1);
+    }
+#pragma unroll
+    for (uint32_t v = 0; v < 16; v++) {
+        uint32_t e[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if ((v >> t) & 1u) {
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    e[c] ^= p[t][c];
+            }
+        }
+        lds_store16(lds, base + v * kLaneEntryStride, vec4(e[0], e[1], e[2], e[3]));
+    }
+}
+
+// Byte offset of the entry for the nibble at bits s .. s+3 of y (s is a
+// constant once the callers' loops are unrolled).
+__device__ __forceinline__ uint32_t lane_entry(uint32_t y, int s, uint32_t base) {
+    constexpr int kPos = 10;   // log2(kLaneEntryStride)
+    const uint32_t shifted = s <= kPos ? y << (kPos - s) : y >> (s - kPos);
+    return (shifted & (15u << kPos)) | base;
+}
+
+// z = y M through the lane's table (both in arithmetic form).
+__device__ __forceinline__ void lane_mul(const uint32_t *lds, uint32_t base, const uint32_t (&y)[4],
+                                         uint32_t (&z)[4]) {
+    // acc[c][w]: word w of sum_q entry(nibble 8q + c) x^(32q), from the
+    // words w - q of the entries
+    uint32_t acc[8][7];
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        u32x4 e[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            e[q] = lds_load16(lds, lane_entry(y[q], 4 * c, base));
+        acc[c][0] = e[0].x;
+        acc[c][1] = e[0].y ^ e[1].x;
+        acc[c][2] = xor3(e[0].z, e[1].y, e[2].x);
+        acc[c][3] = xor3(e[0].w, e[1].z, e[2].y) ^ e[3].x;
+        acc[c][4] = xor3(e[1].w, e[2].z, e[3].y);
+        acc[c][5] = e[2].w ^ e[3].z;
+        acc[c][6] = e[3].w;
+    }
+    // s = sum_c acc[c] x^(4c), 256 bits: per word the eight shifted terms
+    uint32_t s[8];
+#pragma unroll
+    for (int w = 0; w < 8; w++) {
+        uint32_t t[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            const uint32_t hiw = w < 7 ? acc[c][w] : 0u, low = w > 0 ? acc[c][w - 1] : 0u;
+            t[c] = c == 0 ? hiw : __builtin_amdgcn_alignbit(hiw, low, uint32_t(32 - 4 * c));   // (hiw:low) >> (32 - 4c)
+        }
+        s[w] = xor3(xor3(xor3(t[0], t[1], t[2]), t[3], t[4]), t[5], t[6]) ^ t[7];
+    }
+    // s mod P: the upper half U folds back as U (1 + x + x^2 + x^7); the at
+    // most 7 bits that leaves above x^127 (o) fold back once more
+    const uint32_t u[4] = {s[4], s[5], s[6], s[7]};
+    uint32_t s1[4], s2[4], s7[4];
+    s1[0] = u[0] << 1;
+    s2[0] = u[0] << 2;
+    s7[0] = u[0] << 7;
+#pragma unroll
+    for (int j = 1; j < 4; j++) {
+        s1[j] = __builtin_amdgcn_alignbit(u[j], u[j - 1], 31u);
+        s2[j] = __builtin_amdgcn_alignbit(u[j], u[j - 1], 30u);
+        s7[j] = __builtin_amdgcn_alignbit(u[j], u[j - 1], 25u);
+    }
+    const uint32_t o = xor3(u[3] >> 31, u[3] >> 30, u[3] >> 25);
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        z[j] = xor3(xor3(s[j], u[j], s1[j]), s2[j], s7[j]);
+    z[0] ^= xor3(o, o << 1, o << 2) ^ (o << 7);
+}
+
+// One wave per workgroup, kLaneMsgsPerWave messages per wave: workgroup g
+// takes messages 16g .. 16g + 15 from the back of the GHASH list, a quad of
+// lanes each.
+__global__ __launch_bounds__(64) void ghash_lane_kernel(const BatchKArgs a) {
+    const uint32_t n = a.header->nlane;
+    const uint32_t first = blockIdx.x * kLaneMsgsPerWave;
+    if (first >= n)
+        return;
+    __shared__ uint32_t lds[kLaneTabBytes / 4];
+    const uint32_t lane = threadIdx.x, chain = lane & 3u;
+    const uint32_t base = lane * 16u;
+    const BatchItem *list = a.items + size_t(3) * a.max_msgs;
+    const uint32_t i = first + (lane >> 2);
+    const bool on = i < n;
+    uint32_t msg = 0;
+    uint64_t nC = 0, nA = 0, cbytes = 0, abytes = 0;
+    const uint8_t *ct = nullptr, *aad = nullptr;
+    uint32_t h[4] = {0, 0, 0, 0};
+    if (on) {
+        msg = list[size_t(a.max_msgs) - 1 - i].msg;
+        const aes_msg_desc d = a.desc[msg];
+        const aes_gcm_desc gd = a.gcm[msg];
+        cbytes = d.nbytes;
+        abytes = gd.aad_bytes;
+        nC = (cbytes + 15) >> 4;
+        nA = (abytes + 15) >> 4;
+        ct = d.decrypt ? static_cast<const uint8_t *>(a.in_base) + d.in_off
+                       : static_cast<const uint8_t *>(a.out_base) + d.out_off;
+        aad = static_cast<const uint8_t *>(a.in_base) + gd.aad_off;
+        const uint32_t *slot = a.keytab + size_t(msg) * kKeySlotWords;
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            h[c] = slot[kGcmSlotH + c];
+    }
+    uint64_t hlo, hhi;
+    to_poly(h, hlo, hhi);
+    uint64_t glo = hlo, ghi = hhi;   // G = H^4
+    gf_square(glo, ghi);
+    gf_square(glo, ghi);
+    lane_build(lds, base, glo, ghi);
+    // a wave's LDS accesses complete in order; the fences only keep the
+    // compiler from moving the table reads above the writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // steps of the longest message of the wave; a shorter one keeps Z_p = 0
+    // (and X = 0) until its own top position
+    const uint32_t npos = on ? uint32_t(nC + nA + 1) : 0u;
+    uint32_t top = npos;
+#pragma unroll
+    for (int off = 32; off >= 4; off >>= 1)
+        top = max(top, uint32_t(__shfl_xor(int(top), off, 64)));
+    const uint32_t steps = uniform32((top + 3) / 4);
+    // X_r of this lane's message, zero from its top position on.  The partial
+    // last blocks of the ciphertext (position 1) and of the additional data
+    // (position nC + 1) are read here, zero-padded; in the loop every lane
+    // loads 16 bytes from an address that is always valid (a whole block of
+    // its message, else its own key slot) and picks the value one step
+    // later, so no load waits where it is issued.  Plain (cached) loads: the
+    // four lanes of a quad read 64 neighbouring bytes.
+    const uint64_t nCw = cbytes >> 4, nAw = abytes >> 4;
+    const u32x4 ctail = (cbytes & 15u) ? load_tail(ct + 16 * nCw, uint32_t(cbytes & 15u)) : vec4(0, 0, 0, 0);
+    const u32x4 atail = (abytes & 15u) ? load_tail(aad + 16 * nAw, uint32_t(abytes & 15u)) : vec4(0, 0, 0, 0);
+    const u32x4 lenblk = ghash_block(0, nC, nA, ct, cbytes, aad, abytes);
+    const uint8_t *dummy = reinterpret_cast<const uint8_t *>(a.keytab + size_t(msg) * kKeySlotWords);
+    auto load_at = [&](uint32_t r) -> u32x4 {
+        const uint64_t j = nC - r, k = nC + nA - r;
+        const uint8_t *p = (r >= 1 && r <= nC && j < nCw) ? ct + 16 * j
+                         : (r > nC && r < npos && k < nAw) ? aad + 16 * k : dummy;
+        return *reinterpret_cast<const u32x4 *>(p);
+    };
+    auto pick = [&](uint32_t r, u32x4 v) -> u32x4 {
+        if (r >= npos)
+            return vec4(0, 0, 0, 0);
+        if (r == 0)
+            return lenblk;
+        if (r == 1 && (cbytes & 15u))
+            return ctail;
+        if (r == nC + 1 && (abytes & 15u))
+            return atail;
+        return v;
+    };
+    uint32_t z[4] = {0, 0, 0, 0};
+    u32x4 v = load_at(steps ? 4 * (steps - 1) + chain : 0);
+    for (uint32_t st = steps; st-- > 0;) {
+        const u32x4 vn = load_at(st ? 4 * (st - 1) + chain : 0);   // one step ahead
+        uint32_t t[4];
+        lane_mul(lds, base, z, t);
+        const u32x4 x = pick(4 * st + chain, v);
+        z[0] = t[0] ^ rev_bits_in_bytes(x.x);
+        z[1] = t[1] ^ rev_bits_in_bytes(x.y);
+        z[2] = t[2] ^ rev_bits_in_bytes(x.z);
+        z[3] = t[3] ^ rev_bits_in_bytes(x.w);
+        v = vn;
+    }
+    // H (Z_0 ^ H (Z_1 ^ H (Z_2 ^ H Z_3))) with the table of H, in every lane
+    // of the quad
+    uint32_t zq[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            zq[p][c] = uint32_t(__shfl(int(z[c]), int((lane & ~3u) | uint32_t(p)), 64));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    lane_build(lds, base, hlo, hhi);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t w[4] = {zq[3][0], zq[3][1], zq[3][2], zq[3][3]};
+#pragma unroll
+    for (int p = 2; p >= -1; p--) {
+        uint32_t t[4];
+        lane_mul(lds, base, w, t);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            w[c] = p >= 0 ? t[c] ^ zq[p][c] : t[c];
+    }
+    if (on && chain == 0) {
+        uint32_t *slot = a.keytab + size_t(msg) * kKeySlotWords;
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            slot[kGcmSlotSum + c] = rev_bits_in_bytes(w[c]);
+    }
+}
+
 // One lane per message: every GCM message's tag, Cipher_K(J0) XOR its GHASH
 // sum, written after its output (encryption) or compared with the expected
 // one (decryption); the verdict goes to the message's aes_gcm_desc.
@@ -1076,6 +1342,14 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
+        if (uint64_t(max_count) >= kLaneGhashMinMessages) {
+            // one wave per workgroup, kLaneMsgsPerWave messages per wave
+            const int64_t lane_groups = (int64_t(max_count) + kLaneMsgsPerWave - 1) / kLaneMsgsPerWave;
+            hipLaunchKernelGGL(ghash_lane_kernel, dim3(unsigned(lane_groups)), dim3(64), 0, stream, a);
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
         const int groups = (std::max(max_count, 1) + 255) / 256;
         hipLaunchKernelGGL(gcm_tag_kernel, dim3(groups), dim3(256), 0, stream, a);
         e = hipGetLastError();

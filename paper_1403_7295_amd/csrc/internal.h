@@ -136,16 +136,19 @@ struct BatchHeader {
     uint64_t next[3];     // forward and inverse lists: next share handed out from the
                           // counter; serial list: next message
     uint64_t cost[2];     // work of the forward and inverse lists, in cost units
-    uint32_t ngcm;        // GCM messages (the GHASH list)
+    uint32_t ngcm;        // GCM messages hashed in pieces (the GHASH list)
     uint32_t pad0;
     uint64_t gcm_pieces;  // GHASH pieces of all of them
-    uint32_t pad[46];
+    uint32_t nlane;       // GCM messages hashed one per lane (the back of the GHASH list)
+    uint32_t pad[45];
 };
 static_assert(sizeof(BatchHeader) == 256, "header is one 256-byte line");
 
 // One message in a list.  Forward and inverse lists: start = the cost units of
 // the messages before it in the list.  Serial list: count = its blocks.
-// GHASH list: start = the pieces of the messages before it, count = its own.
+// GHASH list: start = the pieces of the messages before it, count = its own;
+// the messages hashed one per lane fill the same array from its end (entry
+// max_msgs - 1 - i is the i-th of them).
 struct BatchItem {
     uint32_t msg;     // message index
     uint32_t count;
@@ -163,6 +166,11 @@ static_assert(kGcmSlotPow + 4 * kGcmSlotPowers <= kKeySlotWords, "GCM powers fit
 // length block) per piece: one wave hashes one piece
 constexpr int kGhashPieceLog2 = 12;
 constexpr uint64_t kGhashPiece = uint64_t(1) << kGhashPieceLog2;
+// A batch with at least kLaneGhashMinMessages GCM messages of at most
+// kLaneGhashMaxPositions positions hashes each of those in one lane (whole
+// Horner recurrence, per-lane tables) instead of a wave per piece.
+constexpr uint64_t kLaneGhashMaxPositions = 512;
+constexpr uint64_t kLaneGhashMinMessages = 32768;
 // A wave's share of a message starts and ends on a multiple of this many
 // blocks by default (four steps of the block loop, 64 lanes x 2 blocks; the
 // best of 128 .. 1024 over batch sizes from one message to gigabytes).  The
@@ -175,7 +183,7 @@ constexpr int kBatchWavesPerGroup = 16;
 // Messages per chunk of the plan (one workgroup of the prep and plan
 // kernels), and the plan's counters per chunk.
 constexpr int kBatchChunk = 256;
-constexpr int kBatchChunkCounters = 8;
+constexpr int kBatchChunkCounters = 9;
 constexpr int kBatchLists = 4;   // forward, inverse, serial, GHASH
 
 struct BatchKArgs {

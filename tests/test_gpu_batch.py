@@ -574,3 +574,107 @@ def test_gcm_batch_message_beyond_the_stored_powers(A):
     assert torch.equal(y[aad_off:aad_off + 16], tag)
     del x, y, ref_out
     torch.cuda.empty_cache()
+
+
+def _batch_header_nlane(b):
+    """GCM messages the last run of batch b hashed one per lane (the
+    workspace header's count: byte 72 of the 256-byte header at the
+    workspace's 256-byte aligned start)."""
+    off = (b.workspace.data_ptr() + 255) // 256 * 256 - b.workspace.data_ptr()
+    hdr = b.workspace[off:off + 256].cpu().numpy()
+    return int(hdr[72:76].view(np.uint32)[0])
+
+
+def test_gcm_batch_many_short_messages_one_per_lane(A, O):
+    """34,000 short GCM messages (0 .. 4 KiB, additional data 0 .. 1 KiB,
+    AES-128/256): enough that the batch hashes them one per lane.  A sample
+    and the size boundary (512 GHASH positions: per lane; 513: in pieces)
+    against the oracle; every ciphertext and tag against the same messages
+    run as two batches of 17,000, which hash in pieces; then every message
+    decrypted with its tag, a quarter of the tags changed, which must be
+    refused."""
+    n = 34000
+    rng = np.random.default_rng(81)
+    lens = seedgen.log_uniform_lengths(rng, n, 1, 4096)
+    lens[:3] = [0, 1, 16]
+    aadl = rng.integers(0, 1025, n)
+    aadl[:3] = [0, 0, 1]
+    # GHASH positions = ceil(aad/16) + ceil(len/16) + 1: 512 and 513
+    lens[3], aadl[3] = 4096, 255 * 16          # 255 + 256 + 1 = 512
+    lens[4], aadl[4] = 4095, 255 * 16 + 1      # 256 + 256 + 1 = 513
+    keybits = rng.choice([128, 256], n)
+    pad = (lens + 15) // 16 * 16
+    msg_off = np.concatenate([[0], np.cumsum(pad)[:-1]])
+    aad_base = int(pad.sum())
+    apad = (aadl + 15) // 16 * 16
+    aad_off = aad_base + np.concatenate([[0], np.cumsum(apad)[:-1]])
+    tag_base = aad_base + int(apad.sum())
+    tag_off = tag_base + 16 * np.arange(n)
+    total = tag_base + 16 * n + 16
+    x = rng.integers(0, 256, total, dtype=np.uint8)
+    keys = np.zeros((n, 32), np.uint8)
+    keys[:, :32] = rng.integers(0, 256, (n, 32), dtype=np.uint8)
+    keys[keybits == 128, 16:] = 0
+    ctr0 = np.zeros((n, 16), np.uint8)
+    ctr0[:, :12] = rng.integers(0, 256, (n, 12), dtype=np.uint8)
+    g = np.zeros(n, A.GCM_DESC_DTYPE)
+    g["aad_off"], g["aad_bytes"], g["tag_off"], g["tag_bytes"] = aad_off, aadl, tag_off, 16
+    enc = A.make_descs(lens, in_off=msg_off, keybits=keybits, mode="gcm", ctr0=ctr0)
+
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.zeros_like(xd)
+    b = A.Batch(enc, keys, xd, yd, gcm=g)
+    b.run()
+    assert b.query() == (n, 0)
+    assert _batch_header_nlane(b) == n - 1           # all but the 513-position message
+    r = b.gcm_results(n)
+    assert (r["ok"] == 1).all()
+    y = yd.cpu().numpy()
+    b.close()
+
+    # the oracle on a sample and on the boundary messages
+    for m in sorted(set(rng.choice(n, 300, replace=False).tolist()) | {0, 1, 2, 3, 4}):
+        bits = int(keybits[m])
+        rk, nr = O.expand_key(keys[m, :bits // 8])
+        pt = x[msg_off[m]:msg_off[m] + lens[m]]
+        aad = x[aad_off[m]:aad_off[m] + aadl[m]]
+        ct, tag = O.gcm_encrypt(rk, nr, ctr0[m, :12], aad, pt)
+        assert np.array_equal(y[msg_off[m]:msg_off[m] + lens[m]], ct), ("ciphertext", m)
+        assert np.array_equal(y[tag_off[m]:tag_off[m] + 16], tag), ("tag", m)
+
+    # the same messages as two batches below the per-lane threshold: GHASH in pieces
+    y2 = torch.zeros_like(xd)
+    half = n // 2
+    for lo, hi in ((0, half), (half, n)):
+        bh = A.Batch(enc[lo:hi], keys, xd, y2, gcm=g[lo:hi])
+        bh.run()
+        assert bh.query() == (hi - lo, 0)
+        assert _batch_header_nlane(bh) == 0
+        bh.close()
+    assert np.array_equal(y2.cpu().numpy()[:tag_base + 16 * n], y[:tag_base + 16 * n])
+
+    # decryption of every message with its tag; a quarter of the tags changed
+    xin = y.copy()
+    xin[aad_base:tag_base] = x[aad_base:tag_base]     # the additional data
+    forged = np.arange(n) % 4 == 1
+    xin[tag_off[forged] + (np.arange(n)[forged] % 16)] ^= 0x20
+    dec = enc.copy()
+    dec["decrypt"] = 1
+    xd2 = torch.from_numpy(xin).to("cuda")
+    zd = torch.zeros_like(xd2)
+    g["ok"] = -7
+    bd = A.Batch(dec, keys, xd2, zd, gcm=g)
+    bd.run()
+    assert bd.query() == (n, 0)
+    assert _batch_header_nlane(bd) == n - 1
+    rd = bd.gcm_results(n)
+    assert np.array_equal(rd["ok"], np.where(forged, 0, 1).astype(rd["ok"].dtype))
+    # every plaintext recovered (the output holds it whatever the verdict);
+    # the padding between messages untouched
+    z = zd.cpu().numpy()[:aad_base]
+    inside = np.repeat(np.tile([True, False], n), np.column_stack([lens, pad - lens]).ravel())
+    assert np.array_equal(z[inside], x[:aad_base][inside])
+    assert not z[~inside].any()
+    bd.close()
+    del xd, yd, y2, xd2, zd
+    torch.cuda.empty_cache()
