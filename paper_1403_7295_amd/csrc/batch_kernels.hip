@@ -245,6 +245,12 @@ __device__ __forceinline__ void expand_message_keys(const BatchKArgs &a, const a
         uint32_t w2[4 * (NR + 1)];
         expand_key<NK>(a.keys + size_t(xts_key2(d)) * 32, tab, [&](int i, uint32_t v) { w2[i] = v; });
         store_schedule<NK>(slot + (d.decrypt ? 0 : kKeySlotWords / 2), w2);
+        // the encrypted tweak of the message's first unit, so that a
+        // one-unit message's wave need not run it on one lane
+        const uint64_t u = xts_first_unit(d);
+        uint32_t t[4] = {uint32_t(u), uint32_t(u >> 32), 0u, 0u};
+        encrypt_one<NR>(tab, w2, t);
+        reinterpret_cast<u32x4 *>(slot)[kXtsSlotTweak / 4] = vec4(t[0], t[1], t[2], t[3]);
     }
     if (d.mode == AES_MODE_GCM) {
         // H = Cipher_K(0^128); J0 = IV || 0^31 || 1 (a 96-bit IV) and
@@ -603,7 +609,7 @@ __device__ __forceinline__ void run_xts_range(const uint32_t *lds, const LaneCon
     const uint64_t first_unit = xts_first_unit(d);
     for (uint64_t gb0 = first; gb0 < end; gb0 += group)
         xts_group<NR, DIR, BPT>(lds, lc, rk, rk2, in, out, gb0, min(end, gb0 + group),
-                                first_unit + (gb0 >> ushift), ushift);
+                                first_unit + (gb0 >> ushift), ushift, slot + kXtsSlotTweak, first_unit);
 }
 
 // The serial list (CBC encryption): one message per quad of four lanes,

@@ -160,6 +160,9 @@ struct BatchItem {
 // a GCM message keeps H = Cipher_K(0), Cipher_K(J0), its GHASH sum and the
 // powers H^(kGhashPiece * 2^t), t < kGcmSlotPowers, there
 constexpr int kKeySlotWords = 128;
+// an XTS message keeps the encrypted tweak of its first data unit in the four
+// words after the schedule in the first half (a schedule has at most 60)
+constexpr int kXtsSlotTweak = 60;
 constexpr int kGcmSlotH = 64, kGcmSlotEJ0 = 68, kGcmSlotSum = 72, kGcmSlotPow = 76, kGcmSlotPowers = 13;
 static_assert(kGcmSlotPow + 4 * kGcmSlotPowers <= kKeySlotWords, "GCM powers fit the key slot");
 // GHASH positions (16-byte blocks of additional data, ciphertext and the

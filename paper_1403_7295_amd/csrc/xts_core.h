@@ -29,10 +29,13 @@ namespace {
 // unit, the range covers at most 64 units of 2^ushift blocks); unit0 is the
 // tweak value of the unit starting at gb0.  rk1: the data key in the order
 // the rounds use it (wave-uniform); rk2: the tweak key's encryption schedule.
+// known, if not NULL, holds the encrypted tweak of unit known_unit, which
+// the lane owning that unit loads instead of computing it.
 template <int NR, int DIR, int BPT>
 __device__ __forceinline__ void xts_group(const uint32_t *lds, const LaneConsts &lc, const uint32_t *rk1,
                                           const uint32_t *rk2, const uint8_t *in, uint8_t *out, uint64_t gb0,
-                                          uint64_t gb1, uint64_t unit0, uint32_t ushift) {
+                                          uint64_t gb1, uint64_t unit0, uint32_t ushift,
+                                          const uint32_t *known = nullptr, uint64_t known_unit = 0) {
     const uint32_t lane = threadIdx.x & 63u;
     // the tweak of unit unit0 + lane: Cipher_K2 of the unit number, little-endian;
     // only lanes that own one of the group's units compute it (a batch of
@@ -41,7 +44,11 @@ __device__ __forceinline__ void xts_group(const uint32_t *lds, const LaneConsts 
     const uint64_t unit = unit0 + lane;
     const uint32_t units = uint32_t((gb1 - gb0 + (uint64_t(1) << ushift) - 1) >> ushift);
     uint32_t tw[4] = {uint32_t(unit), uint32_t(unit >> 32), 0u, 0u};
-    if (lane < units) {
+    if (known && lane < units && unit == known_unit) {
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            tw[c] = known[c];
+    } else if (lane < units) {
         if (DIR == DIR_ENC) {
             uint32_t t1[1][4] = {{tw[0] ^ rk2[0], tw[1] ^ rk2[1], rk2[2], rk2[3]}};
             rounds<NR, DIR_ENC, LAYOUT_T4X32, 1>(t1, lds, lc, rk2, 1);

@@ -630,6 +630,13 @@ def test_gcm_batch_many_short_messages_one_per_lane(A, O):
     r = b.gcm_results(n)
     assert (r["ok"] == 1).all()
     y = yd.cpu().numpy()
+    # replays of the captured graph give the same bytes (the plan, the lists
+    # and the sums start over at every launch)
+    for _ in range(2):
+        yd.zero_()
+        b.launch_graph()
+        torch.cuda.synchronize()
+        assert np.array_equal(yd.cpu().numpy(), y)
     b.close()
 
     # the oracle on a sample and on the boundary messages
