@@ -825,9 +825,11 @@ __global__ __launch_bounds__(kBatchWavesPerGroup * 64) void batch_kernel(const B
 }
 
 // ---- GCM: GHASH pieces and tags ----------------------------------------------
-// LDS of the GHASH kernel: per wave, one multiplier's table and the scratch
-// for building it (16 waves x 10 KiB = the whole 160 KiB).
-constexpr uint32_t kGhashWaveBytes = kTabBytes + kVecBytes;
+// LDS of the GHASH kernel: per wave, one multiplier's table (16 waves x
+// 8 KiB = 128 KiB per workgroup, one workgroup per compute unit like the
+// cipher kernels: 4,096 waves, which the usual piece counts divide evenly).
+constexpr uint32_t kGhashWaveBytes = kTabBytes;
+constexpr int kGhashWavesPerGroup = kBatchWavesPerGroup;
 
 __device__ __forceinline__ u32x4 load16_masked(const uint8_t *p, bool whole, uint32_t tail) {
     return whole ? load16(p) : load_tail(p, tail);
@@ -861,7 +863,7 @@ __device__ __forceinline__ u32x4 ghash_block(uint64_t r, uint64_t nC, uint64_t n
 // multiplied by H and by H^(p_lo) = product of the stored powers
 // H^(kGhashPiece 2^t) over the set bits t of the piece index (products by
 // the whole wave).
-__device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, uint32_t vec, const BatchKArgs &a,
+__device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, const BatchKArgs &a,
                                             uint32_t msg, uint64_t piece) {
     const uint32_t lane = threadIdx.x & 63u;
     const aes_msg_desc d = a.desc[msg];
@@ -883,26 +885,62 @@ __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, uint32_
         gf_square(glo, ghi);
     uint32_t gw[4];
     from_poly(glo, ghi, gw);
-    build_table_wave(lds, tab, vec, gw);
-    uint32_t w[4] = {0, 0, 0, 0};
-    for (uint64_t q = (p_hi - p_lo + 63) >> 6; q-- > 0;) {
+    build_table_wave(lds, tab, gw);
+    // X_r for the Horner steps, kPrefetch steps ahead: every lane loads 16
+    // bytes from an address that is always valid (a whole block of the
+    // message, else its key slot) and picks the value when the step comes,
+    // so the loads' latency is not waited out step by step; the length block
+    // and the partial last blocks are formed once
+    const uint64_t cbytes = d.nbytes, abytes = g.aad_bytes, nCw = cbytes >> 4, nAw = abytes >> 4;
+    const bool has_ctail = (cbytes & 15u) != 0, has_atail = (abytes & 15u) != 0;
+    const u32x4 ctail = has_ctail ? load_tail(ct + 16 * nCw, uint32_t(cbytes & 15u)) : vec4(0, 0, 0, 0);
+    const u32x4 atail = has_atail ? load_tail(aad + 16 * nAw, uint32_t(abytes & 15u)) : vec4(0, 0, 0, 0);
+    const u32x4 lenblk = ghash_block(0, nC, nA, ct, cbytes, aad, abytes);
+    const uint8_t *dummy = reinterpret_cast<const uint8_t *>(slot);
+    auto load_at = [&](uint64_t q) -> u32x4 {
+        const uint64_t r = p_lo + 64 * q + lane, j = nC - r, k = nC + nA - r;
+        const uint8_t *p = (r >= 1 && r <= nC && j < nCw) ? ct + 16 * j
+                         : (r > nC && r < p_hi && k < nAw) ? aad + 16 * k : dummy;
+        return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    };
+    auto pick = [&](uint64_t q, u32x4 v) -> u32x4 {
         const uint64_t r = p_lo + 64 * q + lane;
-        u32x4 x = vec4(0, 0, 0, 0);
-        if (r < p_hi)
-            x = ghash_block(r, nC, nA, ct, d.nbytes, aad, g.aad_bytes);
+        const bool is_len = r == 0, is_ct = r == 1 && has_ctail, is_at = r == nC + 1 && has_atail;
+        const bool out = r >= p_hi;
+        auto sel = [&](uint32_t vw, uint32_t lw, uint32_t cw, uint32_t aw) {
+            const uint32_t x = is_len ? lw : is_ct ? cw : is_at ? aw : vw;
+            return out ? 0u : x;
+        };
+        return vec4(sel(v.x, lenblk.x, ctail.x, atail.x), sel(v.y, lenblk.y, ctail.y, atail.y),
+                    sel(v.z, lenblk.z, ctail.z, atail.z), sel(v.w, lenblk.w, ctail.w, atail.w));
+    };
+    constexpr int kPrefetch = 2;
+    const uint64_t steps = (p_hi - p_lo + 63) >> 6;
+    u32x4 v[kPrefetch];
+#pragma unroll
+    for (int i = 0; i < kPrefetch; i++)
+        v[i] = steps > uint64_t(i) ? load_at(steps - 1 - i) : vec4(0, 0, 0, 0);
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (uint64_t q = steps; q-- > 0;) {
+        const u32x4 vn = q >= uint64_t(kPrefetch) ? load_at(q - kPrefetch) : vec4(0, 0, 0, 0);
         uint32_t t[4];
         mul_tab(lds, tab, w, t);
+        const u32x4 x = pick(q, v[0]);
         w[0] = t[0] ^ x.x;
         w[1] = t[1] ^ x.y;
         w[2] = t[2] ^ x.z;
         w[3] = t[3] ^ x.w;
+#pragma unroll
+        for (int i = 0; i + 1 < kPrefetch; i++)
+            v[i] = v[i + 1];
+        v[kPrefetch - 1] = vn;
     }
     // sum_l w_l H^l over the lanes
     uint64_t plo = hlo, phi = hhi;
     for (int k = 0; k < 6; k++) {
         uint32_t pw[4];
         from_poly(plo, phi, pw);
-        build_table_wave(lds, tab, vec, pw);
+        build_table_wave(lds, tab, pw);
         uint32_t v[4];
 #pragma unroll
         for (int c = 0; c < 4; c++)
@@ -932,29 +970,31 @@ __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, uint32_
     uint32_t res[4];
     from_poly(rlo, rhi, res);
     if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < 4; c++)
-            atomicXor(slot + kGcmSlotSum + c, res[c]);
+        // two 64-bit atomics (the sum sits at an 8-byte aligned offset of the
+        // 512-byte slot): the pieces of one message all XOR into the same line
+        unsigned long long *sum = reinterpret_cast<unsigned long long *>(slot + kGcmSlotSum);
+        atomicXor(sum, (unsigned long long)res[0] | ((unsigned long long)res[1] << 32));
+        atomicXor(sum + 1, (unsigned long long)res[2] | ((unsigned long long)res[3] << 32));
     }
 }
 
 // Persistent: wave w of NW takes pieces w, w + NW, w + 2 NW, ... of the
 // GHASH list (every GCM message's pieces, in message order).
-__global__ __launch_bounds__(kBatchWavesPerGroup * 64) void ghash_kernel(const BatchKArgs a) {
+__global__ __launch_bounds__(kGhashWavesPerGroup * 64) void ghash_kernel(const BatchKArgs a) {
     const uint32_t n = a.header->ngcm;
     const uint64_t npieces = a.header->gcm_pieces;
     if (n == 0)
         return;
-    __shared__ uint32_t lds[kBatchWavesPerGroup * kGhashWaveBytes / 4];
+    __shared__ uint32_t lds[kGhashWavesPerGroup * kGhashWaveBytes / 4];
     const uint32_t wv = uniform32(threadIdx.x >> 6);
-    const uint32_t tab = wv * kGhashWaveBytes, vec = tab + kTabBytes;
-    const uint64_t wave = uint64_t(blockIdx.x) * kBatchWavesPerGroup + wv;
-    const uint64_t nwaves = uint64_t(gridDim.x) * kBatchWavesPerGroup;
+    const uint32_t tab = wv * kGhashWaveBytes;
+    const uint64_t wave = uint64_t(blockIdx.x) * kGhashWavesPerGroup + wv;
+    const uint64_t nwaves = uint64_t(gridDim.x) * kGhashWavesPerGroup;
     const BatchItem *list = a.items + size_t(3) * a.max_msgs;
     for (uint64_t p = wave; p < npieces; p += nwaves) {
         const uint32_t i = uniform32(find_item(list, n, p));
         const uint32_t msg = uniform32(list[i].msg);
-        ghash_piece(lds, tab, vec, a, msg, p - uniform64(list[i].start));
+        ghash_piece(lds, tab, a, msg, p - uniform64(list[i].start));
     }
 }
 
@@ -1344,7 +1384,7 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
     }
     // GCM: the hash reads the ciphertext the forward kernel has written
     if (lists & 8u) {
-        hipLaunchKernelGGL(ghash_kernel, dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+        hipLaunchKernelGGL(ghash_kernel, dim3(grid), dim3(kGhashWavesPerGroup * 64), 0, stream, a);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -31,11 +31,13 @@ __device__ __forceinline__ void lds_store16(uint32_t *lds, uint32_t off, u32x4 v
     *reinterpret_cast<u32x4 *>(reinterpret_cast<char *>(lds) + off) = v;
 }
 
-// y = x * M for the multiplier whose tables start at byte offset `tab`.
-// Position p = 8c + m is bits 4m .. 4m+3 of word c (byte 4c + m/2 of the
-// block); entry (p, v) sits at tab + 256 p + 16 v, so below 64 KiB the
-// position's offset rides in the read's immediate field and the address
-// register is just 16 v.
+// y = x * M for the multiplier whose tables start at byte offset `tab` (a
+// multiple of 256 below 16 MiB).  Position p = 8c + m is bits 4m .. 4m+3 of
+// word c (byte 4c + m/2 of the block); entry (p, v) sits at tab + 256 p +
+// 16 v: the position's offset rides in the read's immediate field, and the
+// address register is 16 v in byte 0 and tab in bytes 1 and 2, put together
+// by one byte permute from the word's nibbles masked in place (high nibbles:
+// x & 0xF0F0F0F0; low ones: (x << 4) & 0xF0F0F0F0).
 __device__ __forceinline__ void mul_tab(const uint32_t *lds, uint32_t tab, const uint32_t (&x)[4],
                                         uint32_t (&y)[4]) {
     uint32_t acc[4] = {0, 0, 0, 0};
@@ -46,13 +48,16 @@ __device__ __forceinline__ void mul_tab(const uint32_t *lds, uint32_t tab, const
         // addresses and reads are formed here rather than all 32 up front,
         // which would need 128 more registers
         asm volatile("" : "+v"(xc) :: "memory");
-        const uint32_t x4 = xc << 4;
+        const uint32_t xh = xc & 0xF0F0F0F0u;           // high nibble of every byte, times 16
+        const uint32_t xl = (xc << 4) & 0xF0F0F0F0u;    // low nibble of every byte, times 16
 #pragma unroll
         for (int b = 0; b < 4; b++) {
-            const uint32_t vlo = (x4 >> (8 * b)) & 0xF0u;   // low nibble of byte b, times 16
-            const uint32_t vhi = (xc >> (8 * b)) & 0xF0u;   // high nibble of byte b, times 16
-            const u32x4 t0 = lds_load16(lds, vlo + tab + uint32_t(8 * c + 2 * b) * 256u);
-            const u32x4 t1 = lds_load16(lds, vhi + tab + uint32_t(8 * c + 2 * b + 1) * 256u);
+            // byte 0: byte b of the masked word; bytes 1, 2: tab's; byte 3: 0
+            const uint32_t sel = 0x0C020104u + uint32_t(b);
+            const uint32_t alo = __builtin_amdgcn_perm(xl, tab, sel);
+            const uint32_t ahi = __builtin_amdgcn_perm(xh, tab, sel);
+            const u32x4 t0 = lds_load16(lds, alo + uint32_t(8 * c + 2 * b) * 256u);
+            const u32x4 t1 = lds_load16(lds, ahi + uint32_t(8 * c + 2 * b + 1) * 256u);
             acc[0] = xor3(acc[0], t0.x, t1.x);
             acc[1] = xor3(acc[1], t0.y, t1.y);
             acc[2] = xor3(acc[2], t0.z, t1.z);
@@ -161,38 +166,39 @@ __device__ __forceinline__ void encrypt_one(const uint32_t *t0, const uint32_t *
 
 
 // One wave builds the table of multiplier m (the same four words in every
-// lane) at byte offset dst, with kVecBytes of scratch at vec; both regions
-// belong to this wave alone.  LDS accesses of one wave complete in order, so
-// the fences only keep the compiler from moving reads above writes.
-__device__ __forceinline__ void build_table_wave(uint32_t *lds, uint32_t dst, uint32_t vec, const uint32_t (&m)[4]) {
+// lane) at byte offset dst, which belongs to this wave alone.  Lane l fills
+// the 8 entries (p, v) of position p = l / 2 with bit 3 of v equal to l & 1:
+// bit t of nibble value v at position p (4c + h/2 ... see mul_tab) is the
+// coefficient of x^(e + 3 - t), e = 8 * byte + 4 - 4 * half, so the lane
+// forms M x^e .. M x^(e+3) itself (a shift by e and three by one) and its
+// entries as sums of those, in memory form (the conversion is linear).  No
+// LDS is read; the fences only keep the compiler from moving table reads
+// above the writes (a wave's LDS accesses complete in order).
+__device__ __forceinline__ void build_table_wave(uint32_t *lds, uint32_t dst, const uint32_t (&m)[4]) {
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t p = lane >> 1, hb = lane & 1u;
+    const uint32_t byte = 4u * (p >> 3) + ((p & 7u) >> 1), half = p & 1u;
     uint64_t lo, hi;
     to_poly(m, lo, hi);
+    mulx_pow(lo, hi, 8u * byte + 4u - 4u * half);
+    uint32_t vk[4][4];   // M x^(e + k), memory form
 #pragma unroll
-    for (uint32_t h = 0; h < 2; h++) {
-        const uint32_t e = 2u * lane + h;
-        uint64_t vlo = lo, vhi = hi;
-        mulx_pow(vlo, vhi, e);
-        uint32_t r[4];
-        from_poly(vlo, vhi, r);
-        lds_store16(lds, vec + e * 16u, vec4(r[0], r[1], r[2], r[3]));
+    for (int k = 0; k < 4; k++) {
+        from_poly(lo, hi, vk[k]);
+        mulx_small(lo, hi, 1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // v = 8 hb + j: bit 3 (t = 3) takes M x^e, bit 2 M x^(e+1), bit 1 M x^(e+2), bit 0 M x^(e+3)
+    uint32_t base[4];
 #pragma unroll
-    for (uint32_t q = 0; q < 8; q++) {
-        const uint32_t i = q * 64u + lane, p = i >> 4, v = i & 15u;
-        const uint32_t byte = 4u * (p >> 3) + ((p & 7u) >> 1), half = p & 1u;
-        u32x4 acc = vec4(0, 0, 0, 0);
+    for (int c = 0; c < 4; c++)
+        base[c] = hb ? vk[0][c] : 0u;
 #pragma unroll
-        for (uint32_t t = 0; t < 4; t++) {
-            if ((v >> t) & 1u) {
-                const uint32_t e = 8u * byte + 7u - 4u * half - t;
-                acc ^= lds_load16(lds, vec + e * 16u);
-            }
-        }
-        lds_store16(lds, dst + p * 256u + v * 16u, acc);
+    for (uint32_t j = 0; j < 8; j++) {
+        uint32_t e[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            e[c] = base[c] ^ ((j & 1u) ? vk[3][c] : 0u) ^ ((j & 2u) ? vk[2][c] : 0u) ^ ((j & 4u) ? vk[1][c] : 0u);
+        lds_store16(lds, dst + p * 256u + (8u * hb + j) * 16u, vec4(e[0], e[1], e[2], e[3]));
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
