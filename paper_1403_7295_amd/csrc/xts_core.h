@@ -59,6 +59,12 @@ __device__ __forceinline__ void xts_group(const uint32_t *lds, const LaneConsts 
             encrypt_global<NR>(rk2, tw);
         }
     }
+    // when a unit spans at least 64 x BPT blocks, a lane's BPT blocks of a
+    // step (64 apart, the step starting on a multiple of 64 x BPT inside the
+    // unit) all lie in one unit, and each tweak is the previous one times
+    // alpha^64: one shift by 64 with reduction instead of a shift by j
+    constexpr uint32_t kLogBpt = BPT == 1 ? 0u : BPT == 2 ? 1u : BPT == 4 ? 2u : 3u;
+    const bool one_unit = ushift >= 6u + kLogBpt;
     for (uint64_t base = gb0; base < gb1; base += 64u * BPT) {
         const uint32_t nwhole = uint32_t(min<uint64_t>(gb1 - base, 64u * BPT));
         const uint8_t *inb = in + 16 * base;
@@ -68,6 +74,22 @@ __device__ __forceinline__ void xts_group(const uint32_t *lds, const LaneConsts 
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
             const uint32_t jj = uint32_t(i) * 64u + lane;
+            uint64_t lo, hi;
+            if (i > 0 && one_unit) {
+                lo = tlo[i - 1];
+                hi = thi[i - 1];
+                mulx64(lo, hi);
+                tlo[i] = lo;
+                thi[i] = hi;
+                u32x4 x = vec4(0, 0, 0, 0);
+                if (jj < nwhole)
+                    x = load16(inb + 16u * jj);
+                s[i][0] = x.x ^ uint32_t(lo) ^ rk1[0];
+                s[i][1] = x.y ^ uint32_t(lo >> 32) ^ rk1[1];
+                s[i][2] = x.z ^ uint32_t(hi) ^ rk1[2];
+                s[i][3] = x.w ^ uint32_t(hi >> 32) ^ rk1[3];
+                continue;
+            }
             const uint64_t k = base - gb0 + jj;            // block index within the group
             const uint32_t src = uint32_t(k >> ushift) & 63u;
             const uint32_t j = uint32_t(k) & ((1u << ushift) - 1u);
@@ -86,7 +108,8 @@ __device__ __forceinline__ void xts_group(const uint32_t *lds, const LaneConsts 
                 w2 = __builtin_amdgcn_ds_bpermute(int(src << 2), int(tw[2]));
                 w3 = __builtin_amdgcn_ds_bpermute(int(src << 2), int(tw[3]));
             }
-            uint64_t lo = uint64_t(w0) | (uint64_t(w1) << 32), hi = uint64_t(w2) | (uint64_t(w3) << 32);
+            lo = uint64_t(w0) | (uint64_t(w1) << 32);
+            hi = uint64_t(w2) | (uint64_t(w3) << 32);
             mulx_pow(lo, hi, j);
             tlo[i] = lo;
             thi[i] = hi;
