@@ -16,6 +16,7 @@ Prints one JSON line.  Besides the headline it carries:
                 copy kernel's measured bandwidth);
   cpu_baseline  the oracle (plain byte-oriented C AES) on the host's cores,
                 run with the paper's pthreads chunking on a bounded sample;
+  cpu_context   for comparison only: `openssl speed` (AES-NI) on the same cores;
   secondary     the other operations of the path on the same buffer (CTR,
                 ECB decryption, AES-256) and the copy kernel's bandwidth.
 """
@@ -177,6 +178,34 @@ def cpu_baseline(sample_bytes):
             "single_thread_paper_style_GB/s": round(one_bytes / one_paper / 1e9, 5),
             "single_thread_sample": "the first %d MiB, 1 thread, 1 warm-up + median of 5 runs, %.2f s each"
                                     % (one_bytes >> 20, one_med)}
+
+
+def cpu_context_openssl(seconds=1, block=16384):
+    """An optimised CPU for context, beside the oracle: `openssl speed` of
+    AES-128 ECB through EVP (AES-NI where the host has it) in one process per
+    host core, 16 KiB blocks.  A comparison system, not the oracle and not a
+    target; None when the executable is missing or does not answer."""
+    import shutil
+    import subprocess
+    exe = shutil.which("openssl")
+    if exe is None:
+        return None
+    procs = len(os.sched_getaffinity(0))
+    cmd = [exe, "speed", "-evp", "aes-128-ecb", "-seconds", str(seconds), "-bytes", str(block),
+           "-multi", str(procs)]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=60)
+    except (OSError, subprocess.TimeoutExpired):
+        return None
+    rate = None
+    for line in r.stdout.splitlines():
+        f = line.split()
+        if len(f) == 2 and f[0] == "evp" and f[1].endswith("k"):
+            rate = float(f[1][:-1]) * 1000.0   # bytes per second, all processes
+    if r.returncode != 0 or rate is None:
+        return None
+    return {"GB/s": round(rate / 1e9, 2), "processes": procs, "kind": "openssl speed (comparison system)",
+            "cpu_model": cpu_model(), "command": " ".join(["openssl"] + cmd[1:])}
 
 
 LDS_GATHER_ROUNDS = 4096
@@ -602,6 +631,7 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_mib << 20)
+        out["cpu_context"] = cpu_context_openssl()
     print(json.dumps(out))
 
 

@@ -59,6 +59,7 @@ def test_bench_line_fields():
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], rel=1e-3)
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["value"] > 0 and cpu["cores"] >= 1 and cpu["sample"]
+    assert "cpu_context" in d and (d["cpu_context"] is None or d["cpu_context"]["GB/s"] > 0)
     lds = d["lds_gather"]
     assert lds["Tlookup/s"] > 0 and d["roofline_issue"]["measured_peak"] == lds["Tlookup/s"]
 
@@ -73,3 +74,15 @@ def test_cpu_baseline_record():
     assert "median of 5 runs" in c["sample"] and "warm-up" in c["sample"]
     assert c["single_thread_GB/s"] > 0 and "median of 5 runs" in c["single_thread_sample"]
     assert c["paper_style_GB/s"] > 0
+
+
+def test_cpu_context_record():
+    # openssl speed for context, kept apart from the oracle baseline; absent
+    # (None) only where the host has no openssl executable
+    import shutil
+    c = bench.cpu_context_openssl()
+    if shutil.which("openssl") is None:
+        assert c is None
+        return
+    assert c["GB/s"] > 0 and c["processes"] == len(os.sched_getaffinity(0))
+    assert c["kind"].startswith("openssl speed") and "aes-128-ecb" in c["command"]
