@@ -915,25 +915,48 @@ __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, const B
                     sel(v.z, lenblk.z, ctail.z, atail.z), sel(v.w, lenblk.w, ctail.w, atail.w));
     };
     constexpr int kPrefetch = 2;
-    const uint64_t steps = (p_hi - p_lo + 63) >> 6;
-    u32x4 v[kPrefetch];
-#pragma unroll
-    for (int i = 0; i < kPrefetch; i++)
-        v[i] = steps > uint64_t(i) ? load_at(steps - 1 - i) : vec4(0, 0, 0, 0);
     uint32_t w[4] = {0, 0, 0, 0};
-    for (uint64_t q = steps; q-- > 0;) {
-        const u32x4 vn = q >= uint64_t(kPrefetch) ? load_at(q - kPrefetch) : vec4(0, 0, 0, 0);
-        uint32_t t[4];
-        mul_tab(lds, tab, w, t);
-        const u32x4 x = pick(q, v[0]);
-        w[0] = t[0] ^ x.x;
-        w[1] = t[1] ^ x.y;
-        w[2] = t[2] ^ x.z;
-        w[3] = t[3] ^ x.w;
+    if (p_lo >= 2 && p_lo + kGhashPiece <= nC + 1) {
+        // a whole piece of whole ciphertext blocks (neither the length block
+        // nor a partial last block, no additional data): step s (q = 63 - s)
+        // reads the 1 KiB at p0 + 1024 s, no position tests
+        constexpr uint32_t kSteps = uint32_t(kGhashPiece >> 6);
+        const uint8_t *p0 = ct + 16 * (nC - p_lo - (kGhashPiece - 64) - lane);
+        auto ld = [&](uint32_t s) {
+            return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p0 + 1024u * s));
+        };
+        u32x4 v0 = ld(0), v1 = ld(1);
+        for (uint32_t s = 0; s < kSteps; s++) {
+            const u32x4 vn = ld(min(s + uint32_t(kPrefetch), kSteps - 1));   // always a block of the piece
+            uint32_t t[4];
+            mul_tab(lds, tab, w, t);
+            w[0] = t[0] ^ v0.x;
+            w[1] = t[1] ^ v0.y;
+            w[2] = t[2] ^ v0.z;
+            w[3] = t[3] ^ v0.w;
+            v0 = v1;
+            v1 = vn;
+        }
+    } else {
+        const uint64_t steps = (p_hi - p_lo + 63) >> 6;
+        u32x4 v[kPrefetch];
 #pragma unroll
-        for (int i = 0; i + 1 < kPrefetch; i++)
-            v[i] = v[i + 1];
-        v[kPrefetch - 1] = vn;
+        for (int i = 0; i < kPrefetch; i++)
+            v[i] = steps > uint64_t(i) ? load_at(steps - 1 - i) : vec4(0, 0, 0, 0);
+        for (uint64_t q = steps; q-- > 0;) {
+            const u32x4 vn = q >= uint64_t(kPrefetch) ? load_at(q - kPrefetch) : vec4(0, 0, 0, 0);
+            uint32_t t[4];
+            mul_tab(lds, tab, w, t);
+            const u32x4 x = pick(q, v[0]);
+            w[0] = t[0] ^ x.x;
+            w[1] = t[1] ^ x.y;
+            w[2] = t[2] ^ x.z;
+            w[3] = t[3] ^ x.w;
+#pragma unroll
+            for (int i = 0; i + 1 < kPrefetch; i++)
+                v[i] = v[i + 1];
+            v[kPrefetch - 1] = vn;
+        }
     }
     // sum_l w_l H^l over the lanes
     uint64_t plo = hlo, phi = hhi;

@@ -404,7 +404,7 @@ def test_sector_batch_full_size_sampled(A, O):
 
 
 # --- GCM messages in a batch -------------------------------------------------
-def gcm_batch(A, O, n, seed, max_len=1 << 16, big=(), n_other=0):
+def gcm_batch(A, O, n, seed, max_len=1 << 16, big=(), n_other=0, big_aad=None):
     """n GCM messages (and n_other CTR/ECB ones), 128/192/256-bit keys,
     lengths log-uniform up to max_len plus the lengths in `big`, additional
     data of 0 .. 1000 bytes (larger for the big ones), half encryptions and
@@ -421,7 +421,7 @@ def gcm_batch(A, O, n, seed, max_len=1 << 16, big=(), n_other=0):
     aadl = rng.integers(0, 1001, n)
     aadl[1] = 0
     for i in range(len(big)):
-        aadl[n - 1 - i] = 100000 + 7 * i
+        aadl[n - len(big) + i] = big_aad[i] if big_aad is not None else 100000 + 7 * (len(big) - 1 - i)
     keys = np.zeros((n + n_other, 32), np.uint8)
     for m in range(n + n_other):
         keys[m, :keybits[m] // 8] = seedgen.key(seed, m, int(keybits[m]))
@@ -542,6 +542,28 @@ def test_gcm_batch_refuses_bad_fields(A, O):
     b2 = A.Batch(descs, keys, xd, yd)
     b2.run()
     assert b2.query()[1] == n
+
+
+def test_gcm_batch_piece_boundaries(A, O):
+    """Messages around the edges of the GHASH pieces of 4,096 positions
+    (position 0 the length block, 1 .. nC the ciphertext blocks from the
+    last, then the additional data): a piece made only of whole ciphertext
+    blocks takes the hash's fast path, here with its last position exactly
+    the first ciphertext block (nC = 8,191 and 12,287), one short of it,
+    with and without a partial last block and additional data."""
+    big, big_aad = [], []
+    for nc in (4095, 4096, 4097, 8190, 8191, 8192, 12287):
+        for t, aad in ((0, 0), (1, 0), (15, 33), (0, 16)):
+            big.append(16 * nc - t)
+            big_aad.append(aad)
+    descs, keys, g, x, want, n = gcm_batch(A, O, 3, 79, max_len=64, big=big, big_aad=big_aad)
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.zeros_like(xd)
+    b = A.Batch(descs, keys, xd, yd, gcm=g)
+    b.run()
+    assert b.query() == (len(descs), 0)
+    check_gcm_batch(A, O, b, descs, keys, x, yd.cpu().numpy(), want, n, b.gcm_results(len(descs)))
+    b.close()
 
 
 def test_gcm_batch_message_beyond_the_stored_powers(A):
