@@ -440,6 +440,37 @@ __device__ __forceinline__ void process_blocks(const uint32_t *lds, const LaneCo
                 s[i][3] = q3 ^ tl<LAYOUT, 1, 1>(lds, lc, t0);
             }
             rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, 3);
+        } else if (BPT == 4) {
+            // The step's 256 counters cross one multiple of 256: the blocks
+            // before it share their top 24 bits (A), the others the next
+            // value (B, mod 2^24).  The 15 shared lookups are done for both,
+            // and each block takes its own set: 30 lookups for the step
+            // instead of 15 per block.
+            auto shared = [&](uint32_t g3, uint32_t (&q)[4]) __attribute__((always_inline)) {
+                const uint32_t t1 = pre1 ^ tl<LAYOUT, 2, 2>(lds, lc, g3);
+                const uint32_t t2 = pre2 ^ tl<LAYOUT, 1, 1>(lds, lc, g3);
+                const uint32_t t3 = pre3 ^ tl<LAYOUT, 0, 0>(lds, lc, g3);
+                q[0] = tl<LAYOUT, 1, 1>(lds, lc, t1) ^ tl<LAYOUT, 2, 2>(lds, lc, t2) ^ tl<LAYOUT, 3, 3>(lds, lc, t3) ^ rk[8];
+                q[1] = tl<LAYOUT, 0, 0>(lds, lc, t1) ^ tl<LAYOUT, 1, 1>(lds, lc, t2) ^ tl<LAYOUT, 2, 2>(lds, lc, t3) ^ rk[9];
+                q[2] = tl<LAYOUT, 0, 0>(lds, lc, t2) ^ tl<LAYOUT, 1, 1>(lds, lc, t3) ^ tl<LAYOUT, 3, 3>(lds, lc, t1) ^ rk[10];
+                q[3] = tl<LAYOUT, 0, 0>(lds, lc, t3) ^ tl<LAYOUT, 2, 2>(lds, lc, t1) ^ tl<LAYOUT, 3, 3>(lds, lc, t2) ^ rk[11];
+            };
+            uint32_t qa[4], qb[4];
+            shared(bswap(cstep) ^ rk[3], qa);
+            shared(bswap(cstep + 256u) ^ rk[3], qb);
+            const uint32_t lo = cstep & 255u;
+#pragma unroll
+            for (int i = 0; i < BPT; i++) {
+                const uint32_t jj = uint32_t(i) * 64u + lane;
+                const bool b = lo + jj >= 256u;
+                const uint32_t v3 = bswap(cstep + jj) ^ rk[3];
+                const uint32_t t0 = pre0 ^ tl<LAYOUT, 3, 3>(lds, lc, v3);
+                s[i][0] = (b ? qb[0] : qa[0]) ^ tl<LAYOUT, 0, 0>(lds, lc, t0);
+                s[i][1] = (b ? qb[1] : qa[1]) ^ tl<LAYOUT, 3, 3>(lds, lc, t0);
+                s[i][2] = (b ? qb[2] : qa[2]) ^ tl<LAYOUT, 2, 2>(lds, lc, t0);
+                s[i][3] = (b ? qb[3] : qa[3]) ^ tl<LAYOUT, 1, 1>(lds, lc, t0);
+            }
+            rounds<NR, DIR, LAYOUT, BPT>(s, lds, lc, rk, 3);
         } else {
             // counter block j: nonce || big-endian (c0 + j) mod 2^32;
             // round 1 needs only the four lookups on column 3.

@@ -184,38 +184,41 @@ __global__ __launch_bounds__(1024) void gcm_kernel(const GcmArgs a) {
             x[i][2] = v.z;
             x[i][3] = v.w;
         }
+        // rounds 1 and 2.  The chunk's blocks are 256 consecutive ones, from
+        // `low` = nC - head - 256q - 255 (slot 3's first) up; their counters
+        // cross at most one multiple of 256, so they have at most two values
+        // of their top 24 bits (A below it, B from it on).  After round 1
+        // columns 1..3 depend only on those bits, and so do 12 of round 2's
+        // lookups: 15 lookups for each of A and B per chunk, and five per
+        // block.
+        const uint32_t cb = c1 + uint32_t(nC - head - 256 * q - 255);
+        auto shared = [&](uint32_t g3, uint32_t (&qv)[4]) __attribute__((always_inline)) {
+            const uint32_t t1 = pre1 ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, g3);
+            const uint32_t t2 = pre2 ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, g3);
+            const uint32_t t3 = pre3 ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, g3);
+            qv[0] = xor3(tl<LAYOUT_T4X32, 1, 1>(aes, lc, t1), tl<LAYOUT_T4X32, 2, 2>(aes, lc, t2),
+                         tl<LAYOUT_T4X32, 3, 3>(aes, lc, t3)) ^ a.rk[8];
+            qv[1] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t1), tl<LAYOUT_T4X32, 1, 1>(aes, lc, t2),
+                         tl<LAYOUT_T4X32, 2, 2>(aes, lc, t3)) ^ a.rk[9];
+            qv[2] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t2), tl<LAYOUT_T4X32, 1, 1>(aes, lc, t3),
+                         tl<LAYOUT_T4X32, 3, 3>(aes, lc, t1)) ^ a.rk[10];
+            qv[3] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t3), tl<LAYOUT_T4X32, 2, 2>(aes, lc, t1),
+                         tl<LAYOUT_T4X32, 3, 3>(aes, lc, t2)) ^ a.rk[11];
+        };
+        uint32_t qa[4], qb[4];
+        shared(__builtin_bswap32(cb) ^ a.rk[3], qa);
+        shared(__builtin_bswap32(cb + 256u) ^ a.rk[3], qb);
 #pragma unroll
         for (int i = 0; i < BPT; i++) {
-            const uint64_t top = nC - head - 256 * q - 64u * uint32_t(i) - 63;
-            // rounds 1 and 2 (the counters of the slot are cs .. cs + 63)
-            const uint32_t cs = c1 + uint32_t(top);
-            const uint32_t v3 = __builtin_bswap32(cs + (63u - lane)) ^ a.rk[3];
+            // lane l of slot i: block top + 63 - l, the (64 (3 - i) + 63 - l)-th of the chunk
+            const uint32_t jj = 64u * uint32_t(BPT - 1 - i) + (63u - lane);
+            const bool b = (cb & 255u) + jj >= 256u;
+            const uint32_t v3 = __builtin_bswap32(cb + jj) ^ a.rk[3];
             const uint32_t t0 = pre0 ^ tl<LAYOUT_T4X32, 3, 3>(aes, lc, v3);
-            if ((cs & 255u) + 64u <= 256u) {
-                // the slot's counters share their top 24 bits: after round 1
-                // columns 1..3 are the same for all 64 blocks, and so are 12
-                // of round 2's lookups (15 lookups per slot, not per block)
-                const uint32_t g3 = __builtin_bswap32(cs) ^ a.rk[3];
-                const uint32_t t1 = pre1 ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, g3);
-                const uint32_t t2 = pre2 ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, g3);
-                const uint32_t t3 = pre3 ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, g3);
-                s[i][0] = xor3(tl<LAYOUT_T4X32, 1, 1>(aes, lc, t1), tl<LAYOUT_T4X32, 2, 2>(aes, lc, t2),
-                               tl<LAYOUT_T4X32, 3, 3>(aes, lc, t3)) ^ a.rk[8] ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, t0);
-                s[i][1] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t1), tl<LAYOUT_T4X32, 1, 1>(aes, lc, t2),
-                               tl<LAYOUT_T4X32, 2, 2>(aes, lc, t3)) ^ a.rk[9] ^ tl<LAYOUT_T4X32, 3, 3>(aes, lc, t0);
-                s[i][2] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t2), tl<LAYOUT_T4X32, 1, 1>(aes, lc, t3),
-                               tl<LAYOUT_T4X32, 3, 3>(aes, lc, t1)) ^ a.rk[10] ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, t0);
-                s[i][3] = xor3(tl<LAYOUT_T4X32, 0, 0>(aes, lc, t3), tl<LAYOUT_T4X32, 2, 2>(aes, lc, t1),
-                               tl<LAYOUT_T4X32, 3, 3>(aes, lc, t2)) ^ a.rk[11] ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, t0);
-            } else {
-                const uint32_t t1 = pre1 ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, v3);
-                const uint32_t t2 = pre2 ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, v3);
-                const uint32_t t3 = pre3 ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, v3);
-                s[i][0] = round_col<LAYOUT_T4X32>(aes, lc, t0, t1, t2, t3, a.rk[8]);
-                s[i][1] = round_col<LAYOUT_T4X32>(aes, lc, t1, t2, t3, t0, a.rk[9]);
-                s[i][2] = round_col<LAYOUT_T4X32>(aes, lc, t2, t3, t0, t1, a.rk[10]);
-                s[i][3] = round_col<LAYOUT_T4X32>(aes, lc, t3, t0, t1, t2, a.rk[11]);
-            }
+            s[i][0] = (b ? qb[0] : qa[0]) ^ tl<LAYOUT_T4X32, 0, 0>(aes, lc, t0);
+            s[i][1] = (b ? qb[1] : qa[1]) ^ tl<LAYOUT_T4X32, 3, 3>(aes, lc, t0);
+            s[i][2] = (b ? qb[2] : qa[2]) ^ tl<LAYOUT_T4X32, 2, 2>(aes, lc, t0);
+            s[i][3] = (b ? qb[3] : qa[3]) ^ tl<LAYOUT_T4X32, 1, 1>(aes, lc, t0);
         }
         rounds<NR, DIR_ENC, LAYOUT_T4X32, BPT>(s, aes, lc, a.rk, 3);
 #pragma unroll

@@ -162,6 +162,29 @@ def test_launch_configurations_agree(A, ragged_case, cfg):
         A.aes_set_launch(None)
 
 
+@pytest.mark.parametrize("start", [1, 0x80, 0xFF, 0xFFFFFF81], ids=lambda v: "c%08x" % v)
+def test_ctr_unaligned_counter_starts(A, O, start):
+    """CTR whose 32-bit counter starts off a multiple of 256: every step of
+    256 blocks then crosses one, and the blocks on either side share
+    different round-1 columns (the last start also crosses the 2^32 wrap).
+    Every table layout at four blocks per thread, default grid and seven
+    workgroups, against the oracle on a ragged 1 MiB buffer."""
+    k = seedgen.key(9, start & 0xFF, 128)
+    rk, nr = A.aes_expand_key(k)
+    x = seedgen.data_np(9, 1, (1 << 20) + 21)
+    ctr0 = seedgen.nonce(9, 2)
+    ctr0[12:16] = list(int(start).to_bytes(4, "big"))
+    want = O.ctr(rk, nr, ctr0, x)
+    for layout in (0, 1, 3, 4):
+        for grid in (0, 7):
+            cfg = dict(layout=layout, blocks_per_thread=4, wg_size=1024, grid=grid)
+            A.aes_set_launch(cfg)
+            try:
+                assert_same(gpu_op(A, "ctr", x, rk, nr, ctr0=ctr0), want, "ctr from %#x %s" % (start, cfg))
+            finally:
+                A.aes_set_launch(None)
+
+
 def test_side_stream(A, O):
     k = seedgen.key(7, 0, 256)
     rk, nr = A.aes_expand_key(k)
