@@ -914,6 +914,11 @@ __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, const B
         return vec4(sel(v.x, lenblk.x, ctail.x, atail.x), sel(v.y, lenblk.y, ctail.y, atail.y),
                     sel(v.z, lenblk.z, ctail.z, atail.z), sel(v.w, lenblk.w, ctail.w, atail.w));
     };
+    // the stored powers H^(kGhashPiece 2^t) for the piece's factor below,
+    // one vector load for all of them (lane t holds power t) issued here, so
+    // that its latency passes during the hashing
+    const u32x4 pows = *reinterpret_cast<const u32x4 *>(
+        slot + kGcmSlotPow + 4 * (lane < uint32_t(kGcmSlotPowers) ? lane : 0u));
     constexpr int kPrefetch = 2;
     uint32_t w[4] = {0, 0, 0, 0};
     if (p_lo >= 2 && p_lo + kGhashPiece <= nC + 1) {
@@ -921,21 +926,27 @@ __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, const B
         // nor a partial last block, no additional data): step s (q = 63 - s)
         // reads the 1 KiB at p0 + 1024 s, no position tests
         constexpr uint32_t kSteps = uint32_t(kGhashPiece >> 6);
+        constexpr uint32_t kAhead = uint32_t(kPrefetch);
         const uint8_t *p0 = ct + 16 * (nC - p_lo - (kGhashPiece - 64) - lane);
         auto ld = [&](uint32_t s) {
             return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p0 + 1024u * s));
         };
-        u32x4 v0 = ld(0), v1 = ld(1);
+        u32x4 v[kAhead];
+#pragma unroll
+        for (uint32_t i = 0; i < kAhead; i++)
+            v[i] = ld(i);
         for (uint32_t s = 0; s < kSteps; s++) {
-            const u32x4 vn = ld(min(s + uint32_t(kPrefetch), kSteps - 1));   // always a block of the piece
+            const u32x4 vn = ld(min(s + kAhead, kSteps - 1));   // always a block of the piece
             uint32_t t[4];
             mul_tab(lds, tab, w, t);
-            w[0] = t[0] ^ v0.x;
-            w[1] = t[1] ^ v0.y;
-            w[2] = t[2] ^ v0.z;
-            w[3] = t[3] ^ v0.w;
-            v0 = v1;
-            v1 = vn;
+            w[0] = t[0] ^ v[0].x;
+            w[1] = t[1] ^ v[0].y;
+            w[2] = t[2] ^ v[0].z;
+            w[3] = t[3] ^ v[0].w;
+#pragma unroll
+            for (uint32_t i = 0; i + 1 < kAhead; i++)
+                v[i] = v[i + 1];
+            v[kAhead - 1] = vn;
         }
     } else {
         const uint64_t steps = (p_hi - p_lo + 63) >> 6;
@@ -981,8 +992,10 @@ __device__ __forceinline__ void ghash_piece(uint32_t *lds, uint32_t tab, const B
     mul_wave(rlo, rhi, hlo, hhi, rlo, rhi);
     for (int t = 0; (piece >> t) != 0; t++) {
         if (t < kGcmSlotPowers) {
-            const uint32_t pw[4] = {uniform32(slot[kGcmSlotPow + 4 * t]), uniform32(slot[kGcmSlotPow + 4 * t + 1]),
-                                    uniform32(slot[kGcmSlotPow + 4 * t + 2]), uniform32(slot[kGcmSlotPow + 4 * t + 3])};
+            const uint32_t pw[4] = {uint32_t(__builtin_amdgcn_readlane(int(pows.x), t)),
+                                    uint32_t(__builtin_amdgcn_readlane(int(pows.y), t)),
+                                    uint32_t(__builtin_amdgcn_readlane(int(pows.z), t)),
+                                    uint32_t(__builtin_amdgcn_readlane(int(pows.w), t))};
             to_poly(pw, blo, bhi);
         } else {
             gf_square(blo, bhi);   // beyond the stored powers (messages over 2^(12+13) blocks)
