@@ -396,7 +396,9 @@ typedef struct {
  * forward list; then their GHASH (section 6.4) over the additional data,
  * the ciphertext and the lengths is cut into pieces of up to 4,096 blocks,
  * one wave per piece (the pieces' sums are added by linearity), and a last
- * kernel forms or checks each tag.  A message with an invalid descriptor (bad key code or
+ * kernel forms or checks each tag.  GCM messages of at least 131,072 GHASH
+ * blocks (about 2 MiB) are encrypted and hashed in one pass instead, one
+ * workgroup per piece of 65,536 blocks.  A message with an invalid descriptor (bad key code or
  * mode, ECB length not a multiple of 16, misaligned offset, outside the
  * buffers, input and output partly overlapping, key_idx >= nkeys) is
  * skipped and counted (aes_batch_query).
@@ -440,7 +442,7 @@ int aes_batch_run(const aes_batch *b, void *stream);
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * The batch's workspace is not the caller's: it is a buffer the library
  * holds in device memory for the life of the process, one per device
- * (AES_BATCH_NOALLOC_MAX_MSGS messages' worth, about 9.0 MiB), set up with
+ * (AES_BATCH_NOALLOC_MAX_MSGS messages' worth, about 9.3 MiB), set up with
  * the device's other state on the first call.  The call allocates nothing;
  * the caller still passes descriptors, keys, input and output as for
  * aes_batch_run, with b->workspace NULL and b->workspace_bytes 0.

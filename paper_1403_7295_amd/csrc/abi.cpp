@@ -610,7 +610,7 @@ int aes_batch_run(const aes_batch *b, void *stream) {
         return st;
     // without a device-side count the host knows how many messages there are
     // the GHASH and tag kernels only if the batch can hold GCM messages
-    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 15u : 7u,
+    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 31u : 7u,
                                 a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -643,7 +643,7 @@ int aes_batch_run_noalloc(const aes_batch *b, void *stream) {
     st = batch_args(&w, &a);
     if (st != AES_OK)
         return st;
-    e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 15u : 7u,
+    e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 31u : 7u,
                      a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -662,7 +662,7 @@ int aes_batch_query(const aes_batch *b, void *stream, uint64_t *planned, uint64_
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch query: ") + hipGetErrorString(e));
     if (planned)
-        *planned = uint64_t(h.nitems[0]) + h.nitems[1] + h.nitems[2];
+        *planned = uint64_t(h.nitems[0]) + h.nitems[1] + h.nitems[2] + h.nfused[0] + h.nfused[1] + h.nfused[2];
     if (rejected)
         *rejected = h.rejected;
     return AES_OK;
@@ -686,7 +686,7 @@ int aes_batch_graph_create(const aes_batch *b, void **graph) {
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         // the count may change per replay
-        hipError_t le = launch_batch(a, batch_grid(*d), s, a.gcm ? 15u : 7u, a.max_msgs);
+        hipError_t le = launch_batch(a, batch_grid(*d), s, a.gcm ? 31u : 7u, a.max_msgs);
         e = hipStreamEndCapture(s, &g);
         if (le != hipSuccess)
             e = le;

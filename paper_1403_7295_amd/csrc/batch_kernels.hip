@@ -19,6 +19,11 @@
 //                   long lists, the second half of them taken off a counter)
 //                   with every message's round keys in scalar registers and
 //                   the same block loop as the single-buffer kernels.
+//   gcm_fused_kernel  GCM messages of at least kFusedMinPositions GHASH
+//                   positions (one kernel per key size): counter mode and
+//                   GHASH in one pass over each piece of kFusedPiece
+//                   positions, one workgroup per piece, as the single-buffer
+//                   GCM kernel does over a whole buffer.
 //   ghash_kernel    GCM messages only: GHASH (SP 800-38D section 6.4) over
 //                   each message's additional data, ciphertext and lengths,
 //                   cut into pieces of kGhashPiece positions, one wave per
@@ -322,10 +327,12 @@ __device__ __forceinline__ void block_exclusive_scan(uint64_t (&v)[N], uint64_t 
     }
 }
 
-// items in lists 0, 1, 2; cost of lists 0, 1; rejected; GCM messages; their
-// GHASH pieces; the short ones among them (at most kLaneGhashMaxPositions
-// positions: one piece each)
+// items in lists 0, 1, 2; cost of lists 0, 1; rejected; GCM messages hashed
+// in pieces; their GHASH pieces; the short ones among them (at most
+// kLaneGhashMaxPositions positions: one piece each); GCM messages encrypted
+// and hashed in one pass, per key size (9 .. 11), and their pieces (12 .. 14)
 constexpr int kPlanCounters = kBatchChunkCounters;
+constexpr int kFusedMsgs = 9, kFusedPieces = 12;
 
 // GHASH positions of a GCM message: its additional data, its ciphertext
 // and the length block, 16 bytes each.
@@ -339,13 +346,19 @@ __device__ __forceinline__ uint64_t mul_div_floor(uint64_t a, uint64_t b, uint64
     return uint64_t((unsigned __int128)a * b / c);
 }
 
+// Whether a valid GCM message goes to the fused list.
+__device__ __forceinline__ bool gcm_fused(const aes_msg_desc &d, const aes_gcm_desc &g) {
+    return d.mode == AES_MODE_GCM && ghash_positions(d, g) >= kFusedMinPositions;
+}
+
 // One message's contribution to the plan's counters (all zero past the
-// batch's end).
+// batch's end).  fused: a GCM message of the fused list, in no other list.
 __device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, uint32_t n, bool &valid, int &k,
-                                               uint64_t (&c)[kPlanCounters]) {
+                                               bool &fused, uint64_t (&c)[kPlanCounters]) {
     for (int j = 0; j < kPlanCounters; j++)
         c[j] = 0;
     valid = false;
+    fused = false;
     k = 0;
     if (m >= n)
         return;
@@ -356,6 +369,22 @@ __device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, 
     }
     valid = true;
     k = desc_class(d);
+    if (d.mode == AES_MODE_GCM) {
+        const uint64_t npos = ghash_positions(d, a.gcm[m]);
+        fused = npos >= kFusedMinPositions;
+        if (fused) {
+            const uint64_t pieces = (npos + kFusedPiece - 1) / kFusedPiece;
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                c[kFusedMsgs + j] = d.keybits_code == uint32_t(j) ? 1 : 0;
+                c[kFusedPieces + j] = d.keybits_code == uint32_t(j) ? pieces : 0;
+            }
+            return;
+        }
+        c[6] = 1;
+        c[7] = (npos + kGhashPiece - 1) / kGhashPiece;
+        c[8] = npos <= kLaneGhashMaxPositions ? 1 : 0;
+    }
     const uint64_t cost = ((d.nbytes + 15) >> 4) * block_cost(d);
     // (selects, not indexed stores: keeps c[] in registers)
     c[0] = k == 0 ? 1 : 0;
@@ -363,12 +392,6 @@ __device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, 
     c[2] = k == 2 ? 1 : 0;
     c[3] = k == 0 ? cost : 0;
     c[4] = k == 1 ? cost : 0;
-    if (d.mode == AES_MODE_GCM) {
-        const uint64_t npos = ghash_positions(d, a.gcm[m]);
-        c[6] = 1;
-        c[7] = (npos + kGhashPiece - 1) / kGhashPiece;
-        c[8] = npos <= kLaneGhashMaxPositions ? 1 : 0;
-    }
 }
 
 // Whether the batch hashes its short GCM messages one per lane: when there
@@ -386,6 +409,11 @@ __device__ __forceinline__ void gcm_header(BatchHeader *h, const uint64_t (&tota
     h->ngcm = uint32_t(total[6] - short_msgs);
     h->gcm_pieces = total[7] - short_msgs;
     h->nlane = uint32_t(short_msgs);
+    for (int j = 0; j < 3; j++) {
+        h->nfused[j] = uint32_t(total[kFusedMsgs + j]);
+        h->fused_pieces[j] = total[kFusedPieces + j];
+        h->next_fused[j] = 0;
+    }
 }
 
 // The GHASH list's item of GCM message m: its pieces, and the pieces of the
@@ -393,11 +421,23 @@ __device__ __forceinline__ void gcm_header(BatchHeader *h, const uint64_t (&tota
 // or, for a short message when the batch hashes those per lane, its place at
 // the back of the list.
 __device__ __forceinline__ void gcm_item(const BatchKArgs &a, uint32_t m, const uint64_t (&before)[kPlanCounters],
-                                         const uint64_t (&c)[kPlanCounters], bool lanes) {
+                                         const uint64_t (&c)[kPlanCounters], const uint64_t (&total)[kPlanCounters],
+                                         bool lanes) {
     const aes_msg_desc d = a.desc[m];
     if (d.mode != AES_MODE_GCM)
         return;
     const uint64_t npos = ghash_positions(d, a.gcm[m]);
+    if (npos >= kFusedMinPositions) {
+        // after the messages of the smaller key sizes
+        const int j = int(d.keybits_code);
+        const uint64_t off = (j > 0 ? total[kFusedMsgs] : 0) + (j > 1 ? total[kFusedMsgs + 1] : 0);
+        BatchItem it;
+        it.msg = m;
+        it.count = uint32_t((npos + kFusedPiece - 1) / kFusedPiece);
+        it.start = before[kFusedPieces + j] + c[kFusedPieces + j];
+        a.items[size_t(4) * a.max_msgs + off + before[kFusedMsgs + j] + c[kFusedMsgs + j]] = it;
+        return;
+    }
     const uint64_t short_before = lanes ? before[8] + c[8] : 0;
     BatchItem it;
     it.msg = m;
@@ -422,10 +462,11 @@ __global__ __launch_bounds__(kPlanThreads) void prep_kernel(const BatchKArgs a) 
         tab[i] = g_base[i];
     const uint32_t n = batch_count(a);
     const uint32_t m = blockIdx.x * kPlanThreads + threadIdx.x;
-    bool valid;
+    bool valid, fused;
     int k;
     uint64_t c[kPlanCounters], total[kPlanCounters];
-    message_counts(a, m, n, valid, k, c);
+    message_counts(a, m, n, valid, k, fused, c);
+    (void)fused;
     if (m < n && !valid && a.reject_flags)
         a.reject_flags[m] = 1;
     block_exclusive_scan<kPlanCounters>(c, wsum, total);   // its barrier also covers tab[]
@@ -455,10 +496,10 @@ __global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArg
         tab[i] = g_base[i];
     const uint32_t n = min(batch_count(a), uint32_t(kPlanThreads));
     const uint32_t m = threadIdx.x;
-    bool valid;
+    bool valid, fused;
     int k;
     uint64_t c[kPlanCounters], total[kPlanCounters];
-    message_counts(a, m, n, valid, k, c);
+    message_counts(a, m, n, valid, k, fused, c);
     if (m < n && !valid && a.reject_flags)
         a.reject_flags[m] = 1;
     block_exclusive_scan<kPlanCounters>(c, wsum, total);   // its barrier also covers tab[]
@@ -476,13 +517,15 @@ __global__ __launch_bounds__(kPlanThreads) void prep_plan_kernel(const BatchKArg
     if (!valid)
         return;
     const aes_msg_desc d = a.desc[m];
-    BatchItem it;
-    it.msg = m;
-    it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;
-    it.start = k == 0 ? c[3] : k == 1 ? c[4] : 0;
-    a.items[size_t(k) * a.max_msgs + (k == 0 ? c[0] : k == 1 ? c[1] : c[2])] = it;
+    if (!fused) {
+        BatchItem it;
+        it.msg = m;
+        it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;
+        it.start = k == 0 ? c[3] : k == 1 ? c[4] : 0;
+        a.items[size_t(k) * a.max_msgs + (k == 0 ? c[0] : k == 1 ? c[1] : c[2])] = it;
+    }
     const uint64_t zero[kPlanCounters] = {};
-    gcm_item(a, m, zero, c, lane_ghash(total));
+    gcm_item(a, m, zero, c, total, lane_ghash(total));
     uint32_t *slot = a.keytab + size_t(m) * kKeySlotWords;
     if (d.keybits_code == 0)
         expand_message_keys<4>(a, d, slot, tab);
@@ -518,20 +561,22 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const BatchKArgs a) 
     block_exclusive_scan<kPlanCounters>(all, wsum, sum_all);
     __syncthreads();
     const uint32_t m = blockIdx.x * kPlanThreads + threadIdx.x;
-    bool valid;
+    bool valid, fused;
     int k;
     uint64_t c[kPlanCounters], chunk_total[kPlanCounters];
-    message_counts(a, m, n, valid, k, c);
+    message_counts(a, m, n, valid, k, fused, c);
     block_exclusive_scan<kPlanCounters>(c, wsum, chunk_total);   // c: the messages before m in the chunk
     if (valid) {
         const aes_msg_desc d = a.desc[m];
-        BatchItem it;
-        it.msg = m;
-        it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;   // desc_valid keeps a serial message below 2^32 blocks
-        it.start = k == 0 ? base[3] + c[3] : k == 1 ? base[4] + c[4] : 0;
-        const uint64_t i = k == 0 ? base[0] + c[0] : k == 1 ? base[1] + c[1] : base[2] + c[2];
-        a.items[size_t(k) * a.max_msgs + i] = it;
-        gcm_item(a, m, base, c, lane_ghash(sum_all));
+        if (!fused) {
+            BatchItem it;
+            it.msg = m;
+            it.count = k == 2 ? uint32_t((d.nbytes + 15) >> 4) : 0u;   // desc_valid keeps a serial message below 2^32 blocks
+            it.start = k == 0 ? base[3] + c[3] : k == 1 ? base[4] + c[4] : 0;
+            const uint64_t i = k == 0 ? base[0] + c[0] : k == 1 ? base[1] + c[1] : base[2] + c[2];
+            a.items[size_t(k) * a.max_msgs + i] = it;
+        }
+        gcm_item(a, m, base, c, sum_all, lane_ghash(sum_all));
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         BatchHeader *h = a.header;
@@ -1268,6 +1313,316 @@ __global__ __launch_bounds__(64) void ghash_lane_kernel(const BatchKArgs a) {
     }
 }
 
+// ---- GCM: large messages encrypted and hashed in one pass -----------------
+// A GCM message of at least kFusedMinPositions GHASH positions is cut into
+// pieces of kFusedPiece positions (numbered from the end as in ghash_block:
+// piece f holds r = kFusedPiece f .. kFusedPiece (f + 1) - 1), and one
+// workgroup takes a piece whole, with the AES tables and the table of
+// G = H^256 in LDS.  Wave w takes the 4,096 positions from
+// p_lo + 4,096 w up, 256 at a time from the top down: four slots of 64
+// lanes, a Horner chain W_i <- W_i G ^ X_r per slot and lane.  A step of 256
+// whole ciphertext blocks is a counter-mode chunk as in the single-buffer
+// kernel (load, encrypt, store, hash the ciphertext); any other step goes
+// one slot at a time (the length block, partial blocks, additional data,
+// positions past the end).  After the loop the AES tables' space holds the
+// eleven folding tables: the slots with H^64, the lanes with H, H^2 .. H^32,
+// the waves with H^4096 .. H^32768; the workgroup's sum times H^(p_lo + 1)
+// is XORed into the message's sum (GHASH is linear), and the AES tables are
+// staged again for the next piece.
+constexpr uint32_t kFusedAesBytes = 128u * 1024u;
+constexpr uint32_t kFusedGTab = kFusedAesBytes;              // G's table, after the AES tables
+constexpr uint32_t kFusedPartials = kFusedGTab + kTabBytes;  // the waves' sums
+constexpr uint32_t kFusedLdsWords = (kFusedPartials + 16u * kBatchWavesPerGroup) / 4u;
+constexpr int kFusedFoldTabs = 11;
+constexpr uint64_t kFusedWavePositions = kFusedPiece / kBatchWavesPerGroup;
+constexpr int kFusedWaveSteps = int(kFusedWavePositions / 256);
+static_assert(kFusedFoldTabs * kTabBytes <= kFusedAesBytes, "the folding tables fit the AES tables' space");
+static_assert(kFusedWavePositions == 4096, "the waves' folding tables are H^4096 .. H^32768");
+
+// Piece `piece` of fused GCM message `msg`, by the whole workgroup; the AES
+// tables are staged, and G's table is built here when build_g.  Ends with a
+// barrier (the next piece stages the tables again).
+template <int NR>
+__device__ __forceinline__ void fused_piece(uint32_t *lds, const LaneConsts &lc, const BatchKArgs &a, uint32_t msg,
+                                            uint64_t piece, bool build_g) {
+    const uint32_t lane = threadIdx.x & 63u, wv = uniform32(threadIdx.x >> 6);
+    // the message's fields, the same in every lane: kept in scalar registers
+    const aes_msg_desc &d = a.desc[msg];
+    const aes_gcm_desc &g = a.gcm[msg];
+    const bool dec = uniform32(d.decrypt) != 0;
+    const uint64_t cbytes = uniform64(d.nbytes), abytes = uniform64(g.aad_bytes);
+    const uint64_t nC = (cbytes + 15) >> 4, nA = (abytes + 15) >> 4, npos = nC + nA + 1;
+    const uint64_t nCw = cbytes >> 4, nAw = abytes >> 4;
+    const uint32_t ctail = uint32_t(cbytes & 15u), atail = uint32_t(abytes & 15u);
+    const uint8_t *in = static_cast<const uint8_t *>(a.in_base) + uniform64(d.in_off);
+    uint8_t *out = static_cast<uint8_t *>(a.out_base) + uniform64(d.out_off);
+    const uint8_t *aad = static_cast<const uint8_t *>(a.in_base) + uniform64(g.aad_off);
+    uint32_t *slot = a.keytab + size_t(msg) * kKeySlotWords;
+    uint32_t rk[4 * (NR + 1)];
+    load_round_keys<NR>(slot, rk);
+    const uint32_t h[4] = {uniform32(slot[kGcmSlotH]), uniform32(slot[kGcmSlotH + 1]), uniform32(slot[kGcmSlotH + 2]),
+                           uniform32(slot[kGcmSlotH + 3])};
+    uint64_t hlo, hhi;
+    to_poly(h, hlo, hhi);
+    const u32x4 pows = *reinterpret_cast<const u32x4 *>(
+        slot + kGcmSlotPow + 4 * (lane < uint32_t(kGcmSlotPowers) ? lane : 0u));
+    if (build_g && wv == 0) {
+        uint64_t glo = hlo, ghi = hhi;
+        for (int t = 0; t < 8; t++)
+            gf_square(glo, ghi);
+        uint32_t gw[4];
+        from_poly(glo, ghi, gw);
+        build_table_wave(lds, kFusedGTab, gw);
+    }
+    __syncthreads();   // the AES tables (staged by the caller) and G's
+
+    // counter blocks: IV || BE32(2 + j) for ciphertext block j (J0 + 1 + j)
+    const uint32_t n0 = uniform32(le32(d.ctr0)) ^ rk[0], n1 = uniform32(le32(d.ctr0 + 4)) ^ rk[1],
+                   n2 = uniform32(le32(d.ctr0 + 8)) ^ rk[2];
+    const uint32_t pre0 = tl<LAYOUT_T4X32, 0, 0>(lds, lc, n0) ^ tl<LAYOUT_T4X32, 1, 1>(lds, lc, n1) ^
+                          tl<LAYOUT_T4X32, 2, 2>(lds, lc, n2) ^ rk[4];
+    const uint32_t pre1 = tl<LAYOUT_T4X32, 0, 0>(lds, lc, n1) ^ tl<LAYOUT_T4X32, 1, 1>(lds, lc, n2) ^
+                          tl<LAYOUT_T4X32, 3, 3>(lds, lc, n0) ^ rk[5];
+    const uint32_t pre2 = tl<LAYOUT_T4X32, 0, 0>(lds, lc, n2) ^ tl<LAYOUT_T4X32, 2, 2>(lds, lc, n0) ^
+                          tl<LAYOUT_T4X32, 3, 3>(lds, lc, n1) ^ rk[6];
+    const uint32_t pre3 = tl<LAYOUT_T4X32, 1, 1>(lds, lc, n0) ^ tl<LAYOUT_T4X32, 2, 2>(lds, lc, n1) ^
+                          tl<LAYOUT_T4X32, 3, 3>(lds, lc, n2) ^ rk[7];
+    const uint64_t abits = 8 * abytes, cbits = 8 * cbytes;
+    const u32x4 lenblk = vec4(__builtin_bswap32(uint32_t(abits >> 32)), __builtin_bswap32(uint32_t(abits)),
+                              __builtin_bswap32(uint32_t(cbits >> 32)), __builtin_bswap32(uint32_t(cbits)));
+    uint32_t tmask[4];   // bytes of a partial last ciphertext block that enter GHASH
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const int keep = int(ctail) - 4 * c;
+        tmask[c] = keep >= 4 ? ~0u : keep <= 0 ? 0u : (1u << (8 * keep)) - 1u;
+    }
+
+    uint32_t W[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        W[i][0] = W[i][1] = W[i][2] = W[i][3] = 0;
+    // Steps of 256 whole ciphertext blocks: the blocks from `low` up, slot i
+    // lane l taking block low + 64 (3 - i) + 63 - l (position rq + 64 i + l).
+    auto fast_step = [&](uint64_t rq) __attribute__((always_inline)) {
+        const uint64_t low = nC - rq - 255;
+        uint32_t x[4][4], s[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const u32x4 v = load16(in + 16 * (low + 64u * uint32_t(3 - i) + (63u - lane)));
+            x[i][0] = v.x;
+            x[i][1] = v.y;
+            x[i][2] = v.z;
+            x[i][3] = v.w;
+        }
+        // rounds 1 and 2: the 256 counters have at most two values of their
+        // top 24 bits (A below a multiple of 256, B from it on); the 15
+        // lookups that depend only on those bits are done for both
+        const uint32_t cb = 2u + uint32_t(low);
+        auto shared = [&](uint32_t g3, uint32_t (&qv)[4]) __attribute__((always_inline)) {
+            const uint32_t t1 = pre1 ^ tl<LAYOUT_T4X32, 2, 2>(lds, lc, g3);
+            const uint32_t t2 = pre2 ^ tl<LAYOUT_T4X32, 1, 1>(lds, lc, g3);
+            const uint32_t t3 = pre3 ^ tl<LAYOUT_T4X32, 0, 0>(lds, lc, g3);
+            qv[0] = xor3(tl<LAYOUT_T4X32, 1, 1>(lds, lc, t1), tl<LAYOUT_T4X32, 2, 2>(lds, lc, t2),
+                         tl<LAYOUT_T4X32, 3, 3>(lds, lc, t3)) ^ rk[8];
+            qv[1] = xor3(tl<LAYOUT_T4X32, 0, 0>(lds, lc, t1), tl<LAYOUT_T4X32, 1, 1>(lds, lc, t2),
+                         tl<LAYOUT_T4X32, 2, 2>(lds, lc, t3)) ^ rk[9];
+            qv[2] = xor3(tl<LAYOUT_T4X32, 0, 0>(lds, lc, t2), tl<LAYOUT_T4X32, 1, 1>(lds, lc, t3),
+                         tl<LAYOUT_T4X32, 3, 3>(lds, lc, t1)) ^ rk[10];
+            qv[3] = xor3(tl<LAYOUT_T4X32, 0, 0>(lds, lc, t3), tl<LAYOUT_T4X32, 2, 2>(lds, lc, t1),
+                         tl<LAYOUT_T4X32, 3, 3>(lds, lc, t2)) ^ rk[11];
+        };
+        uint32_t qa[4], qb[4];
+        shared(__builtin_bswap32(cb) ^ rk[3], qa);
+        shared(__builtin_bswap32(cb + 256u) ^ rk[3], qb);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint32_t jj = 64u * uint32_t(3 - i) + (63u - lane);
+            const bool b = (cb & 255u) + jj >= 256u;
+            const uint32_t v3 = __builtin_bswap32(cb + jj) ^ rk[3];
+            const uint32_t t0 = pre0 ^ tl<LAYOUT_T4X32, 3, 3>(lds, lc, v3);
+            s[i][0] = (b ? qb[0] : qa[0]) ^ tl<LAYOUT_T4X32, 0, 0>(lds, lc, t0);
+            s[i][1] = (b ? qb[1] : qa[1]) ^ tl<LAYOUT_T4X32, 3, 3>(lds, lc, t0);
+            s[i][2] = (b ? qb[2] : qa[2]) ^ tl<LAYOUT_T4X32, 2, 2>(lds, lc, t0);
+            s[i][3] = (b ? qb[3] : qa[3]) ^ tl<LAYOUT_T4X32, 1, 1>(lds, lc, t0);
+        }
+        rounds<NR, DIR_ENC, LAYOUT_T4X32, 4>(s, lds, lc, rk, 3);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint32_t o[4] = {x[i][0] ^ s[i][0], x[i][1] ^ s[i][1], x[i][2] ^ s[i][2], x[i][3] ^ s[i][3]};
+            store16(out + 16 * (low + 64u * uint32_t(3 - i) + (63u - lane)), vec4(o[0], o[1], o[2], o[3]));
+            uint32_t t[4];
+            mul_tab(lds, kFusedGTab, W[i], t);
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                W[i][c] = t[c] ^ (dec ? x[i][c] : o[c]);
+        }
+    };
+    // Any other step, one slot at a time.
+    auto slow_step = [&](uint64_t rq) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint64_t r = rq + 64u * uint32_t(i) + lane;
+            const bool is_c = r >= 1 && r <= nC;
+            const uint64_t j = nC - r;
+            u32x4 v = vec4(0, 0, 0, 0);
+            if (r == 0) {
+                v = lenblk;
+            } else if (is_c) {
+                v = j < nCw ? load16(in + 16 * j) : load_tail(in + 16 * j, ctail);
+            } else if (r < npos) {
+                const uint64_t k = nC + nA - r;
+                v = k < nAw ? load16(aad + 16 * k) : load_tail(aad + 16 * k, atail);
+            }
+            uint32_t x[4] = {v.x, v.y, v.z, v.w};
+            uint32_t st[1][4] = {{n0, n1, n2, __builtin_bswap32(2u + uint32_t(j)) ^ rk[3]}};
+            rounds<NR, DIR_ENC, LAYOUT_T4X32, 1>(st, lds, lc, rk, 1);
+            if (is_c) {
+                const uint32_t o[4] = {x[0] ^ st[0][0], x[1] ^ st[0][1], x[2] ^ st[0][2], x[3] ^ st[0][3]};
+                const bool whole = j < nCw;
+                if (whole)
+                    store16(out + 16 * j, vec4(o[0], o[1], o[2], o[3]));
+                else
+                    store_tail(out + 16 * j, vec4(o[0], o[1], o[2], o[3]), ctail);
+                if (!dec)
+#pragma unroll
+                    for (int c = 0; c < 4; c++)
+                        x[c] = whole ? o[c] : o[c] & tmask[c];
+            }
+            uint32_t t[4];
+            mul_tab(lds, kFusedGTab, W[i], t);
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                W[i][c] = t[c] ^ x[c];
+            asm volatile("" ::: "memory");   // one slot's work at a time
+        }
+    };
+    const uint64_t p_lo = piece * kFusedPiece;
+    const uint64_t w_lo = p_lo + uint64_t(wv) * kFusedWavePositions;
+    for (int st = kFusedWaveSteps - 1; st >= 0; st--) {
+        const uint64_t rq = w_lo + 256u * uint32_t(st);
+        if (rq >= npos)
+            continue;   // past the end: the chains are still zero
+        if (rq >= 2 && rq + 255 <= nC)
+            fast_step(rq);
+        else
+            slow_step(rq);
+    }
+
+    // fold: tables k < 6 hold H^(2^k), table 6 H^64, tables 7 .. 10 H^(4096 2^(k-7))
+    __syncthreads();   // every wave is done with the AES tables
+    if (wv < uint32_t(kFusedFoldTabs)) {
+        const int e = wv < 7 ? int(wv) : int(wv) + 5;
+        uint64_t lo = hlo, hi = hhi;
+        for (int t = 0; t < e; t++)
+            gf_square(lo, hi);
+        uint32_t mw[4];
+        from_poly(lo, hi, mw);
+        build_table_wave(lds, wv * kTabBytes, mw);
+    }
+    __syncthreads();
+    uint32_t u[4] = {W[3][0], W[3][1], W[3][2], W[3][3]};
+#pragma unroll
+    for (int i = 2; i >= 0; i--) {
+        mul_tab(lds, 6 * kTabBytes, u, u);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            u[c] ^= W[i][c];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        uint32_t v[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            v[c] = uint32_t(__shfl_down(int(u[c]), 1u << k, 64));
+        mul_tab(lds, uint32_t(k) * kTabBytes, v, v);
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            u[c] ^= v[c];
+    }
+    if (lane == 0)
+        lds_store16(lds, kFusedPartials + 16u * wv, vec4(u[0], u[1], u[2], u[3]));
+    __syncthreads();
+    if (wv == 0) {
+        const u32x4 pv = lane < uint32_t(kBatchWavesPerGroup) ? lds_load16(lds, kFusedPartials + 16u * lane)
+                                                              : vec4(0, 0, 0, 0);
+        uint32_t y[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            uint32_t v[4];
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                v[c] = uint32_t(__shfl_down(int(y[c]), 1u << k, 64));
+            mul_tab(lds, uint32_t(7 + k) * kTabBytes, v, v);
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                y[c] ^= v[c];
+        }
+        // times H^(p_lo + 1): H, times the stored powers H^(4096 2^t) over
+        // the set bits t of p_lo / 4096 (= 16 piece)
+        const uint32_t s0[4] = {uniform32(y[0]), uniform32(y[1]), uniform32(y[2]), uniform32(y[3])};
+        uint64_t rlo, rhi, blo = 0, bhi = 0;
+        to_poly(s0, rlo, rhi);
+        mul_wave(rlo, rhi, hlo, hhi, rlo, rhi);
+        const uint64_t idx = p_lo >> kGhashPieceLog2;
+        for (int t = 0; (idx >> t) != 0; t++) {
+            if (t < kGcmSlotPowers) {
+                const uint32_t pw[4] = {uint32_t(__builtin_amdgcn_readlane(int(pows.x), t)),
+                                        uint32_t(__builtin_amdgcn_readlane(int(pows.y), t)),
+                                        uint32_t(__builtin_amdgcn_readlane(int(pows.z), t)),
+                                        uint32_t(__builtin_amdgcn_readlane(int(pows.w), t))};
+                to_poly(pw, blo, bhi);
+            } else {
+                gf_square(blo, bhi);
+            }
+            if ((idx >> t) & 1)
+                mul_wave(rlo, rhi, blo, bhi, rlo, rhi);
+        }
+        uint32_t res[4];
+        from_poly(rlo, rhi, res);
+        if (lane == 0) {
+            unsigned long long *sum = reinterpret_cast<unsigned long long *>(slot + kGcmSlotSum);
+            atomicXor(sum, (unsigned long long)res[0] | ((unsigned long long)res[1] << 32));
+            atomicXor(sum + 1, (unsigned long long)res[2] | ((unsigned long long)res[3] << 32));
+        }
+    }
+    __syncthreads();   // the folding tables are read until here
+}
+
+// Persistent, one kernel per key size (one instantiation of the piece each,
+// which keeps its registers within four waves per SIMD): every workgroup
+// takes the pieces of that key size's messages off a counter, one at a time,
+// until none is left.
+template <int NR>
+__global__ __launch_bounds__(kBatchWavesPerGroup * 64) void gcm_fused_kernel(const BatchKArgs a) {
+    constexpr int J = (NR - 10) / 2;
+    const uint32_t n = a.header->nfused[J];
+    if (n == 0)
+        return;
+    const uint64_t total = a.header->fused_pieces[J];
+    __shared__ uint32_t lds[kFusedLdsWords];
+    __shared__ uint64_t next_piece;
+    const uint32_t lane = threadIdx.x & 63u;
+    const LaneConsts lc = lane_consts<LAYOUT_T4X32>(lane);
+    const uint32_t off = (J > 0 ? a.header->nfused[0] : 0u) + (J > 1 ? a.header->nfused[1] : 0u);
+    const BatchItem *list = a.items + size_t(4) * a.max_msgs + off;
+    uint32_t have_g = 0xFFFFFFFFu;   // the message whose G table is in LDS
+    for (;;) {
+        if (threadIdx.x == 0)
+            next_piece = atomicAdd(reinterpret_cast<unsigned long long *>(&a.header->next_fused[J]), 1ull);
+        __syncthreads();
+        const uint64_t p = next_piece;
+        if (p >= total)
+            break;
+        stage_tables<LAYOUT_T4X32, DIR_ENC>(lds);
+        const uint32_t i = uniform32(find_item(list, n, p));
+        const uint32_t msg = uniform32(list[i].msg);
+        const uint64_t piece = p - uniform64(list[i].start);
+        const bool build_g = msg != have_g;
+        have_g = msg;
+        fused_piece<NR>(lds, lc, a, msg, piece, build_g);
+    }
+}
+
 // One lane per message: every GCM message's tag, Cipher_K(J0) XOR its GHASH
 // sum, written after its output (encryption) or compared with the expected
 // one (decryption); the verdict goes to the message's aes_gcm_desc.
@@ -1420,6 +1775,14 @@ hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsig
     }
     // GCM: the hash reads the ciphertext the forward kernel has written
     if (lists & 8u) {
+        if (lists & 16u) {
+            for (BatchFn fused : {gcm_fused_kernel<10>, gcm_fused_kernel<12>, gcm_fused_kernel<14>}) {
+                hipLaunchKernelGGL(fused, dim3(grid), dim3(kBatchWavesPerGroup * 64), 0, stream, a);
+                e = hipGetLastError();
+                if (e != hipSuccess)
+                    return e;
+            }
+        }
         hipLaunchKernelGGL(ghash_kernel, dim3(grid), dim3(kGhashWavesPerGroup * 64), 0, stream, a);
         e = hipGetLastError();
         if (e != hipSuccess)

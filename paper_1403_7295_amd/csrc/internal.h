@@ -140,7 +140,11 @@ struct BatchHeader {
     uint32_t pad0;
     uint64_t gcm_pieces;  // GHASH pieces of all of them
     uint32_t nlane;       // GCM messages hashed one per lane (the back of the GHASH list)
-    uint32_t pad[45];
+    uint32_t nfused[3];       // GCM messages encrypted and hashed in one pass (the fused
+                              // list), per key size (128, 192, 256 bits)
+    uint64_t fused_pieces[3];  // their pieces, per key size
+    uint64_t next_fused[3];   // next piece of each key size handed out from the counter
+    uint32_t pad[30];
 };
 static_assert(sizeof(BatchHeader) == 256, "header is one 256-byte line");
 
@@ -148,7 +152,9 @@ static_assert(sizeof(BatchHeader) == 256, "header is one 256-byte line");
 // the messages before it in the list.  Serial list: count = its blocks.
 // GHASH list: start = the pieces of the messages before it, count = its own;
 // the messages hashed one per lane fill the same array from its end (entry
-// max_msgs - 1 - i is the i-th of them).
+// max_msgs - 1 - i is the i-th of them).  Fused list: the 128-bit keys'
+// messages, then the 192-bit and the 256-bit ones, start = the pieces of the
+// messages before it with the same key size.
 struct BatchItem {
     uint32_t msg;     // message index
     uint32_t count;
@@ -174,6 +180,13 @@ constexpr uint64_t kGhashPiece = uint64_t(1) << kGhashPieceLog2;
 // Horner recurrence, per-lane tables) instead of a wave per piece.
 constexpr uint64_t kLaneGhashMaxPositions = 512;
 constexpr uint64_t kLaneGhashMinMessages = 32768;
+// GCM messages of at least kFusedMinPositions positions are encrypted and
+// hashed in one pass (the fused list) in pieces of kFusedPiece positions, one
+// workgroup per piece, instead of a counter-mode pass and a hash pass that
+// reads the ciphertext again.
+constexpr int kFusedPieceLog2 = 16;
+constexpr uint64_t kFusedPiece = uint64_t(1) << kFusedPieceLog2;
+constexpr uint64_t kFusedMinPositions = 2 * kFusedPiece;
 // A wave's share of a message starts and ends on a multiple of this many
 // blocks by default (four steps of the block loop, 64 lanes x 2 blocks; the
 // best of 128 .. 1024 over batch sizes from one message to gigabytes).  The
@@ -186,8 +199,8 @@ constexpr int kBatchWavesPerGroup = 16;
 // Messages per chunk of the plan (one workgroup of the prep and plan
 // kernels), and the plan's counters per chunk.
 constexpr int kBatchChunk = 256;
-constexpr int kBatchChunkCounters = 9;
-constexpr int kBatchLists = 4;   // forward, inverse, serial, GHASH
+constexpr int kBatchChunkCounters = 15;
+constexpr int kBatchLists = 5;   // forward, inverse, serial, GHASH, fused GCM
 
 struct BatchKArgs {
     const aes_msg_desc *desc;
@@ -253,7 +266,8 @@ constexpr size_t kNoAllocScratchBytes = batch_layout(AES_BATCH_NOALLOC_MAX_MSGS)
 hipError_t init_batch_scratch(int dev);
 void *batch_scratch(int dev);
 // lists: bit k set if list k may hold messages (bit 0 forward, 1 inverse, 2
-// serial, 3 GCM: the GHASH and tag kernels); a kernel whose lists are all
+// serial, 3 GCM: the GHASH and tag kernels, 4 GCM messages of at least
+// kFusedMinPositions positions: the fused kernels); a kernel whose lists are all
 // known to be empty is not launched.  max_count: a bound on the message count known to the caller
 // (at most max_msgs); up to one chunk, Key Expansion and the plan run as one
 // launch.  Key Expansion and the plan always run.

@@ -165,6 +165,9 @@ struct Loop {
                 g[k].tag_bytes = 16;
                 g[k].ok = -1;
                 lists |= 8u;
+                // long enough for the fused kernels (GHASH positions: the data and the length block)
+                if ((q.nbytes + 15) / 16 + 1 >= kFusedMinPositions)
+                    lists |= 16u;
             }
         }
         h->nmsg = n;

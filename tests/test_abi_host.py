@@ -167,12 +167,12 @@ def test_launch_config_validation(A):
 
 
 def test_batch_workspace_size(A):
-    # header + key slots of 512 bytes + four lists of 16-byte items (forward,
-    # inverse, serial, GHASH) + the plan's nine 8-byte counters per chunk of
-    # 256 messages
-    assert A.aes_batch_workspace_size(10) == 256 + 10 * 512 + 4 * 10 * 16 + 72
-    assert A.aes_batch_workspace_size(1) == 256 + 512 + 4 * 16 + 72
-    assert A.aes_batch_workspace_size(257) == 256 + 257 * 512 + 4 * 257 * 16 + 2 * 72
+    # header + key slots of 512 bytes + five lists of 16-byte items (forward,
+    # inverse, serial, GHASH, fused GCM) + the plan's fifteen 8-byte counters
+    # per chunk of 256 messages
+    assert A.aes_batch_workspace_size(10) == 256 + 10 * 512 + 5 * 10 * 16 + 120
+    assert A.aes_batch_workspace_size(1) == 256 + 512 + 5 * 16 + 120
+    assert A.aes_batch_workspace_size(257) == 256 + 257 * 512 + 5 * 257 * 16 + 2 * 120
     for bad in (0, -3):
         with pytest.raises(A.AESError) as e:
             A.aes_batch_workspace_size(bad)

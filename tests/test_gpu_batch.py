@@ -404,7 +404,7 @@ def test_sector_batch_full_size_sampled(A, O):
 
 
 # --- GCM messages in a batch -------------------------------------------------
-def gcm_batch(A, O, n, seed, max_len=1 << 16, big=(), n_other=0, big_aad=None):
+def gcm_batch(A, O, n, seed, max_len=1 << 16, big=(), n_other=0, big_aad=None, big_bits=None):
     """n GCM messages (and n_other CTR/ECB ones), 128/192/256-bit keys,
     lengths log-uniform up to max_len plus the lengths in `big`, additional
     data of 0 .. 1000 bytes (larger for the big ones), half encryptions and
@@ -417,6 +417,8 @@ def gcm_batch(A, O, n, seed, max_len=1 << 16, big=(), n_other=0, big_aad=None):
     n = len(lens)
     lens[0] = 0
     keybits = rng.choice([128, 192, 256], n + n_other)
+    if big_bits is not None:
+        keybits[n - len(big):n] = big_bits
     dec = rng.integers(0, 2, n)
     aadl = rng.integers(0, 1001, n)
     aadl[1] = 0
@@ -562,6 +564,34 @@ def test_gcm_batch_piece_boundaries(A, O):
     b = A.Batch(descs, keys, xd, yd, gcm=g)
     b.run()
     assert b.query() == (len(descs), 0)
+    check_gcm_batch(A, O, b, descs, keys, x, yd.cpu().numpy(), want, n, b.gcm_results(len(descs)))
+    b.close()
+
+
+def test_gcm_batch_fused_messages(A, O):
+    """GCM messages of at least 2 x 65,536 GHASH positions (about 2 MiB) are
+    encrypted and hashed in one pass, one workgroup per piece of 65,536
+    positions: messages at the threshold and one short of it, partial last
+    blocks, additional data long enough to fill slow steps, every key size,
+    both directions and forged tags, beside short GCM messages and other
+    modes in the same batch, against the oracle; then a graph replay."""
+    K = 65536
+    big = [16 * (2 * K - 1), 16 * (2 * K - 1) - 1, 16 * (2 * K - 2), 16 * (3 * K) + 5, 16 * (2 * K + 37) + 9,
+           16 * (2 * K) + 1]
+    big_aad = [0, 0, 0, 16 * 100 + 3, 70000, 17]
+    big_bits = [128, 192, 256, 256, 128, 192]
+    descs, keys, g, x, want, n = gcm_batch(A, O, 30, 83, max_len=1 << 14, big=big, n_other=12, big_aad=big_aad,
+                                           big_bits=big_bits)
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.zeros_like(xd)
+    b = A.Batch(descs, keys, xd, yd, gcm=g)
+    b.run()
+    assert b.query() == (len(descs), 0)
+    check_gcm_batch(A, O, b, descs, keys, x, yd.cpu().numpy(), want, n, b.gcm_results(len(descs)))
+    yd.zero_()
+    b.launch_graph()
+    b.launch_graph()
+    torch.cuda.synchronize()
     check_gcm_batch(A, O, b, descs, keys, x, yd.cpu().numpy(), want, n, b.gcm_results(len(descs)))
     b.close()
 
