@@ -346,10 +346,6 @@ __device__ __forceinline__ uint64_t mul_div_floor(uint64_t a, uint64_t b, uint64
     return uint64_t((unsigned __int128)a * b / c);
 }
 
-// Whether a valid GCM message goes to the fused list.
-__device__ __forceinline__ bool gcm_fused(const aes_msg_desc &d, const aes_gcm_desc &g) {
-    return d.mode == AES_MODE_GCM && ghash_positions(d, g) >= kFusedMinPositions;
-}
 
 // One message's contribution to the plan's counters (all zero past the
 // batch's end).  fused: a GCM message of the fused list, in no other list.
@@ -371,7 +367,7 @@ __device__ __forceinline__ void message_counts(const BatchKArgs &a, uint32_t m, 
     k = desc_class(d);
     if (d.mode == AES_MODE_GCM) {
         const uint64_t npos = ghash_positions(d, a.gcm[m]);
-        fused = npos >= kFusedMinPositions;
+        fused = a.fuse_gcm && npos >= kFusedMinPositions;
         if (fused) {
             const uint64_t pieces = (npos + kFusedPiece - 1) / kFusedPiece;
 #pragma unroll
@@ -427,7 +423,7 @@ __device__ __forceinline__ void gcm_item(const BatchKArgs &a, uint32_t m, const 
     if (d.mode != AES_MODE_GCM)
         return;
     const uint64_t npos = ghash_positions(d, a.gcm[m]);
-    if (npos >= kFusedMinPositions) {
+    if (a.fuse_gcm && npos >= kFusedMinPositions) {
         // after the messages of the smaller key sizes
         const int j = int(d.keybits_code);
         const uint64_t off = (j > 0 ? total[kFusedMsgs] : 0) + (j > 1 ? total[kFusedMsgs + 1] : 0);
@@ -1739,9 +1735,11 @@ hipError_t launch_stage(const void *host_dev, void *dev, uint64_t nbytes, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchKArgs &a, int grid, hipStream_t stream, unsigned lists, int max_count) {
+hipError_t launch_batch(const BatchKArgs &args, int grid, hipStream_t stream, unsigned lists, int max_count) {
     if (grid < 1 || grid * kBatchWavesPerGroup > kBatchMaxWaves)
         return hipErrorInvalidConfiguration;
+    BatchKArgs a = args;
+    a.fuse_gcm = (lists & 16u) ? 1u : 0u;
     hipError_t e;
     if (uint64_t(max_count) <= uint64_t(kPlanThreads)) {
         hipLaunchKernelGGL(prep_plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, a);

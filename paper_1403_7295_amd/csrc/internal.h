@@ -224,6 +224,8 @@ struct BatchKArgs {
                              // caller clears them; the request loop points
                              // this at pinned host memory)
     aes_gcm_desc *gcm;       // NULL, or the GCM fields per message
+    uint32_t fuse_gcm;       // 1: GCM messages of at least kFusedMinPositions positions go to
+                             // the fused list (set by launch_batch from its lists argument)
 };
 
 // Synthetic payloads of the request loop (batch_kernels.hip).
@@ -266,8 +268,9 @@ constexpr size_t kNoAllocScratchBytes = batch_layout(AES_BATCH_NOALLOC_MAX_MSGS)
 hipError_t init_batch_scratch(int dev);
 void *batch_scratch(int dev);
 // lists: bit k set if list k may hold messages (bit 0 forward, 1 inverse, 2
-// serial, 3 GCM: the GHASH and tag kernels, 4 GCM messages of at least
-// kFusedMinPositions positions: the fused kernels); a kernel whose lists are all
+// serial, 3 GCM: the GHASH and tag kernels, 4 the fused list: GCM messages
+// of at least kFusedMinPositions positions are encrypted and hashed in one
+// pass, else in the forward and GHASH lists); a kernel whose lists are all
 // known to be empty is not launched.  max_count: a bound on the message count known to the caller
 // (at most max_msgs); up to one chunk, Key Expansion and the plan run as one
 // launch.  Key Expansion and the plan always run.

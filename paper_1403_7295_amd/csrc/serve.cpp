@@ -135,7 +135,10 @@ struct Loop {
         FillDesc *f = reinterpret_cast<FillDesc *>(s.host + L.fill_off);
         aes_gcm_desc *g = reinterpret_cast<aes_gcm_desc *>(s.host + L.gcm_off);
         uint64_t chunks = 0;
-        unsigned lists = 0;   // the batch kernel's lists this batch uses
+        // the batch kernel's lists this batch uses; never the fused GCM list:
+        // its pieces hold a workgroup for ~0.3 ms each, which lengthened the
+        // loop's tail latency without adding measurably to its capacity
+        unsigned lists = 0;
         for (int k = 0; k < n; k++) {
             const aes_request &q = reqs[s.reqs[k]];
             const aes_request_result &r = res[s.reqs[k]];
@@ -165,9 +168,6 @@ struct Loop {
                 g[k].tag_bytes = 16;
                 g[k].ok = -1;
                 lists |= 8u;
-                // long enough for the fused kernels (GHASH positions: the data and the length block)
-                if ((q.nbytes + 15) / 16 + 1 >= kFusedMinPositions)
-                    lists |= 16u;
             }
         }
         h->nmsg = n;

@@ -222,3 +222,44 @@ def test_served_gcm_requests_match_the_oracle(A):
             assert np.array_equal(got, ct), "request %d ciphertext" % i
             assert np.array_equal(srv.tag(res[i], n).cpu().numpy(), tag), "request %d tag" % i
             assert res["authentic"][i] == 1
+
+
+def test_served_gcm_long_requests(A):
+    """Long GCM requests (6 .. 16 MiB, hundreds of MiB per batch, GHASH in
+    thousands of pieces): every result equals the single-buffer GCM call on
+    the same payload (ciphertext and tag, or plaintext and the refusal of the
+    random tag that follows the payload), a separate implementation checked
+    against the oracle elsewhere."""
+    r, keys = requests(A, 48, rate=1e6, seed=59, lo=6 << 20, hi=16 << 20)
+    r["mode"] = A.AES_MODE_GCM
+    fp = 2 * ((r["nbytes"].astype(np.int64) + 16 + 255) // 256 * 256)
+    cfg = A.serve_cfg(streams=2, budget_bytes=int(fp.sum()) + (1 << 20), max_batch_msgs=64)
+    srv = A.Server(keys, cfg)
+    res, st = srv.run(r)
+    torch.cuda.synchronize()
+    assert st["completed"] == len(r)
+    assert (res["status"] == A.AES_OK).all() and not res["overwritten"].any()
+    ws = torch.empty(A.aes_gcm_workspace_size(), dtype=torch.uint8, device="cuda")
+    tag = torch.empty(16, dtype=torch.uint8, device="cuda")
+    ok = torch.empty(1, dtype=torch.int32, device="cuda")
+    aad = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    for i, q in enumerate(r):
+        n = int(q["nbytes"])
+        pad = (n + 15) // 16 * 16
+        bits = 128 + 64 * int(q["keybits_code"])
+        rk, nr = A.aes_expand_key(keys[i][:bits // 8])
+        iv = q["ctr0"][:12]
+        src = seedgen.bytes_torch(int(q["payload_seed"]), pad + 16, "cuda")
+        want = torch.empty(n, dtype=torch.uint8, device="cuda")
+        got = srv.output(res[i], n)
+        if q["decrypt"]:
+            A.aes_gcm_decrypt(src[:n], want, n, aad, 0, rk, nr, iv, src[pad:pad + 16], 16, ok, ws)
+            torch.cuda.synchronize()
+            assert torch.equal(got, want), "request %d plaintext" % i
+            assert res["authentic"][i] == int(ok.item()) == 0, "request %d verdict" % i
+        else:
+            A.aes_gcm_encrypt(src[:n], want, n, aad, 0, rk, nr, iv, tag, ws)
+            torch.cuda.synchronize()
+            assert torch.equal(got, want), "request %d ciphertext" % i
+            assert torch.equal(srv.tag(res[i], n), tag), "request %d tag" % i
+            assert res["authentic"][i] == 1
