@@ -385,6 +385,13 @@ typedef struct {
  *   blocks_per_thread  16-byte blocks each lane carries through the rounds
  *                    at once in the parallel lists, 2 or 4; 0 = library
  *                    choice (4).  (XTS pieces always carry 2.)
+ *   gcm_two_pass     0: GCM messages of at least 131,072 GHASH blocks are
+ *                    encrypted and hashed in one pass (the kernels for it
+ *                    are launched whenever gcm is set); nonzero: every GCM
+ *                    message takes the counter-mode pass and the hash pass,
+ *                    and those kernels are not launched (a caller that
+ *                    knows its batches hold no such message saves their
+ *                    launches; the results are the same either way).
  * The sequence is: on-device Key Expansion for every message (FIPS-197
  * section 5.2; the decryption schedule of section 5.3.5 where needed) and a
  * plan that puts the messages in three lists (encryption tables, inverse
@@ -419,6 +426,7 @@ typedef struct {
     int tile_blocks;
     aes_gcm_desc *gcm;
     int blocks_per_thread;
+    int gcm_two_pass;
 } aes_batch;
 
 /* Workspace bytes for batches of up to max_msgs messages (any lengths).

@@ -127,7 +127,7 @@ class aes_batch(ctypes.Structure):
                 ("out_base", ctypes.c_void_p), ("out_bytes", ctypes.c_uint64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("max_msgs", ctypes.c_int), ("tile_blocks", ctypes.c_int), ("gcm", ctypes.c_void_p),
-                ("blocks_per_thread", ctypes.c_int)]
+                ("blocks_per_thread", ctypes.c_int), ("gcm_two_pass", ctypes.c_int)]
 
 
 # aes_request and aes_request_result, as numpy records
@@ -508,6 +508,23 @@ def xts_ctr0(first_unit, key2_idx, unit_bytes):
                          int(unit_bytes).to_bytes(4, "little"), dtype=np.uint8).copy()
 
 
+# GCM messages of at least this many GHASH blocks (additional data,
+# ciphertext, the length block) can take the library's one-pass kernels
+GCM_ONE_PASS_MIN_BLOCKS = 2 * 65536
+
+
+def _has_long_gcm(descs, gcm):
+    """Whether a GCM descriptor is long enough for the one-pass kernels
+    (additional data counted when its fields are given)."""
+    m = descs["mode"] == AES_MODE_GCM
+    if not m.any():
+        return False
+    pos = (descs["nbytes"][m].astype(np.uint64) + 15) // 16 + 1
+    if gcm is not None:
+        pos = pos + (np.asarray(gcm["aad_bytes"])[m].astype(np.uint64) + 15) // 16
+    return bool((pos >= GCM_ONE_PASS_MIN_BLOCKS).any())
+
+
 class Batch:
     """A batch of messages on the device: descriptors, keys and workspace held
     in torch tensors (torch supplies the memory), run through
@@ -521,7 +538,7 @@ class Batch:
     """
 
     def __init__(self, descs, keys, inp, out, tile_blocks=0, max_msgs=None, device=None, gcm=None,
-                 blocks_per_thread=0):
+                 blocks_per_thread=0, gcm_two_pass=None):
         import torch
         self.device = device or inp.device
         _dev((inp, 0, "inp"), (out, 0, "out"))
@@ -548,6 +565,9 @@ class Batch:
         if gcm is not None:
             self.d_gcm = torch.zeros(self.max_msgs * GCM_DESC_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
             self.c.gcm = self.d_gcm.data_ptr()
+        # None: two passes for every GCM message unless the descriptors hold
+        # one long enough for the one-pass kernels (a launch choice only)
+        self.gcm_two_pass = gcm_two_pass
         self.graph = None
         self.set_descs(descs, gcm=gcm)
 
@@ -569,6 +589,10 @@ class Batch:
         self.d_desc[:raw.numel()].copy_(raw)
         self.d_nmsg.fill_(len(descs))
         self.c.nmsg = len(descs)
+        if self.gcm_two_pass is None:
+            self.c.gcm_two_pass = 0 if _has_long_gcm(descs, gcm) else 1
+        else:
+            self.c.gcm_two_pass = int(bool(self.gcm_two_pass))
         if keys is not None:
             k = torch.from_numpy(np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1).copy())
             self.d_keys[:k.numel()].copy_(k)

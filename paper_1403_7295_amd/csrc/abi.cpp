@@ -365,6 +365,15 @@ int gcm_crypt(int decrypt, const void *in, void *out, size_t nbytes, const void 
 // Cipher-kernel workgroups for a batch launch on this device.
 int batch_grid(const DeviceState &d) { return std::min(d.cus, kBatchMaxWaves / kBatchWavesPerGroup); }
 
+// The lists a batch may use (launch_batch's mask): without GCM fields the
+// three cipher lists; with them also the GCM kernels, and the one-pass GCM
+// list unless the caller asked for two passes throughout.
+unsigned batch_lists(const aes_batch &b, const BatchKArgs &a) {
+    if (!a.gcm)
+        return 7u;
+    return b.gcm_two_pass ? 15u : 31u;
+}
+
 int batch_args(const aes_batch *b, BatchKArgs *a) {
     if (!b)
         return fail(AES_E_NULL, "batch must not be NULL");
@@ -610,7 +619,7 @@ int aes_batch_run(const aes_batch *b, void *stream) {
         return st;
     // without a device-side count the host knows how many messages there are
     // the GHASH and tag kernels only if the batch can hold GCM messages
-    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 31u : 7u,
+    hipError_t e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), batch_lists(*b, a),
                                 a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -643,7 +652,7 @@ int aes_batch_run_noalloc(const aes_batch *b, void *stream) {
     st = batch_args(&w, &a);
     if (st != AES_OK)
         return st;
-    e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), a.gcm ? 31u : 7u,
+    e = launch_batch(a, batch_grid(*d), static_cast<hipStream_t>(stream), batch_lists(*b, a),
                      a.d_nmsg ? a.max_msgs : a.nmsg);
     if (e != hipSuccess)
         return fail(AES_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -686,7 +695,7 @@ int aes_batch_graph_create(const aes_batch *b, void **graph) {
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         // the count may change per replay
-        hipError_t le = launch_batch(a, batch_grid(*d), s, a.gcm ? 31u : 7u, a.max_msgs);
+        hipError_t le = launch_batch(a, batch_grid(*d), s, batch_lists(*b, a), a.max_msgs);
         e = hipStreamEndCapture(s, &g);
         if (le != hipSuccess)
             e = le;

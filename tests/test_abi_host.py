@@ -317,3 +317,16 @@ def test_binding_checks_xts_and_gcm_extents(A, monkeypatch):
                           stream=0)
     with pytest.raises(ValueError, match="device"):
         A.aes_gcm_decrypt(x, y, 512, aad, 32, rk, nr, bytes(12), tag, 16, ok, ws, stream=0)
+
+
+def test_batch_binding_picks_gcm_passes(A):
+    # the binding asks for the one-pass GCM kernels only when a GCM message
+    # has at least 2 x 65,536 GHASH blocks (additional data, ciphertext and
+    # the length block)
+    d = A.make_descs([16 * 131071, 16 * 131070, 5], mode="gcm", keybits=128)
+    assert A._has_long_gcm(d, None)
+    assert not A._has_long_gcm(d[1:], None)
+    g = np.zeros(2, A.GCM_DESC_DTYPE)
+    g["aad_bytes"] = [16, 0]
+    assert A._has_long_gcm(d[1:], g)
+    assert not A._has_long_gcm(A.make_descs([16 << 20], mode="ctr"), None)

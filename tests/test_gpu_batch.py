@@ -593,7 +593,16 @@ def test_gcm_batch_fused_messages(A, O):
     b.launch_graph()
     torch.cuda.synchronize()
     check_gcm_batch(A, O, b, descs, keys, x, yd.cpu().numpy(), want, n, b.gcm_results(len(descs)))
+    assert b.c.gcm_two_pass == 0
     b.close()
+    # the same batch with two passes for every message
+    y2 = torch.zeros_like(xd)
+    b2 = A.Batch(descs, keys, xd, y2, gcm=g, gcm_two_pass=True)
+    assert b2.c.gcm_two_pass == 1
+    b2.run()
+    assert b2.query() == (len(descs), 0)
+    check_gcm_batch(A, O, b2, descs, keys, x, y2.cpu().numpy(), want, n, b2.gcm_results(len(descs)))
+    b2.close()
 
 
 def test_gcm_batch_message_beyond_the_stored_powers(A):
