@@ -394,8 +394,8 @@ typedef struct {
  *                    launches; the results are the same either way).
  * The sequence is: on-device Key Expansion for every message (FIPS-197
  * section 5.2; the decryption schedule of section 5.3.5 where needed) and a
- * plan that puts the messages in three lists (encryption tables, inverse
- * tables, serial CBC encryption) and splits each parallel list into equal
+ * plan that puts the messages in lists (encryption tables, inverse tables,
+ * serial CBC encryption, and for GCM the hash lists) and splits each parallel list into equal
  * shares of work, one per wave, by cost (blocks times rounds): the paper's
  * chunking into one piece per processor, Section IV-A, across messages; then
  * persistent kernels, one workgroup per compute unit, in which every wave
