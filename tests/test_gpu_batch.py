@@ -746,3 +746,97 @@ def test_gcm_batch_many_short_messages_one_per_lane(A, O):
     bd.close()
     del xd, yd, y2, xd2, zd
     torch.cuda.empty_cache()
+
+
+def _gcm_random_batch(A, seed, lens, aad_lens, base=0):
+    """GCM descriptors over random data: messages back to back from `base`,
+    then their additional data, then one 16-byte tag slot each (random bytes:
+    the expected tags of the decryptions); encryptions and decryptions, key
+    sizes and IVs at random."""
+    rng = np.random.default_rng(seed)
+    n = len(lens)
+    pad = lambda v: (int(v) + 15) // 16 * 16  # noqa: E731
+    off, msg_off, aad_off, tag_off = base, [], [], []
+    for L in lens:
+        msg_off.append(off)
+        off += pad(L)
+    for L in aad_lens:
+        aad_off.append(off)
+        off += pad(L)
+    for _ in range(n):
+        tag_off.append(off)
+        off += 16
+    keybits = rng.choice([128, 192, 256], n)
+    keys = np.zeros((n, 32), np.uint8)
+    keys[:, :] = rng.integers(0, 256, (n, 32), dtype=np.uint8)
+    ctr0 = np.zeros((n, 16), np.uint8)
+    ctr0[:, :12] = rng.integers(0, 256, (n, 12), dtype=np.uint8)
+    descs = A.make_descs(list(lens), in_off=msg_off, keybits=keybits, mode="gcm",
+                         decrypt=list(rng.integers(0, 2, n)), ctr0=ctr0)
+    g = np.zeros(n, A.GCM_DESC_DTYPE)
+    g["aad_off"], g["aad_bytes"], g["tag_off"], g["tag_bytes"] = aad_off, aad_lens, tag_off, 16
+    return descs, keys, g, off
+
+
+def _gcm_results(yd, descs, g):
+    """Outputs, encryption tags and verdicts of a finished GCM batch."""
+    y = yd.cpu().numpy()
+    outs = [y[int(d["out_off"]):int(d["out_off"]) + int(d["nbytes"])] for d in descs]
+    tags = [y[int(t):int(t) + 16] if not d["decrypt"] else None for d, t in zip(descs, g["tag_off"])]
+    return outs, tags
+
+
+def test_gcm_batch_one_pass_in_place_and_replayed(A):
+    """The one-pass kernels in place (output over input) and from a graph
+    replayed with rewritten descriptors equal the two-pass kernels on the
+    same messages: outputs, tags and verdicts (the two-pass path is checked
+    against the oracle elsewhere)."""
+    K = 65536
+    lens = [16 * (2 * K) + 5, 16 * (3 * K) - 1, 16 * (2 * K + 300), 0, 17, 4096, 100000, 16 * (5 * K) + 8]
+    aad_lens = [0, 33, 16 * 700, 5, 0, 64, 1000, 0]
+    descs, keys, g, total = _gcm_random_batch(A, 91, lens, aad_lens)
+    x = torch.randint(0, 256, (total + 64,), dtype=torch.uint8, device="cuda")
+
+    def run(descs, keys, g, two_pass, inplace, graph=None):
+        src = x.clone()
+        dst = src if inplace else torch.zeros_like(x)
+        b = A.Batch(descs, keys, src, dst, gcm=g, gcm_two_pass=two_pass)
+        b.run()
+        torch.cuda.synchronize()
+        assert b.query() == (len(descs), 0)
+        res = _gcm_results(dst, descs, g), b.gcm_results(len(descs))["ok"].copy()
+        b.close()
+        return res
+
+    (want_o, want_t), want_ok = run(descs, keys, g, True, False)
+    (got_o, got_t), got_ok = run(descs, keys, g, False, True)
+    assert list(got_ok) == list(want_ok)
+    for m in range(len(descs)):
+        assert np.array_equal(got_o[m], want_o[m]), "message %d in place" % m
+        if want_t[m] is not None:
+            assert np.array_equal(got_t[m], want_t[m]), "message %d tag in place" % m
+    # a graph with room for 12 messages, replayed with rewritten descriptors
+    y = torch.zeros_like(x)
+    b = A.Batch(descs, keys, x, y, gcm=g, max_msgs=12, gcm_two_pass=False)
+    b.launch_graph()
+    torch.cuda.synchronize()
+    (o1, t1) = _gcm_results(y, descs, g)
+    for m in range(len(descs)):
+        assert np.array_equal(o1[m], want_o[m]), "message %d from the graph" % m
+        if want_t[m] is not None:
+            assert np.array_equal(t1[m], want_t[m]), "message %d tag from the graph" % m
+    lens2 = [16 * (4 * K) + 3, 50, 16 * (2 * K) - 16, 16 * (2 * K) + 1, 7000]
+    descs2, keys2, g2, total2 = _gcm_random_batch(A, 92, lens2, [0, 16, 48, 0, 3])
+    assert total2 <= total
+    (want2_o, want2_t), want2_ok = run(descs2, keys2, g2, True, False)
+    y.zero_()
+    b.set_descs(descs2, keys2, gcm=g2)
+    b.launch_graph()
+    torch.cuda.synchronize()
+    (o2, t2) = _gcm_results(y, descs2, g2)
+    assert list(b.gcm_results(len(descs2))["ok"]) == list(want2_ok)
+    for m in range(len(descs2)):
+        assert np.array_equal(o2[m], want2_o[m]), "rewritten message %d from the graph" % m
+        if want2_t[m] is not None:
+            assert np.array_equal(t2[m], want2_t[m]), "rewritten message %d tag from the graph" % m
+    b.close()
